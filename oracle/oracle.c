@@ -1,0 +1,693 @@
+/*
+ * FP64 reference ("oracle") of the ProbeSDF per-ray render step.
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  It shares no code
+ * with the HIP library.  Everything is double precision, scalar, and follows
+ * the paper's equations in the paper's order; OpenMP only spreads rays over
+ * cores.
+ *
+ * Paper sections cited: Sec. 3.1 "Decoupled Parametrization of Radiance"
+ * (Eqs. rendering/classic/shlick/newparametrization), Sec. 3.2 "Light Field
+ * Probes on a Coarse Grid" (Eqs. spherical_harmonics, sh_eval1, sh_eval2),
+ * Sec. 3.3 "SDF Estimation Approach" (Eq. neus and the loss Eqs. smooth_sdf ..
+ * photo_loss), Sec. 3.4 "Training", Sec. 4 "Implementation Details",
+ * Supplementary Sec. A "Scheduling" (Adam moments).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXN 1024   /* max samples per ray */
+#define MAXIN 64    /* max MLP inputs */
+#define MAXH 128    /* max MLP hidden width */
+#define MAXSH 16
+
+static double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+/* ---------------------------------------------------------------------------
+ * Ray / box interval.  The paper renders pixel-aligned rays (Sec. 3.3); the
+ * sampling interval is the ray's intersection with the grid's domain
+ * [-1,1]^3 (slab test), clipped to t >= 0.  Returns 1 iff t_f > t_n.
+ * ------------------------------------------------------------------------- */
+int orc_ray_box(const double o[3], const double d[3], double* tn, double* tf) {
+  double t0 = -INFINITY, t1 = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    double ta = (-1.0 - o[a]) / d[a];
+    double tb = (1.0 - o[a]) / d[a];
+    t0 = fmax(t0, fmin(ta, tb));
+    t1 = fmin(t1, fmax(ta, tb));
+  }
+  t0 = fmax(t0, 0.0);
+  *tn = t0;
+  *tf = t1;
+  return t1 > t0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Trilinear interpolation on an align-corners grid (Sec. 3.2: "the voxels
+ * tri-linearly interpolate the 8 nearest probes"; the same operator serves the
+ * SDF and spatial features).  Reading: per axis u = (x+1)/h,
+ * k0 = clamp(floor(u), 0, R-2), f = u - k0; weight of corner (dx,dy,dz) is the
+ * product over axes of (f if d=1 else 1-f).
+ * ------------------------------------------------------------------------- */
+static void cell_coord(int R, double x, int* k0, double* f) {
+  double h = 2.0 / (double)(R - 1);
+  double u = (x + 1.0) / h;
+  double fl = floor(u);
+  if (fl < 0.0) fl = 0.0;
+  if (fl > (double)(R - 2)) fl = (double)(R - 2);
+  *k0 = (int)fl;
+  *f = u - fl;
+}
+
+void orc_tri_corners(int R, const double x[3], int64_t idx[8], double w[8]) {
+  int k[3];
+  double f[3];
+  for (int a = 0; a < 3; ++a) cell_coord(R, x[a], &k[a], &f[a]);
+  for (int c = 0; c < 8; ++c) {
+    int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+    double wx = dx ? f[0] : 1.0 - f[0];
+    double wy = dy ? f[1] : 1.0 - f[1];
+    double wz = dz ? f[2] : 1.0 - f[2];
+    idx[c] = ((int64_t)(k[2] + dz) * R + (k[1] + dy)) * R + (k[0] + dx);
+    w[c] = wx * wy * wz;
+  }
+}
+
+void orc_trilinear(const double* grid, int R, int C, const double x[3], double* out) {
+  int64_t idx[8];
+  double w[8];
+  orc_tri_corners(R, x, idx, w);
+  for (int ch = 0; ch < C; ++ch) out[ch] = 0.0;
+  for (int c = 0; c < 8; ++c)
+    for (int ch = 0; ch < C; ++ch) out[ch] += w[c] * grid[idx[c] * C + ch];
+}
+
+/* ---------------------------------------------------------------------------
+ * SDF gradient for the normal n = grad s / |grad s| (Sec. 3.3, Eq.
+ * smmoth_normals defines n this way; the gradient operator is not given).
+ * Reading: central difference of the trilinear SDF with step h along each
+ * axis; both stencil points are clamped to the domain and the difference is
+ * divided by the actual distance between them.
+ * ------------------------------------------------------------------------- */
+void orc_sdf_gradient(const double* sdf, int R, const double x[3], double g[3]) {
+  double h = 2.0 / (double)(R - 1);
+  for (int a = 0; a < 3; ++a) {
+    double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+    xp[a] = clampd(x[a] + h, -1.0, 1.0);
+    xm[a] = clampd(x[a] - h, -1.0, 1.0);
+    double sp, sm;
+    orc_trilinear(sdf, R, 1, xp, &sp);
+    orc_trilinear(sdf, R, 1, xm, &sm);
+    g[a] = (sp - sm) / (xp[a] - xm[a]);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Real spherical-harmonic basis Y_j (Sec. 3.2, Eq. spherical_harmonics: l^2
+ * coefficients with one-indexed l).  Reading: orthonormal real SH on the unit
+ * sphere, no Condon-Shortley phase, ordered (0,0), (1,-1), (1,0), (1,1),
+ * (2,-2) .. (2,2), (3,-3) .. (3,3).  Constants are computed here from their
+ * closed forms.
+ * ------------------------------------------------------------------------- */
+int orc_sh_basis(int n_sh, const double v[3], double* Y) {
+  const double pi = acos(-1.0);
+  double x = v[0], y = v[1], z = v[2];
+  if (n_sh != 1 && n_sh != 4 && n_sh != 9 && n_sh != 16) return -1;
+  Y[0] = 0.5 * sqrt(1.0 / pi);
+  if (n_sh >= 4) {
+    double c1 = sqrt(3.0 / (4.0 * pi));
+    Y[1] = c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = c1 * x;
+  }
+  if (n_sh >= 9) {
+    double c2 = 0.5 * sqrt(15.0 / pi);
+    Y[4] = c2 * x * y;
+    Y[5] = c2 * y * z;
+    Y[6] = 0.25 * sqrt(5.0 / pi) * (3.0 * z * z - 1.0);
+    Y[7] = c2 * x * z;
+    Y[8] = 0.25 * sqrt(15.0 / pi) * (x * x - y * y);
+  }
+  if (n_sh >= 16) {
+    Y[9] = 0.25 * sqrt(35.0 / (2.0 * pi)) * y * (3.0 * x * x - y * y);
+    Y[10] = 0.5 * sqrt(105.0 / pi) * x * y * z;
+    Y[11] = 0.25 * sqrt(21.0 / (2.0 * pi)) * y * (5.0 * z * z - 1.0);
+    Y[12] = 0.25 * sqrt(7.0 / pi) * z * (5.0 * z * z - 3.0);
+    Y[13] = 0.25 * sqrt(21.0 / (2.0 * pi)) * x * (5.0 * z * z - 1.0);
+    Y[14] = 0.25 * sqrt(105.0 / pi) * z * (x * x - y * y);
+    Y[15] = 0.25 * sqrt(35.0 / (2.0 * pi)) * x * (x * x - 3.0 * y * y);
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * log Phi_tau(s) with Phi the logistic of Eq. neus: log(1/(1+e^{-x})) written
+ * as min(x,0) - log1p(e^{-|x|}), which is the same function without overflow.
+ * ------------------------------------------------------------------------- */
+double orc_logsigmoid(double x) { return fmin(x, 0.0) - log1p(exp(-fabs(x))); }
+
+static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* ---------------------------------------------------------------------------
+ * Colour MLP (Sec. 4: ReLU hidden layer(s), sigmoid output).  One hidden layer
+ * of `hidden` units: pre1 = W1 z + b1, hid = max(pre1, 0), out = W2 hid + b2,
+ * C = sigmoid(out).  Packed weights: W1[hidden][n_in] row-major, b1, W2[3][hidden], b2.
+ * ------------------------------------------------------------------------- */
+void orc_mlp_forward(const double* mlp, int n_in, int hidden, const double* z, double* pre1,
+                     double* hid, double out[3], double C[3]) {
+  const double* W1 = mlp;
+  const double* b1 = W1 + hidden * n_in;
+  const double* W2 = b1 + hidden;
+  const double* b2 = W2 + 3 * hidden;
+  for (int k = 0; k < hidden; ++k) {
+    double acc = b1[k];
+    for (int j = 0; j < n_in; ++j) acc += W1[k * n_in + j] * z[j];
+    pre1[k] = acc;
+    hid[k] = acc > 0.0 ? acc : 0.0;
+  }
+  for (int c = 0; c < 3; ++c) {
+    double acc = b2[c];
+    for (int k = 0; k < hidden; ++k) acc += W2[c * hidden + k] * hid[k];
+    out[c] = acc;
+    C[c] = sigmoid(acc);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * NeuS compositing weights (Sec. 3.3, Eq. neus):
+ *   alpha_i = max((Phi(s_i) - Phi(s_{i+1})) / Phi(s_i), 0),
+ *   T_i = prod_{j<i} (1 - alpha_j),  weight w_i = T_i alpha_i.
+ * Evaluated in the log domain: 1 - Phi(s_{i+1})/Phi(s_i) = -expm1(dl) with
+ * dl = log Phi(s_{i+1}) - log Phi(s_i), and log(1 - alpha_i) = min(dl, 0).
+ * Reading: alpha of the last sample is 0 (it has no successor), inactive
+ * samples (skip rule) have alpha 0.  Returns log T after the last sample.
+ * ------------------------------------------------------------------------- */
+double orc_composite(int N, const double* s, const int32_t* active, double tau, double* alpha,
+                     double* T, double* w) {
+  double logT = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double a = 0.0;
+    double dl = 0.0;
+    if (i + 1 < N && active[i]) {
+      dl = orc_logsigmoid(tau * s[i + 1]) - orc_logsigmoid(tau * s[i]);
+      a = dl < 0.0 ? -expm1(dl) : 0.0;
+    }
+    alpha[i] = a;
+    T[i] = exp(logT);
+    w[i] = T[i] * a;
+    if (a > 0.0) logT += dl;
+  }
+  return logT;
+}
+
+/* ---------------------------------------------------------------------------
+ * Colour of one sample (Sec. 3.1 Eq. newparametrization, Sec. 3.2 Eqs.
+ * sh_eval1/sh_eval2, Sec. 4):
+ *   F_s = trilinear spatial features at x,
+ *   bhat_j = sum_i w_i b_ij (trilinear over the 8 probes),  F_a = sum_j bhat_j Y_j(v),
+ *   c = n.v with n the normalised SDF gradient,
+ *   C = MLP([F_s, F_a, c, c^2, c^4]).
+ * Readings: SH is evaluated in the view direction v (pointing from the sample
+ * to the camera); the incidence inputs are (c, c^2, c^4).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double g[3], gn, n[3], c;
+  double z[MAXIN], pre1[MAXH], hid[MAXH], out[3], C[3];
+  double Y[MAXSH];
+} shade_state;
+
+static void shade_full(const orc_field* f, int32_t flags, const double x[3], const double v[3],
+                       shade_state* st) {
+  int nf = f->n_feat, na = f->n_ang, nsh = f->n_sh;
+  int n_in = nf + na + 3;
+  orc_sh_basis(nsh, v, st->Y);
+  /* normal and incidence cosine */
+  orc_sdf_gradient(f->sdf, f->R, x, st->g);
+  st->gn = sqrt(st->g[0] * st->g[0] + st->g[1] * st->g[1] + st->g[2] * st->g[2]);
+  double inv = 1.0 / fmax(st->gn, 1e-30);
+  for (int a = 0; a < 3; ++a) st->n[a] = st->g[a] * inv;
+  st->c = (flags & ORC_NV_ONE) ? 1.0 : st->n[0] * v[0] + st->n[1] * v[1] + st->n[2] * v[2];
+  /* spatial features */
+  if (flags & ORC_NO_FS) {
+    for (int k = 0; k < nf; ++k) st->z[k] = 0.0;
+  } else {
+    orc_trilinear(f->feat, f->R, nf, x, st->z);
+  }
+  /* angular features: interpolate the coefficients, then evaluate the basis */
+  if (flags & ORC_NO_FA) {
+    for (int a = 0; a < na; ++a) st->z[nf + a] = 0.0;
+  } else {
+    double bhat[MAXSH * 16];
+    orc_trilinear(f->probes, f->P, nsh * na, x, bhat);
+    for (int a = 0; a < na; ++a) {
+      double acc = 0.0;
+      for (int j = 0; j < nsh; ++j) acc += bhat[j * na + a] * st->Y[j];
+      st->z[nf + a] = acc;
+    }
+  }
+  double c = st->c;
+  st->z[nf + na + 0] = c;
+  st->z[nf + na + 1] = c * c;
+  st->z[nf + na + 2] = c * c * c * c;
+  orc_mlp_forward(f->mlp, n_in, f->hidden, st->z, st->pre1, st->hid, st->out, st->C);
+}
+
+void orc_shade(const orc_field* f, int32_t flags, const double x[3], const double v[3],
+               double C[3], double* z_out) {
+  shade_state st;
+  shade_full(f, flags, x, v, &st);
+  for (int c = 0; c < 3; ++c) C[c] = st.C[c];
+  if (z_out)
+    for (int j = 0; j < f->n_feat + f->n_ang + 3; ++j) z_out[j] = st.z[j];
+}
+
+/* ---------------------------------------------------------------------------
+ * Samples along one ray.  Reading (the paper gives no sampler): N cell-centred
+ * samples t_i = t_n + (i + 1/2) dt, dt = (t_f - t_n)/N, positions clamped to
+ * the domain; s_i is the trilinear SDF.  Skip rule: sample i is active iff
+ * |s_i| <= skip_voxels * h (skip_voxels <= 0: always).  margin = distance of
+ * the closest |s_i| to the skip threshold (decisions near it may flip between
+ * precisions).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int hit;
+  double o[3], d[3], v[3], tn, tf, dt;
+  int N;
+  double t[MAXN], x[MAXN][3], s[MAXN], alpha[MAXN], T[MAXN], w[MAXN];
+  int32_t active[MAXN];
+  double logT_final, margin;
+} ray_state;
+
+static void march(const orc_field* f, const orc_render_opts* opt, const double* o_in,
+                  const double* d_in, ray_state* r) {
+  int N = opt->n_samples;
+  double h = 2.0 / (double)(f->R - 1);
+  double dn = sqrt(d_in[0] * d_in[0] + d_in[1] * d_in[1] + d_in[2] * d_in[2]);
+  for (int a = 0; a < 3; ++a) {
+    r->o[a] = o_in[a];
+    r->d[a] = d_in[a] / dn;
+    r->v[a] = -r->d[a];
+  }
+  r->N = N;
+  r->margin = INFINITY;
+  r->logT_final = 0.0;
+  r->hit = orc_ray_box(r->o, r->d, &r->tn, &r->tf);
+  if (!r->hit) return;
+  r->dt = (r->tf - r->tn) / N;
+  double thr = opt->skip_voxels * h;
+  for (int i = 0; i < N; ++i) {
+    r->t[i] = r->tn + (i + 0.5) * r->dt;
+    for (int a = 0; a < 3; ++a) r->x[i][a] = clampd(r->o[a] + r->t[i] * r->d[a], -1.0, 1.0);
+    orc_trilinear(f->sdf, f->R, 1, r->x[i], &r->s[i]);
+    if (opt->skip_voxels > 0.0) {
+      r->active[i] = fabs(r->s[i]) <= thr;
+      if (i + 1 < N) r->margin = fmin(r->margin, fabs(fabs(r->s[i]) - thr));
+    } else {
+      r->active[i] = 1;
+    }
+  }
+  r->logT_final = orc_composite(N, r->s, r->active, opt->tau, r->alpha, r->T, r->w);
+}
+
+/* ---------------------------------------------------------------------------
+ * Forward render (Sec. 3.3): c = sum_i T_i alpha_i C_i.  Also returned:
+ * aux = (c, log T_final), depth_wsum = (sum_i w_i (t_i + dt/2), sum_i w_i),
+ * margin (see march), n_shaded = samples with alpha > 0.  Misses give 0
+ * (no background term).
+ * ------------------------------------------------------------------------- */
+void orc_render_forward(const orc_field* f, const orc_render_opts* opt, int64_t B,
+                        const double* rays_o, const double* rays_d, double* rgb, double* aux,
+                        double* depth_wsum, double* margin, int32_t* n_shaded) {
+#pragma omp parallel
+  {
+  ray_state* r = (ray_state*)malloc(sizeof(ray_state));
+#pragma omp for schedule(dynamic, 16)
+  for (int64_t b = 0; b < B; ++b) {
+    march(f, opt, rays_o + 3 * b, rays_d + 3 * b, r);
+    double col[3] = {0, 0, 0}, wsum = 0.0, depth = 0.0;
+    int ns = 0;
+    if (r->hit) {
+      for (int i = 0; i < r->N; ++i) {
+        if (!(r->alpha[i] > 0.0)) continue;
+        double C[3];
+        orc_shade(f, opt->flags, r->x[i], r->v, C, NULL);
+        for (int c = 0; c < 3; ++c) col[c] += r->w[i] * C[c];
+        wsum += r->w[i];
+        depth += r->w[i] * (r->t[i] + 0.5 * r->dt);
+        ++ns;
+      }
+    }
+    for (int c = 0; c < 3; ++c) rgb[3 * b + c] = col[c];
+    if (aux) {
+      for (int c = 0; c < 3; ++c) aux[4 * b + c] = col[c];
+      aux[4 * b + 3] = r->logT_final;
+    }
+    if (depth_wsum) {
+      depth_wsum[2 * b + 0] = depth;
+      depth_wsum[2 * b + 1] = wsum;
+    }
+    if (margin) margin[b] = r->margin;
+    if (n_shaded) n_shaded[b] = ns;
+  }
+  free(r);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Analytic reverse mode of the forward render (Sec. 3.3: the SDF, features,
+ * probes and MLP are trained by backpropagating the colour loss through the
+ * rendering equation).  Gradients are ADDED to g_* (accumulation over batches,
+ * Supplementary Sec. A).  Steps:
+ *  d c / d C_i = w_i;
+ *  d c / d alpha_i = T_i (C_i - S_i) with the colour behind sample i
+ *      S_{N-1} = 0, S_{i-1} = alpha_i C_i + (1 - alpha_i) S_i;
+ *  alpha_i = -expm1(dl_i): d alpha_i/d s_i = (1-alpha_i) tau sigma(-tau s_i),
+ *      d alpha_i / d s_{i+1} = -(1-alpha_i) tau sigma(-tau s_{i+1}), zero when the
+ *      max(., 0) clamp is active or the sample is inactive;
+ *  then the MLP, the cosine (d c/d g = (v - c n)/|g|), the finite-difference
+ *  stencil, and the trilinear weights scatter into nodes.
+ * ------------------------------------------------------------------------- */
+static void add_atomic(double* p, double v) {
+#pragma omp atomic
+  *p += v;
+}
+
+static void scatter_tri(double* grid, int R, int C, const double x[3], const double* val) {
+  int64_t idx[8];
+  double w[8];
+  orc_tri_corners(R, x, idx, w);
+  for (int c = 0; c < 8; ++c)
+    for (int ch = 0; ch < C; ++ch)
+      if (val[ch] != 0.0) add_atomic(&grid[idx[c] * C + ch], w[c] * val[ch]);
+}
+
+static void shade_backward(const orc_field* f, int32_t flags, const double x[3],
+                           const double v[3], const shade_state* st, const double dC[3],
+                           double* g_sdf, double* g_feat, double* g_probes, double* g_mlp) {
+  int nf = f->n_feat, na = f->n_ang, nsh = f->n_sh, H = f->hidden;
+  int n_in = nf + na + 3;
+  const double* W1 = f->mlp;
+  const double* W2 = W1 + H * n_in + H;
+  double* gW1 = g_mlp;
+  double* gb1 = gW1 + H * n_in;
+  double* gW2 = gb1 + H;
+  double* gb2 = gW2 + 3 * H;
+  /* sigmoid output */
+  double dout[3];
+  for (int c = 0; c < 3; ++c) dout[c] = dC[c] * st->C[c] * (1.0 - st->C[c]);
+  double dhid[MAXH];
+  for (int k = 0; k < H; ++k) {
+    double acc = 0.0;
+    for (int c = 0; c < 3; ++c) acc += W2[c * H + k] * dout[c];
+    dhid[k] = acc;
+  }
+  for (int c = 0; c < 3; ++c) {
+    add_atomic(&gb2[c], dout[c]);
+    for (int k = 0; k < H; ++k) add_atomic(&gW2[c * H + k], dout[c] * st->hid[k]);
+  }
+  /* ReLU: derivative 1 iff pre-activation > 0 */
+  double dpre[MAXH];
+  for (int k = 0; k < H; ++k) dpre[k] = st->pre1[k] > 0.0 ? dhid[k] : 0.0;
+  double dz[MAXIN];
+  for (int j = 0; j < n_in; ++j) {
+    double acc = 0.0;
+    for (int k = 0; k < H; ++k) acc += W1[k * n_in + j] * dpre[k];
+    dz[j] = acc;
+  }
+  for (int k = 0; k < H; ++k) {
+    add_atomic(&gb1[k], dpre[k]);
+    for (int j = 0; j < n_in; ++j) add_atomic(&gW1[k * n_in + j], dpre[k] * st->z[j]);
+  }
+  /* spatial features */
+  if (!(flags & ORC_NO_FS)) scatter_tri(g_feat, f->R, nf, x, dz);
+  /* probes: d/d b_ij = w_i Y_j dF_a */
+  if (!(flags & ORC_NO_FA)) {
+    double gb[MAXSH * 16];
+    for (int j = 0; j < nsh; ++j)
+      for (int a = 0; a < na; ++a) gb[j * na + a] = st->Y[j] * dz[nf + a];
+    scatter_tri(g_probes, f->P, nsh * na, x, gb);
+  }
+  /* incidence cosine -> normal -> SDF gradient stencil */
+  if (!(flags & ORC_NV_ONE)) {
+    double c = st->c;
+    double dc = dz[nf + na] + 2.0 * c * dz[nf + na + 1] + 4.0 * c * c * c * dz[nf + na + 2];
+    double dg[3];
+    if (st->gn >= 1e-30) {
+      for (int a = 0; a < 3; ++a) dg[a] = dc * (v[a] - c * st->n[a]) / st->gn;
+    } else {
+      for (int a = 0; a < 3; ++a) dg[a] = dc * v[a] / 1e-30;
+    }
+    double h = 2.0 / (double)(f->R - 1);
+    for (int a = 0; a < 3; ++a) {
+      double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+      xp[a] = clampd(x[a] + h, -1.0, 1.0);
+      xm[a] = clampd(x[a] - h, -1.0, 1.0);
+      double coef = dg[a] / (xp[a] - xm[a]);
+      double mc = -coef;
+      scatter_tri(g_sdf, f->R, 1, xp, &coef);
+      scatter_tri(g_sdf, f->R, 1, xm, &mc);
+    }
+  }
+}
+
+static double sigm_neg(double tau, double s) { return 1.0 / (1.0 + exp(tau * s)); }
+
+void orc_render_backward(const orc_field* f, const orc_render_opts* opt, int64_t B,
+                         const double* rays_o, const double* rays_d, const double* dL_drgb,
+                         double* g_sdf, double* g_feat, double* g_probes, double* g_mlp) {
+#pragma omp parallel
+  {
+  ray_state* r = (ray_state*)malloc(sizeof(ray_state));
+  shade_state* st = (shade_state*)malloc(sizeof(shade_state));
+  double(*C)[3] = (double(*)[3])malloc(sizeof(double[MAXN][3]));
+  double* ds = (double*)malloc(sizeof(double[MAXN]));
+#pragma omp for schedule(dynamic, 16)
+  for (int64_t b = 0; b < B; ++b) {
+    const double* dL = dL_drgb + 3 * b;
+    if (dL[0] == 0.0 && dL[1] == 0.0 && dL[2] == 0.0) continue;
+    for (int i = 0; i < opt->n_samples; ++i) ds[i] = 0.0;
+    march(f, opt, rays_o + 3 * b, rays_d + 3 * b, r);
+    if (r->hit) {
+      int N = r->N;
+      for (int i = 0; i < N; ++i) {
+        if (!(r->alpha[i] > 0.0)) continue;
+        orc_shade(f, opt->flags, r->x[i], r->v, C[i], NULL);
+      }
+      /* reverse sweep: S_i = colour behind sample i (normalised by T_{i+1}) */
+      double S[3] = {0, 0, 0};
+      for (int i = N - 1; i >= 0; --i) {
+        /* here S = S_i */
+        if (r->alpha[i] > 0.0) {
+          double dalpha = 0.0;
+          for (int c = 0; c < 3; ++c) dalpha += dL[c] * r->T[i] * (C[i][c] - S[c]);
+          double one_m = 1.0 - r->alpha[i];
+          ds[i] += dalpha * one_m * opt->tau * sigm_neg(opt->tau, r->s[i]);
+          ds[i + 1] += -dalpha * one_m * opt->tau * sigm_neg(opt->tau, r->s[i + 1]);
+          /* colour path */
+          double dC[3];
+          for (int c = 0; c < 3; ++c) dC[c] = r->w[i] * dL[c];
+          shade_full(f, opt->flags, r->x[i], r->v, st);
+          shade_backward(f, opt->flags, r->x[i], r->v, st, dC, g_sdf, g_feat, g_probes, g_mlp);
+        }
+        for (int c = 0; c < 3; ++c) S[c] = r->alpha[i] * C[i][c] + (1.0 - r->alpha[i]) * S[c];
+      }
+      for (int i = 0; i < N; ++i)
+        if (ds[i] != 0.0) scatter_tri(g_sdf, f->R, 1, r->x[i], &ds[i]);
+    }
+  }
+  free(ds);
+  free(C);
+  free(st);
+  free(r);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Photometric loss.  The paper uses a relatively weighted L2 (Eq. photo_loss);
+ * the reading here is the L1 form L = mean over B x 3 of |c - c_gt|, with
+ * dL/dc = sign(c - c_gt)/(3B) and sign(0) = 0.
+ * ------------------------------------------------------------------------- */
+double orc_l1_loss(int64_t B, const double* rgb, const double* target, double* dL_drgb) {
+  double acc = 0.0;
+  double inv = 1.0 / (3.0 * (double)B);
+  for (int64_t i = 0; i < 3 * B; ++i) {
+    double d = rgb[i] - target[i];
+    acc += fabs(d);
+    dL_drgb[i] = (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) * inv;
+  }
+  return acc * inv;
+}
+
+/* ---------------------------------------------------------------------------
+ * Regularisers (Sec. 3.3, Eqs. eikonal_reg, smooth_features, smooth_probes),
+ * mean-normalised:
+ *   L_Eik   = lambda_eik / M * sum over interior SDF nodes (|grad s| - 1)^2, grad s by
+ *             central differences (s[n+e_a] - s[n-e_a]) / 2h, M = (R-2)^3;
+ *   L_feat  = lambda / (3 R^2 (R-1) n_feat) * sum over axis-adjacent node pairs and
+ *             channels of squared differences (each unordered pair once);
+ *   L_probe = the same on the probe grid over its n_sh*n_ang coefficients.
+ * Gradients are ADDED to g_*; losses[0..2] receive the three values.  The
+ * derivative of |g| at g = 0 is taken as 0.
+ * ------------------------------------------------------------------------- */
+static double tv_grid(int R, int C, const double* F, double lam, double* gF) {
+  double npairs = 3.0 * (double)R * R * (R - 1);
+  double scale = lam / (npairs * C);
+  double acc = 0.0;
+  for (int64_t k = 0; k < R; ++k)
+    for (int64_t j = 0; j < R; ++j)
+      for (int64_t i = 0; i < R; ++i) {
+        int64_t n = (k * R + j) * R + i;
+        int64_t nb[3] = {i + 1 < R ? n + 1 : -1, j + 1 < R ? n + R : -1,
+                         k + 1 < R ? n + (int64_t)R * R : -1};
+        for (int a = 0; a < 3; ++a) {
+          if (nb[a] < 0) continue;
+          for (int c = 0; c < C; ++c) {
+            double d = F[nb[a] * C + c] - F[n * C + c];
+            acc += d * d;
+            gF[nb[a] * C + c] += 2.0 * scale * d;
+            gF[n * C + c] -= 2.0 * scale * d;
+          }
+        }
+      }
+  return scale * acc;
+}
+
+void orc_regularizers(int R, int P, int n_feat, int n_pc, const double* sdf, const double* feat,
+                      const double* probes, double lambda_eik, double lambda_tv_feat,
+                      double lambda_tv_probe, double* g_sdf, double* g_feat, double* g_probes,
+                      double losses[3]) {
+  double h = 2.0 / (double)(R - 1);
+  double M = (double)(R - 2) * (R - 2) * (R - 2);
+  double acc = 0.0;
+  int64_t st[3] = {1, R, (int64_t)R * R};
+  for (int64_t k = 1; k < R - 1; ++k)
+    for (int64_t j = 1; j < R - 1; ++j)
+      for (int64_t i = 1; i < R - 1; ++i) {
+        int64_t n = (k * R + j) * R + i;
+        double g[3];
+        for (int a = 0; a < 3; ++a) g[a] = (sdf[n + st[a]] - sdf[n - st[a]]) / (2.0 * h);
+        double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        acc += (gn - 1.0) * (gn - 1.0);
+        if (gn > 0.0) {
+          double coef = lambda_eik / M * 2.0 * (gn - 1.0) / gn;
+          for (int a = 0; a < 3; ++a) {
+            g_sdf[n + st[a]] += coef * g[a] / (2.0 * h);
+            g_sdf[n - st[a]] -= coef * g[a] / (2.0 * h);
+          }
+        }
+      }
+  losses[0] = lambda_eik / M * acc;
+  losses[1] = tv_grid(R, n_feat, feat, lambda_tv_feat, g_feat);
+  losses[2] = tv_grid(P, n_pc, probes, lambda_tv_probe, g_probes);
+}
+
+/* ---------------------------------------------------------------------------
+ * Adam (Kingma & Ba 2015, Algorithm 1, bias-corrected), the optimiser named in
+ * Sec. 3.4 with the moments of Supplementary Sec. A.  step is 1-based.
+ * ------------------------------------------------------------------------- */
+void orc_adam(int64_t n, double* p, const double* g, double* m, double* v, int64_t step,
+              double lr, double beta1, double beta2, double eps) {
+  double bc1 = 1.0 - pow(beta1, (double)step);
+  double bc2 = 1.0 - pow(beta2, (double)step);
+  for (int64_t i = 0; i < n; ++i) {
+    m[i] = beta1 * m[i] + (1.0 - beta1) * g[i];
+    v[i] = beta2 * v[i] + (1.0 - beta2) * g[i] * g[i];
+    double mh = m[i] / bc1;
+    double vh = v[i] / bc2;
+    p[i] -= lr * mh / (sqrt(vh) + eps);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * One optimiser step over all trained parameters (Sec. 3.4: raw SDF, spatial
+ * features, probe coefficients, MLP weights): total gradient = render
+ * gradient + regulariser gradient, then Adam per group with its own learning
+ * rate.  m and v are concatenated in the order sdf | feat | probes | mlp.
+ * ------------------------------------------------------------------------- */
+void orc_grid_step(int R, int P, int n_feat, int n_pc, int n_mlp, double* sdf, double* feat,
+                   double* probes, double* mlp, const double* g_sdf, const double* g_feat,
+                   const double* g_probes, const double* g_mlp, double* m, double* v,
+                   int64_t step, const orc_step_opts* opt, double losses[3]) {
+  int64_t ns = (int64_t)R * R * R, nf = ns * n_feat, np = (int64_t)P * P * P * n_pc;
+  double* G = (double*)calloc((size_t)(ns + nf + np), sizeof(double));
+  memcpy(G, g_sdf, (size_t)ns * sizeof(double));
+  memcpy(G + ns, g_feat, (size_t)nf * sizeof(double));
+  memcpy(G + ns + nf, g_probes, (size_t)np * sizeof(double));
+  orc_regularizers(R, P, n_feat, n_pc, sdf, feat, probes, opt->lambda_eik, opt->lambda_tv_feat,
+                   opt->lambda_tv_probe, G, G + ns, G + ns + nf, losses);
+  orc_adam(ns, sdf, G, m, v, step, opt->lr_sdf, opt->beta1, opt->beta2, opt->eps);
+  orc_adam(nf, feat, G + ns, m + ns, v + ns, step, opt->lr_feat, opt->beta1, opt->beta2,
+           opt->eps);
+  orc_adam(np, probes, G + ns + nf, m + ns + nf, v + ns + nf, step, opt->lr_probe, opt->beta1,
+           opt->beta2, opt->eps);
+  orc_adam(n_mlp, mlp, g_mlp, m + ns + nf + np, v + ns + nf + np, step, opt->lr_mlp,
+           opt->beta1, opt->beta2, opt->eps);
+  free(G);
+}
+
+/* ---------------------------------------------------------------------------
+ * Sphere-traced inference render.  The paper's real-time path shades voxels
+ * and volume-renders them (Supplementary "Performance Analysis"); the reading
+ * used here marches t <- t + s(x) from the box entry until s < eps (hit) or
+ * t > t_f (miss), at most max_steps evaluations, then shades the hit point
+ * once with the same colour model (v = -d).  Pixel rays come from pinhole
+ * cameras: cams[v] = c2w (3x4 row-major), fx, fy, cx, cy; the camera-space
+ * direction of pixel (px, py) is ((px+.5-cx)/fx, (py+.5-cy)/fy, 1).
+ * pixel_ids index views x H x W (v*H*W + py*W + px).  margin = closest
+ * approach of a decision to its threshold (|s - eps|, |t - t_f|).
+ * ------------------------------------------------------------------------- */
+void orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max_steps,
+                      int32_t V, const double* cams, int32_t W, int32_t H,
+                      const int64_t* pixel_ids, int64_t n_pix, double* out, double* t_hit,
+                      int32_t* steps, double* margin) {
+  (void)V;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t q = 0; q < n_pix; ++q) {
+    int64_t id = pixel_ids[q];
+    int64_t vi = id / ((int64_t)W * H);
+    int64_t rem = id % ((int64_t)W * H);
+    int py = (int)(rem / W), px = (int)(rem % W);
+    const double* cam = cams + 16 * vi;
+    double dc[3] = {(px + 0.5 - cam[14]) / cam[12], (py + 0.5 - cam[15]) / cam[13], 1.0};
+    double o[3], d[3];
+    for (int r = 0; r < 3; ++r) {
+      d[r] = cam[4 * r + 0] * dc[0] + cam[4 * r + 1] * dc[1] + cam[4 * r + 2] * dc[2];
+      o[r] = cam[4 * r + 3];
+    }
+    double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int r = 0; r < 3; ++r) d[r] /= dn;
+    double tn, tf, mg = INFINITY, th = -1.0;
+    int hit = 0, k = 0;
+    double x[3];
+    if (orc_ray_box(o, d, &tn, &tf)) {
+      double t = tn;
+      for (k = 0; k < max_steps; ++k) {
+        for (int a = 0; a < 3; ++a) x[a] = clampd(o[a] + t * d[a], -1.0, 1.0);
+        double s;
+        orc_trilinear(f->sdf, f->R, 1, x, &s);
+        mg = fmin(mg, fabs(s - eps));
+        if (s < eps) {
+          hit = 1;
+          break;
+        }
+        t += s;
+        mg = fmin(mg, fabs(t - tf));
+        if (t > tf) break;
+      }
+      if (hit) th = t;
+    }
+    double C[3] = {0, 0, 0};
+    if (hit) {
+      double v[3] = {-d[0], -d[1], -d[2]};
+      orc_shade(f, flags, x, v, C, NULL);
+    }
+    for (int c = 0; c < 3; ++c) out[3 * q + c] = C[c];
+    if (t_hit) t_hit[q] = th;
+    if (steps) steps[q] = k;
+    if (margin) margin[q] = mg;
+  }
+}
