@@ -469,7 +469,10 @@ void orc_render_backward(const orc_field* f, const orc_render_opts* opt, int64_t
   for (int64_t b = 0; b < B; ++b) {
     const double* dL = dL_drgb + 3 * b;
     if (dL[0] == 0.0 && dL[1] == 0.0 && dL[2] == 0.0) continue;
-    for (int i = 0; i < opt->n_samples; ++i) ds[i] = 0.0;
+    for (int i = 0; i < opt->n_samples; ++i) {
+      ds[i] = 0.0;
+      C[i][0] = C[i][1] = C[i][2] = 0.0;
+    }
     march(f, opt, rays_o + 3 * b, rays_d + 3 * b, r);
     if (r->hit) {
       int N = r->N;
@@ -493,7 +496,9 @@ void orc_render_backward(const orc_field* f, const orc_render_opts* opt, int64_t
           shade_full(f, opt->flags, r->x[i], r->v, st);
           shade_backward(f, opt->flags, r->x[i], r->v, st, dC, g_sdf, g_feat, g_probes, g_mlp);
         }
-        for (int c = 0; c < 3; ++c) S[c] = r->alpha[i] * C[i][c] + (1.0 - r->alpha[i]) * S[c];
+        /* alpha_i = 0 leaves S unchanged (S_{i-1} = S_i) */
+        if (r->alpha[i] > 0.0)
+          for (int c = 0; c < 3; ++c) S[c] = r->alpha[i] * C[i][c] + (1.0 - r->alpha[i]) * S[c];
       }
       for (int i = 0; i < N; ++i)
         if (ds[i] != 0.0) scatter_tri(g_sdf, f->R, 1, r->x[i], &ds[i]);
