@@ -1,0 +1,291 @@
+"""Benchmark of the ProbeSDF render step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = one training iteration of the render path on the train256 workload
+(256^3 SDF + 3 features, 64^3 probes x 9 SH x 4, MLP 10-16-3; 2^18 rays from 8
+cameras at 256x128, 128 samples, skip |s| > 4 voxels; L1 loss against a torus
+target): render_forward -> l1_loss -> render_backward -> grid_step (eikonal +
+smoothness + Adam over all 76.5 M parameters).  Inputs are resident in HBM
+before timing starts.  value = rays per second of that whole step.
+
+The JSON line also carries the per-kernel times, the roofline of the dominant
+kernel (HIP events on the stream the kernels run on), the same step with FP16
+storage and the MLP on FP16 MFMA, the sphere-traced 1080p inference rate, and
+the FP64 oracle timed on the host cores over a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class KernelTimer:
+    """Events around each launch on torch's current stream (the launch stream)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pending = []
+        self.enabled = False
+
+    def run(self, name, fn):
+        if not self.enabled:
+            fn()
+            return
+        t = self.torch
+        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        self.pending.append((name, a, b))
+
+    def summary(self):
+        out = {}
+        for name, a, b in self.pending:
+            out.setdefault(name, []).append(a.elapsed_time(b))
+        return {k: sum(v) / len(v) for k, v in out.items()}
+
+
+def make_state(torch, ps, wl, w, feat_half=False, mlp_dtype=0, seed=0):
+    import numpy as np
+    f = wl.random_field(seed, w.R, w.P, n_sh=w.n_sh)
+    ft = wl.random_field(seed + 1, w.R, w.P, n_sh=w.n_sh, shape="torus")
+    o, d = wl.workload_rays(w)
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    master = dict(sdf=cu(f.sdf), feat=cu(f.feat), probes=cu(f.probes), mlp=cu(f.mlp))
+    spare = {k: torch.empty_like(v) for k, v in master.items() if k != "mlp"}
+    half = {}
+    if feat_half:
+        half = dict(feat=master["feat"].half(), probes=master["probes"].half())
+    st = dict(master=master, spare=spare, half=half, mlp_dtype=mlp_dtype,
+              o=cu(o), d=cu(d), B=o.shape[0],
+              grads={k: torch.zeros_like(v) for k, v in master.items()},
+              m={k: torch.zeros_like(v) for k, v in master.items()},
+              v={k: torch.zeros_like(v) for k, v in master.items()})
+    B = o.shape[0]
+    st["rgb"] = torch.empty((B, 3), device="cuda")
+    st["aux"] = torch.empty((B, 4), device="cuda")
+    st["dL"] = torch.empty((B, 3), device="cuda")
+    st["loss"] = torch.empty(1, device="cuda")
+    # target image: the torus field rendered by the same forward kernel
+    tfield = ps.Field(cu(ft.sdf), cu(ft.feat), cu(ft.probes), cu(ft.mlp))
+    st["target"] = torch.empty((B, 3), device="cuda")
+    ps.render_forward(tfield, ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels), st["o"], st["d"],
+                      st["target"])
+    torch.cuda.synchronize()
+    del tfield
+    return st, f, (o, d)
+
+
+def train_step(ps, w, st, step, timer):
+    p = st["master"]
+    if st["half"]:
+        fld = ps.Field(p["sdf"], st["half"]["feat"], st["half"]["probes"], p["mlp"], st["mlp_dtype"])
+    else:
+        fld = ps.Field(p["sdf"], p["feat"], p["probes"], p["mlp"], st["mlp_dtype"])
+    opts = ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels)
+    timer.run("render_forward", lambda: ps.render_forward(fld, opts, st["o"], st["d"], st["rgb"],
+                                                           st["aux"]))
+    timer.run("l1_loss", lambda: ps.l1_loss(st["rgb"], st["target"], st["dL"], st["loss"]))
+    timer.run("render_backward", lambda: ps.render_backward(fld, opts, st["o"], st["d"], st["aux"],
+                                                             st["dL"], st["grads"]))
+    out = dict(st["spare"], mlp=p["mlp"])
+    timer.run("grid_step", lambda: ps.grid_step(p, out, st["grads"], st["m"], st["v"], step,
+                                                ps.StepOpts(), half_out=st["half"] or None))
+    # ping-pong the grids (the step is out of place)
+    st["spare"] = {k: p[k] for k in ("sdf", "feat", "probes")}
+    st["master"] = dict(sdf=out["sdf"], feat=out["feat"], probes=out["probes"], mlp=p["mlp"])
+
+
+def time_training(torch, ps, w, st, steps, warmup, label):
+    timer = KernelTimer(torch)
+    for i in range(warmup):
+        train_step(ps, w, st, i + 1, timer)
+    torch.cuda.synchronize()
+    log(f"{label}: warmup done ({warmup} steps)")
+    timer.enabled = True
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for i in range(steps):
+        train_step(ps, w, st, warmup + i + 1, timer)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    kern = timer.summary()
+    log(f"{label}: {ms:.3f} ms/step, kernels " + ", ".join(f"{k} {v:.3f}" for k, v in kern.items()))
+    return ms, kern
+
+
+def time_inference(torch, ps, wl, steps, warmup):
+    """Sphere-traced inference, FP16 grids 512^3 / 128^3, 16 views at 1920x1080."""
+    import numpy as np
+    w = wl.WORKLOADS["trace512"]
+    g = torch.Generator(device="cuda").manual_seed(0)
+    R, P = w.R, w.P
+    a = torch.linspace(-1.0, 1.0, R, device="cuda", dtype=torch.float64)
+    z, y, x = torch.meshgrid(a, a, a, indexing="ij")
+    sdf = (torch.sqrt(x * x + y * y + z * z) - 0.5).half()
+    del x, y, z
+    feat = (torch.randn((R, R, R, 3), generator=g, device="cuda") * 0.1).half()
+    probes = (torch.randn((P, P, P, w.n_sh, 4), generator=g, device="cuda") * 0.1).half()
+    mlp = torch.from_numpy(wl.xavier_uniform_mlp(np.random.default_rng(0))).cuda()
+    fld = ps.Field(sdf, feat, probes, mlp, 0)
+    cams = torch.from_numpy(np.stack([c.as_array() for c in wl.fibonacci_cameras(w.views, w.W, w.H)])).cuda()
+    out = torch.empty((w.views, w.H, w.W, 3), device="cuda")
+    for _ in range(warmup):
+        ps.sphere_trace(fld, cams, w.W, w.H, out)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        ps.sphere_trace(fld, cams, w.W, w.H, out)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    rays = w.views * w.W * w.H
+    log(f"inference: {ms:.3f} ms per launch of {w.views} views")
+    return dict(workload="trace512", ms_per_frame=ms / w.views, rays_per_s=rays / (ms * 1e-3),
+                views=w.views, W=w.W, H=w.H, grids="fp16 512^3 / 128^3", mlp="f32")
+
+
+def cpu_baseline(wl, w, field, rays, n_rays=16384):
+    """FP64 oracle on the host cores: forward + L1 + backward on a ray sample,
+    plus one full oracle grid step, scaled to a step over the whole batch."""
+    import numpy as np
+    import oracle
+    o, d = rays
+    idx = np.linspace(0, o.shape[0] - 1, n_rays).astype(np.int64)
+    of = oracle.field_from(field)
+    t0 = time.time()
+    ref = oracle.render_forward(of, o[idx], d[idx], w.n_samples, tau=w.tau,
+                                skip_voxels=w.skip_voxels)
+    _, dL = oracle.l1_loss(ref["rgb"], np.full_like(ref["rgb"], 0.5))
+    oracle.render_backward(of, o[idx], d[idx], dL, w.n_samples, tau=w.tau,
+                           skip_voxels=w.skip_voxels)
+    t_rays = time.time() - t0
+    params = dict(sdf=of.sdf, feat=of.feat, probes=of.probes, mlp=of.mlp)
+    grads = {k: np.zeros_like(v) for k, v in params.items()}
+    n = sum(v.size for v in params.values())
+    t0 = time.time()
+    oracle.grid_step(params, grads, np.zeros(n), np.zeros(n), 1, oracle.StepOpts())
+    t_step = time.time() - t0
+    B = o.shape[0]
+    t_full = t_rays * B / n_rays + t_step
+    shaded = float(ref["n_shaded"].mean())
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=B / t_full, unit="rays/s", cores=cores, kind="oracle",
+                sample=(f"fwd+L1+bwd on {n_rays} evenly spaced rays of the {B}-ray batch "
+                        f"({t_rays:.2f} s) scaled to the batch, plus one full grid step over "
+                        f"{n} parameters ({t_step:.2f} s, single thread)")), shaded
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="skip mixed precision and inference")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the render step is measured on "
+                                   "one MI355X; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2412_10084_amd as ps
+    import workloads as wl
+
+    ps.lib()
+    torch.cuda.set_device(0)
+    w = wl.WORKLOADS["train256"]
+    log(f"setting up {w.name}: R={w.R} P={w.P} B={w.rays} N={w.n_samples}")
+    st, field, rays = make_state(torch, ps, wl, w)
+    ms, kern = time_training(torch, ps, w, st, args.steps, args.warmup, "fp32")
+    B = st["B"]
+    value = B / (ms * 1e-3)
+    del st
+    torch.cuda.empty_cache()
+
+    result = {
+        "metric": "train rays/s (fwd+bwd) FP32 vs FP16-MFMA at 256^3/64^3; ms per 1080p frame",
+        "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "train256", "R": w.R, "P": w.P, "sh_coeffs": w.n_sh,
+                   "rays": B, "samples": w.n_samples, "skip_voxels": w.skip_voxels,
+                   "step": "render_forward + l1_loss + render_backward + grid_step"},
+        "kernels_ms": kern,
+        "fwd_bwd_rays_per_s": B / ((kern["render_forward"] + kern["render_backward"]) * 1e-3),
+    }
+
+    shaded = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cb, shaded = cpu_baseline(wl, w, field, rays)
+        result["cpu_baseline"] = cb
+        result["shaded_samples_per_ray"] = shaded
+        log(f"cpu baseline: {cb['value']:.4g} rays/s on {cb['cores']} threads")
+
+    # roofline of the dominant kernel: algorithmic bytes per launch / launch time
+    n_params = w.R ** 3 * 4 + w.P ** 3 * w.n_sh * 4 + 227
+    dom = max(kern, key=kern.get)
+    per_launch = None
+    if dom == "grid_step":
+        # read p, g, m, v; write p, m, v, g (zero): 8 x 4 B per parameter
+        per_launch = 32.0 * n_params
+    elif shaded is not None:
+        # per ray: SDF scan 32 B x N; per shaded sample 1376 B read (forward) and
+        # another 1376 B of gradient payload (backward); ray / aux / dL I/O
+        if dom == "render_backward":
+            per_launch = B * (32.0 * w.n_samples + shaded * 2 * 1376.0 + 52.0)
+        else:
+            per_launch = B * (32.0 * w.n_samples + shaded * 1376.0 + 64.0)
+    if per_launch is not None:
+        ach = per_launch / (kern[dom] * 1e-3) / 1e9
+        result["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                              "algorithmic_bytes_per_launch": per_launch}
+
+    if not args.no_extras:
+        log("mixed precision (fp16 storage, fp16 MFMA MLP) ...")
+        stm, _, _ = make_state(torch, ps, wl, w, feat_half=True, mlp_dtype=1)
+        msm, kernm = time_training(torch, ps, w, stm, args.steps, args.warmup, "mixed")
+        del stm
+        torch.cuda.empty_cache()
+        result["mixed"] = {"rays_per_s": B / (msm * 1e-3), "ms_per_step": msm, "kernels_ms": kernm,
+                           "dtype": "f16 storage, f16 MFMA MLP, f32 accumulate",
+                           "speedup_vs_fp32": ms / msm}
+        log("inference (sphere trace, 16 x 1080p) ...")
+        result["inference"] = time_inference(torch, ps, wl, max(2, args.steps // 4), 1)
+
+    if args.calib_copy:
+        x = torch.empty(1 << 28, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = 2 * x.numel() * 4
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * probesdf.h -- C ABI of the MI355X (gfx950) ProbeSDF render-step library.
+ *
+ * Method: Toussaint, Thomas, Franco, "ProbeSDF: Light Field Probes For Neural
+ * Surface Reconstruction", CVPR 2025 (arXiv 2412.10084).  The library computes
+ * the fused per-ray render step of that method on an explicit SDF voxel grid:
+ *   - a dense SDF grid s and spatial features F_s (Sec. 3.1), sampled by
+ *     trilinear interpolation;
+ *   - a lower-resolution grid of light-field probes, each holding l^2
+ *     spherical-harmonic coefficient vectors b_j (Sec. 3.2, Eqs.
+ *     spherical_harmonics, sh_eval1, sh_eval2), interpolated and evaluated in the
+ *     view direction;
+ *   - incidence inputs from n.v with n the normalised SDF gradient
+ *     (Sec. 3.1, Eq. newparametrization);
+ *   - a tiny MLP that decodes colour (Sec. 4);
+ *   - NeuS SDF-to-opacity compositing along the ray (Sec. 3.3, Eq. neus).
+ *
+ * Common conventions
+ *   Grids are align-corners over the cube [-1,1]^3: R nodes per axis, node
+ *   (i,j,k) at (-1 + i h, -1 + j h, -1 + k h), h = 2/(R-1); stored x fastest,
+ *   flat index (k*R + j)*R + i.  Trilinear interpolation takes, per axis,
+ *   u = (x+1)/h, cell k0 = clamp(floor(u), 0, R-2), weight f = u - k0; sample
+ *   positions are clamped to the cube.
+ *     sdf     [R][R][R]                      FP32 or FP16
+ *     feat    [R][R][R][n_feat]              FP32 or FP16   (F_s)
+ *     probes  [P][P][P][sh_coeffs][n_ang]    FP32 or FP16   (b_ij)
+ *     mlp     W1[hidden][n_in] row-major, b1[hidden], W2[3][hidden], b2[3],
+ *             FP32, n_in = n_feat + n_ang + 3; MLP input z = [F_s, F_a, c, c^2, c^4]
+ *             with c = n.v (v = -ray direction), hidden ReLU, sigmoid output.
+ *   Rays: origins and directions [B][3] FP32 (directions need not be unit).
+ *   Per ray: interval [t_n, t_f] = ray / cube intersection (t >= 0); N samples
+ *   t_i = t_n + (i + 1/2)(t_f - t_n)/N; alpha_i from s_i and s_{i+1}; the last
+ *   sample has alpha 0.  A sample is active iff |s_i| <= skip_voxels * h
+ *   (skip_voxels <= 0: every sample).  Rays that miss the cube render 0.
+ *
+ * Memory and streams
+ *   Every pointer argument except the descriptor structs themselves is DEVICE
+ *   memory owned by the caller; descriptor structs are host memory read during
+ *   the call only.  Calls enqueue work on `stream` (a hipStream_t; NULL = the
+ *   null stream) and return without synchronising.  The library allocates no
+ *   device memory and keeps no per-call state.  Gradient buffers are
+ *   accumulated into (+=); the caller zeroes them, or psdf_grid_step does.
+ *
+ * Errors
+ *   Every entry point returns PSDF_OK (0) or a negative code; arguments are
+ *   validated on the host before anything is enqueued, and on error nothing
+ *   is enqueued.  psdf_last_error() returns a thread-local message for the last
+ *   failing call on this thread.  B = 0 (or an empty image) is a no-op that
+ *   returns PSDF_OK.  NaN/Inf inputs are propagated, never trapped; every
+ *   memory access is clamped into the grids, so no input can make a kernel
+ *   read or write out of bounds.  Faults inside a kernel surface at the
+ *   caller's next synchronisation of the stream.
+ */
+#ifndef PROBESDF_H
+#define PROBESDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSDF_ABI_VERSION 1
+
+#define PSDF_OK 0
+#define PSDF_EINVAL (-1)       /* null pointer, bad size or shape, aliasing */
+#define PSDF_EALIGN (-2)       /* a pointer is not aligned as documented */
+#define PSDF_EUNSUPPORTED (-3) /* a shape or dtype combination not compiled in */
+#define PSDF_EHIP (-4)         /* the HIP runtime reported an error */
+
+typedef enum { PSDF_F32 = 0, PSDF_F16 = 1, PSDF_BF16 = 2 } psdf_dtype;
+
+/* render flags (ablations of the colour model, Sec. 5 "Ablations") */
+#define PSDF_FLAG_NO_FS 1  /* F_s := 0 */
+#define PSDF_FLAG_NO_FA 2  /* F_a := 0 */
+#define PSDF_FLAG_NV_ONE 4 /* n.v := 1 (no incidence dependence) */
+
+/*
+ * The scene parameters (Sec. 3.4: raw SDF values, spatial features, probe
+ * coefficients and MLP weights).  Supported shapes: n_feat = 3, n_ang = 4,
+ * mlp_hidden = 16, sh_coeffs in {1, 4, 9, 16}, 2 <= R, P <= 1024 with
+ * R^3 * n_feat and P^3 * sh_coeffs * n_ang below 2^31.
+ * Dtypes: sdf_dtype F32 | F16, feat_dtype F32 | F16 (features and probes),
+ * mlp_dtype F32 | F16 | BF16 (the precision the MLP computes in; weights are
+ * always passed FP32 and rounded to nearest-even on use).
+ * Alignment: sdf, feat 4 bytes (2 for FP16); probes 16 bytes (8 for FP16);
+ * mlp 4 bytes.
+ */
+typedef struct psdf_field {
+  uint32_t struct_size; /* sizeof(psdf_field) */
+  int32_t R;
+  int32_t P;
+  int32_t n_feat;
+  int32_t sh_coeffs;
+  int32_t n_ang;
+  int32_t mlp_hidden;
+  int32_t sdf_dtype;
+  int32_t feat_dtype;
+  int32_t mlp_dtype;
+  const void* sdf;
+  const void* feat;
+  const void* probes;
+  const float* mlp;
+} psdf_field;
+
+typedef struct psdf_render_opts {
+  uint32_t struct_size; /* sizeof(psdf_render_opts) */
+  int32_t n_samples;    /* N, 2 <= N <= 4096 */
+  float tau;            /* NeuS sharpness of Phi_tau (Eq. neus), > 0 */
+  float skip_voxels;    /* skip rule threshold in voxels; <= 0 disables */
+  int32_t flags;        /* PSDF_FLAG_* */
+} psdf_render_opts;
+
+/* FP32 gradient accumulators, same layouts as the parameters.  A NULL member
+ * skips that group (its scatter is not performed). */
+typedef struct psdf_grads {
+  float* sdf;
+  float* feat;
+  float* probes;
+  float* mlp;
+} psdf_grads;
+
+/*
+ * psdf_render_forward -- colour of B rays (Sec. 3.3): c = sum_i T_i alpha_i C_i,
+ * T_i = prod_{j<i} (1 - alpha_j), alpha_i = max((Phi(s_i) - Phi(s_{i+1}))/Phi(s_i), 0),
+ * C_i = MLP(F_s(x_i), F_a(x_i, v), c, c^2, c^4).
+ *   rgb         [B][3] out
+ *   aux         [B][4] out, nullable: (rgb, log T_final); required by the backward
+ *   depth_wsum  [B][2] out, nullable: (sum_i w_i (t_i + dt/2), sum_i w_i), w_i = T_i alpha_i
+ */
+int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
+                        const float* rays_o, const float* rays_d, float* rgb, float* aux,
+                        float* depth_wsum, void* stream);
+
+/*
+ * psdf_render_backward -- reverse mode of psdf_render_forward for the same
+ * field, opts and rays: given dL/drgb [B][3] and the forward's aux [B][4], ADDS
+ * dL/d(sdf, feat, probes, mlp) into `grads` (Sec. 3.3: the SDF and appearance
+ * are optimised by back-propagating the colour loss through the rendering
+ * equation).  The march is recomputed; no per-sample state is stored.
+ * Gradients accumulate with FP32 atomics, so the summation order (and the last
+ * bits) varies from run to run.  Gradients are defined with respect to the
+ * values the forward reads (FP16 storage: the rounded values).
+ */
+int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
+                         const float* rays_o, const float* rays_d, const float* aux,
+                         const float* dL_drgb, const psdf_grads* grads, void* stream);
+
+/*
+ * psdf_l1_loss -- photometric loss.  The paper uses a relatively weighted L2
+ * (Eq. photo_loss); this is its L1 form L = mean over B x 3 of |rgb - target|.
+ *   dL_drgb [B][3] out = sign(rgb - target) / (3B), sign(0) = 0
+ *   loss    [1] out, nullable: L (overwritten)
+ */
+int psdf_l1_loss(int64_t B, const float* rgb, const float* target, float* dL_drgb, float* loss,
+                 void* stream);
+
+/*
+ * psdf_grid_step -- one optimiser step over all parameters (Sec. 3.4: Adam over
+ * the raw SDF, features, probes and MLP; moments beta1, beta2 as in the
+ * supplementary scheduling section).  For each group the total gradient is the
+ * accumulated render gradient plus the regulariser gradient:
+ *   eikonal (Eq. eikonal_reg):  lambda_eik / (R-2)^3 * sum over interior nodes of
+ *       (|grad s| - 1)^2, grad s by central differences (s[n+e]-s[n-e])/2h;
+ *   feature smoothness (Eq. smooth_features) and probe smoothness
+ *       (Eq. smooth_probes): lambda / (3 R^2 (R-1) C) * sum over axis-adjacent
+ *       node pairs and the C channels of squared differences;
+ * then bias-corrected Adam (Kingma & Ba, Algorithm 1) with `step` >= 1.
+ * Grids are updated OUT OF PLACE (the stencils read neighbours): *_in and
+ * *_out must not overlap; the MLP is updated in place.  Gradients are zeroed.
+ * Optional FP16 render copies (round to nearest even) of the new sdf, feat
+ * and probes are written when their pointers are non-NULL.  `losses` [3]
+ * (nullable, device) receives (L_eik, L_feat, L_probe) of the input
+ * parameters.
+ */
+typedef struct psdf_step_args {
+  uint32_t struct_size; /* sizeof(psdf_step_args) */
+  int32_t R, P, n_feat, n_pc; /* n_pc = sh_coeffs * n_ang */
+  int32_t n_mlp;
+  int64_t step;
+  float lr_sdf, lr_feat, lr_probe, lr_mlp;
+  float beta1, beta2, eps;
+  float lambda_eik, lambda_tv_feat, lambda_tv_probe;
+  const float* sdf_in;
+  float* sdf_out;
+  const float* feat_in;
+  float* feat_out;
+  const float* probes_in;
+  float* probes_out;
+  float* mlp;
+  float* g_sdf;
+  float* g_feat;
+  float* g_probes;
+  float* g_mlp;
+  float* m_sdf;
+  float* v_sdf;
+  float* m_feat;
+  float* v_feat;
+  float* m_probes;
+  float* v_probes;
+  float* m_mlp;
+  float* v_mlp;
+  void* sdf_half_out;    /* nullable FP16 copies */
+  void* feat_half_out;
+  void* probes_half_out;
+  float* losses;         /* nullable [3] */
+} psdf_step_args;
+
+int psdf_grid_step(const psdf_step_args* args, void* stream);
+
+/*
+ * psdf_render_sphere_trace -- inference render of V pinhole views.  The paper
+ * renders in real time by shading voxels and volume rendering them
+ * (supplementary "Performance Analysis"); this entry point instead sphere-traces
+ * the SDF (t <- t + s(x) from the cube entry until s < eps: hit, t > t_f: miss,
+ * at most max_steps evaluations) and shades the hit point once with the same
+ * colour model.  Misses render 0.
+ *   cams  [V][16] device FP32: c2w (3x4 row-major; columns = camera x (right),
+ *         y (down), z (forward) axes and the centre), fx, fy, cx, cy; pixel
+ *         (px, py) looks along c2w[:, :3] . ((px+.5-cx)/fx, (py+.5-cy)/fy, 1)
+ *   out   [V][H][W][3] FP32
+ */
+typedef struct psdf_trace_opts {
+  uint32_t struct_size; /* sizeof(psdf_trace_opts) */
+  float eps;            /* hit threshold, > 0 */
+  int32_t max_steps;    /* >= 1 */
+  int32_t flags;        /* PSDF_FLAG_* */
+} psdf_trace_opts;
+
+int psdf_render_sphere_trace(const psdf_field* field, const psdf_trace_opts* opts, int32_t V,
+                             const float* cams, int32_t W, int32_t H, float* out, void* stream);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* psdf_last_error(void);
+
+/* PSDF_ABI_VERSION of the loaded library. */
+int psdf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROBESDF_H */

@@ -1,0 +1,287 @@
+"""Python binding of libprobesdf.so, the MI355X (gfx950) ProbeSDF render step.
+
+Argument marshalling only: every step of the render path runs in the HIP
+kernels behind the C ABI declared in include/probesdf.h.  PyTorch supplies
+device memory (tensors) and the stream (torch's current HIP stream).  If the
+library is not built, every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field as dc_field
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libprobesdf.so")
+
+F32, F16, BF16 = 0, 1, 2
+FLAG_NO_FS, FLAG_NO_FA, FLAG_NV_ONE = 1, 2, 4
+OK, EINVAL, EALIGN, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
+ABI_VERSION = 1
+
+N_FEAT, N_ANG, HIDDEN, N_MLP = 3, 4, 16, 227
+
+EXPORTS = ("psdf_render_forward", "psdf_render_backward", "psdf_l1_loss", "psdf_grid_step",
+           "psdf_render_sphere_trace", "psdf_last_error", "psdf_abi_version")
+
+
+class PsdfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"probesdf error {code}: {msg}")
+        self.code = code
+
+
+class _Field(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("R", C.c_int32), ("P", C.c_int32),
+                ("n_feat", C.c_int32), ("sh_coeffs", C.c_int32), ("n_ang", C.c_int32),
+                ("mlp_hidden", C.c_int32), ("sdf_dtype", C.c_int32), ("feat_dtype", C.c_int32),
+                ("mlp_dtype", C.c_int32), ("sdf", C.c_void_p), ("feat", C.c_void_p),
+                ("probes", C.c_void_p), ("mlp", C.c_void_p)]
+
+
+class _RenderOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_samples", C.c_int32), ("tau", C.c_float),
+                ("skip_voxels", C.c_float), ("flags", C.c_int32)]
+
+
+class _Grads(C.Structure):
+    _fields_ = [("sdf", C.c_void_p), ("feat", C.c_void_p), ("probes", C.c_void_p),
+                ("mlp", C.c_void_p)]
+
+
+class _StepArgs(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("R", C.c_int32), ("P", C.c_int32),
+                ("n_feat", C.c_int32), ("n_pc", C.c_int32), ("n_mlp", C.c_int32),
+                ("step", C.c_int64),
+                ("lr_sdf", C.c_float), ("lr_feat", C.c_float), ("lr_probe", C.c_float),
+                ("lr_mlp", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("lambda_eik", C.c_float), ("lambda_tv_feat", C.c_float),
+                ("lambda_tv_probe", C.c_float)] + [
+        (n, C.c_void_p) for n in (
+            "sdf_in", "sdf_out", "feat_in", "feat_out", "probes_in", "probes_out", "mlp",
+            "g_sdf", "g_feat", "g_probes", "g_mlp", "m_sdf", "v_sdf", "m_feat", "v_feat",
+            "m_probes", "v_probes", "m_mlp", "v_mlp", "sdf_half_out", "feat_half_out",
+            "probes_half_out", "losses")]
+
+
+class _TraceOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("eps", C.c_float), ("max_steps", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libprobesdf.so (built in tree by paper_2412_10084_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2412_10084_amd.build`"
+                               " (the HIP library is required; there is no fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.psdf_render_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.psdf_render_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.psdf_l1_loss.argtypes = [i64, vp, vp, vp, vp, vp]
+        L.psdf_grid_step.argtypes = [vp, vp]
+        L.psdf_render_sphere_trace.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp]
+        L.psdf_last_error.restype = C.c_char_p
+        L.psdf_last_error.argtypes = []
+        L.psdf_abi_version.restype = C.c_int
+        for n in EXPORTS:
+            if n not in ("psdf_last_error", "psdf_abi_version"):
+                getattr(L, n).restype = C.c_int
+        if L.psdf_abi_version() != ABI_VERSION:
+            raise RuntimeError("libprobesdf ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().psdf_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise PsdfError(rc, last_error())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# descriptors
+# ---------------------------------------------------------------------------
+@dataclass
+class Field:
+    """Device tensors of one scene.  sdf (R,R,R) f32|f16; feat (R,R,R,3) f32|f16;
+    probes (P,P,P,sh,4) same dtype as feat; mlp (227,) f32."""
+    sdf: object
+    feat: object
+    probes: object
+    mlp: object
+    mlp_dtype: int = F32
+
+    @staticmethod
+    def _dt(t) -> int:
+        import torch
+        return {torch.float32: F32, torch.float16: F16}[t.dtype]
+
+    def cstruct(self) -> _Field:
+        R = self.sdf.shape[0]
+        P = self.probes.shape[0]
+        sh = self.probes.shape[3]
+        return _Field(C.sizeof(_Field), R, P, self.feat.shape[-1], sh, self.probes.shape[-1],
+                      HIDDEN, self._dt(self.sdf), self._dt(self.feat), self.mlp_dtype,
+                      _ptr(self.sdf), _ptr(self.feat), _ptr(self.probes), _ptr(self.mlp))
+
+
+@dataclass
+class RenderOpts:
+    n_samples: int = 64
+    tau: float = 64.0
+    skip_voxels: float = 0.0
+    flags: int = 0
+
+    def cstruct(self) -> _RenderOpts:
+        return _RenderOpts(C.sizeof(_RenderOpts), self.n_samples, self.tau, self.skip_voxels,
+                           self.flags)
+
+
+@dataclass
+class StepOpts:
+    lr_sdf: float = 0.01
+    lr_feat: float = 0.01
+    lr_probe: float = 0.001
+    lr_mlp: float = 0.001
+    beta1: float = 0.9
+    beta2: float = 0.995
+    eps: float = 1e-8
+    lambda_eik: float = 0.1
+    lambda_tv_feat: float = 0.05
+    lambda_tv_probe: float = 0.2
+
+
+# ---------------------------------------------------------------------------
+# entry points (raw calls: every tensor argument is a device tensor or a pointer)
+# ---------------------------------------------------------------------------
+def render_forward(field: Field, opts: RenderOpts, rays_o, rays_d, rgb, aux=None,
+                   depth_wsum=None, stream=None) -> None:
+    fs, op = field.cstruct(), opts.cstruct()
+    B = rays_o.shape[0] if not isinstance(rays_o, int) else None
+    _check(lib().psdf_render_forward(C.byref(fs), C.byref(op), B, _ptr(rays_o), _ptr(rays_d),
+                                     _ptr(rgb), _ptr(aux), _ptr(depth_wsum), _stream(stream)))
+
+
+def render_backward(field: Field, opts: RenderOpts, rays_o, rays_d, aux, dL_drgb, grads: dict,
+                    stream=None) -> None:
+    fs, op = field.cstruct(), opts.cstruct()
+    g = _Grads(_ptr(grads.get("sdf")), _ptr(grads.get("feat")), _ptr(grads.get("probes")),
+               _ptr(grads.get("mlp")))
+    _check(lib().psdf_render_backward(C.byref(fs), C.byref(op), rays_o.shape[0], _ptr(rays_o),
+                                      _ptr(rays_d), _ptr(aux), _ptr(dL_drgb), C.byref(g),
+                                      _stream(stream)))
+
+
+def l1_loss(rgb, target, dL_drgb, loss=None, stream=None) -> None:
+    _check(lib().psdf_l1_loss(rgb.shape[0], _ptr(rgb), _ptr(target), _ptr(dL_drgb), _ptr(loss),
+                              _stream(stream)))
+
+
+def grid_step(params_in: dict, params_out: dict, grads: dict, m: dict, v: dict, step: int,
+              opts: StepOpts, half_out: Optional[dict] = None, losses=None, stream=None) -> None:
+    """params_*: dict sdf, feat, probes (grids, out of place) and mlp (in place, taken from
+    params_in); grads/m/v: dicts with the same keys; half_out: optional FP16 copies."""
+    half_out = half_out or {}
+    R = params_in["sdf"].shape[0]
+    P = params_in["probes"].shape[0]
+    n_feat = params_in["feat"].shape[-1]
+    n_pc = params_in["probes"][0, 0, 0].numel()
+    a = _StepArgs(C.sizeof(_StepArgs), R, P, n_feat, n_pc, params_in["mlp"].numel(), step,
+                  opts.lr_sdf, opts.lr_feat, opts.lr_probe, opts.lr_mlp, opts.beta1, opts.beta2,
+                  opts.eps, opts.lambda_eik, opts.lambda_tv_feat, opts.lambda_tv_probe,
+                  _ptr(params_in["sdf"]), _ptr(params_out["sdf"]), _ptr(params_in["feat"]),
+                  _ptr(params_out["feat"]), _ptr(params_in["probes"]), _ptr(params_out["probes"]),
+                  _ptr(params_in["mlp"]), _ptr(grads["sdf"]), _ptr(grads["feat"]),
+                  _ptr(grads["probes"]), _ptr(grads["mlp"]), _ptr(m["sdf"]), _ptr(v["sdf"]),
+                  _ptr(m["feat"]), _ptr(v["feat"]), _ptr(m["probes"]), _ptr(v["probes"]),
+                  _ptr(m["mlp"]), _ptr(v["mlp"]), _ptr(half_out.get("sdf")),
+                  _ptr(half_out.get("feat")), _ptr(half_out.get("probes")), _ptr(losses))
+    _check(lib().psdf_grid_step(C.byref(a), _stream(stream)))
+
+
+def sphere_trace(field: Field, cams, W: int, H: int, out, eps: float = 1e-3,
+                 max_steps: int = 256, flags: int = 0, stream=None) -> None:
+    fs = field.cstruct()
+    to = _TraceOpts(C.sizeof(_TraceOpts), eps, max_steps, flags)
+    _check(lib().psdf_render_sphere_trace(C.byref(fs), C.byref(to), cams.shape[0], _ptr(cams), W, H,
+                                          _ptr(out), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+def render(field: Field, opts: RenderOpts, rays_o, rays_d):
+    """Differentiable render: returns rgb (B, 3); gradients flow to field.sdf,
+    field.feat, field.probes and field.mlp (FP32 tensors) through the HIP
+    backward kernel."""
+    return _RenderFn.apply(field.sdf, field.feat, field.probes, field.mlp, field.mlp_dtype, opts,
+                           rays_o, rays_d)
+
+
+def _make_autograd():
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sdf, feat, probes, mlp, mlp_dtype, opts, rays_o, rays_d):
+            B = rays_o.shape[0]
+            rgb = torch.empty((B, 3), device=rays_o.device, dtype=torch.float32)
+            aux = torch.empty((B, 4), device=rays_o.device, dtype=torch.float32)
+            fld = Field(sdf, feat, probes, mlp, mlp_dtype)
+            render_forward(fld, opts, rays_o, rays_d, rgb, aux)
+            ctx.save_for_backward(sdf, feat, probes, mlp, rays_o, rays_d, aux)
+            ctx.mlp_dtype, ctx.opts = mlp_dtype, opts
+            return rgb
+
+        @staticmethod
+        def backward(ctx, g_rgb):
+            sdf, feat, probes, mlp, rays_o, rays_d, aux = ctx.saved_tensors
+            fld = Field(sdf, feat, probes, mlp, ctx.mlp_dtype)
+            gs = torch.zeros(sdf.shape, device=sdf.device, dtype=torch.float32)
+            gf = torch.zeros(feat.shape, device=sdf.device, dtype=torch.float32)
+            gp = torch.zeros(probes.shape, device=sdf.device, dtype=torch.float32)
+            gm = torch.zeros(mlp.shape, device=sdf.device, dtype=torch.float32)
+            render_backward(fld, ctx.opts, rays_o, rays_d, aux, g_rgb.contiguous(),
+                            dict(sdf=gs, feat=gf, probes=gp, mlp=gm))
+            return (gs.to(sdf.dtype), gf.to(feat.dtype), gp.to(probes.dtype), gm, None, None,
+                    None, None)
+
+    return RenderFn
+
+
+class _Lazy:
+    def __init__(self):
+        self._fn = None
+
+    def apply(self, *a):
+        if self._fn is None:
+            self._fn = _make_autograd()
+        return self._fn.apply(*a)
+
+
+_RenderFn = _Lazy()

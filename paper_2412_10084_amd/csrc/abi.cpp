@@ -1,0 +1,306 @@
+// C ABI of the ProbeSDF render-step library: argument validation on the host,
+// then dispatch to the HIP kernels.  No error path enqueues work; no C++
+// exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/probesdf.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int ok() {
+  g_err[0] = '\0';
+  return PSDF_OK;
+}
+
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int dt_size(int dt) { return dt == PSDF_F32 ? 4 : 2; }
+
+int check_field(const psdf_field* f) {
+  if (!f) return fail(PSDF_EINVAL, "field is NULL");
+  if (f->struct_size != sizeof(psdf_field))
+    return fail(PSDF_EINVAL, "field.struct_size %u != %zu", f->struct_size, sizeof(psdf_field));
+  if (f->R < 2 || f->R > 1024 || f->P < 2 || f->P > 1024)
+    return fail(PSDF_EINVAL, "grid sizes R=%d P=%d outside [2, 1024]", f->R, f->P);
+  if (f->n_feat != 3 || f->n_ang != 4 || f->mlp_hidden != 16)
+    return fail(PSDF_EUNSUPPORTED, "compiled shape is n_feat=3 n_ang=4 hidden=16 (got %d %d %d)",
+                f->n_feat, f->n_ang, f->mlp_hidden);
+  if (f->sh_coeffs != 1 && f->sh_coeffs != 4 && f->sh_coeffs != 9 && f->sh_coeffs != 16)
+    return fail(PSDF_EUNSUPPORTED, "sh_coeffs=%d not in {1,4,9,16}", f->sh_coeffs);
+  const double r3 = (double)f->R * f->R * f->R, p3 = (double)f->P * f->P * f->P;
+  if (r3 * f->n_feat >= 2147483648.0 || p3 * f->sh_coeffs * f->n_ang >= 2147483648.0)
+    return fail(PSDF_EINVAL, "grid too large for 32-bit element indices");
+  if (f->sdf_dtype != PSDF_F32 && f->sdf_dtype != PSDF_F16)
+    return fail(PSDF_EUNSUPPORTED, "sdf_dtype %d", f->sdf_dtype);
+  if (f->feat_dtype != PSDF_F32 && f->feat_dtype != PSDF_F16)
+    return fail(PSDF_EUNSUPPORTED, "feat_dtype %d", f->feat_dtype);
+  if (f->mlp_dtype != PSDF_F32 && f->mlp_dtype != PSDF_F16 && f->mlp_dtype != PSDF_BF16)
+    return fail(PSDF_EUNSUPPORTED, "mlp_dtype %d", f->mlp_dtype);
+  if (!f->sdf || !f->feat || !f->probes || !f->mlp)
+    return fail(PSDF_EINVAL, "field has a NULL array");
+  if (!aligned(f->sdf, dt_size(f->sdf_dtype)) || !aligned(f->feat, dt_size(f->feat_dtype)) ||
+      !aligned(f->mlp, 4))
+    return fail(PSDF_EALIGN, "sdf/feat/mlp misaligned");
+  if (!aligned(f->probes, f->feat_dtype == PSDF_F32 ? 16 : 8))
+    return fail(PSDF_EALIGN, "probes must be %d-byte aligned", f->feat_dtype == PSDF_F32 ? 16 : 8);
+  return PSDF_OK;
+}
+
+int check_opts(const psdf_render_opts* o) {
+  if (!o) return fail(PSDF_EINVAL, "opts is NULL");
+  if (o->struct_size != sizeof(psdf_render_opts))
+    return fail(PSDF_EINVAL, "opts.struct_size %u != %zu", o->struct_size, sizeof(psdf_render_opts));
+  if (o->n_samples < 2 || o->n_samples > 4096)
+    return fail(PSDF_EINVAL, "n_samples=%d outside [2, 4096]", o->n_samples);
+  if (!(o->tau > 0.f) || !std::isfinite(o->tau)) return fail(PSDF_EINVAL, "tau must be finite > 0");
+  if (!std::isfinite(o->skip_voxels)) return fail(PSDF_EINVAL, "skip_voxels must be finite");
+  if (o->flags & ~7) return fail(PSDF_EINVAL, "unknown flags 0x%x", o->flags);
+  return PSDF_OK;
+}
+
+int check_f32(const void* p, const char* name) {
+  if (!p) return fail(PSDF_EINVAL, "%s is NULL", name);
+  if (!aligned(p, 4)) return fail(PSDF_EALIGN, "%s misaligned", name);
+  return PSDF_OK;
+}
+
+int hip_status(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(PSDF_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return ok();
+}
+
+psdf::RenderArgs render_args(const psdf_field* f, const psdf_render_opts* o, int64_t B,
+                             const float* ro, const float* rd) {
+  psdf::RenderArgs a{};
+  a.B = B;
+  a.rays_o = ro;
+  a.rays_d = rd;
+  a.R = f->R;
+  a.P = f->P;
+  a.h = (float)(2.0 / (f->R - 1));
+  a.inv_h = (float)((f->R - 1) / 2.0);
+  a.inv_hp = (float)((f->P - 1) / 2.0);
+  a.sdf = f->sdf;
+  a.feat = f->feat;
+  a.probes = f->probes;
+  a.mlp = f->mlp;
+  a.N = o->n_samples;
+  a.tau = o->tau;
+  a.skip_thr = o->skip_voxels > 0.f ? (float)(o->skip_voxels * (2.0 / (f->R - 1))) : 0.f;
+  a.flags = o->flags;
+  return a;
+}
+
+const int64_t kMaxRays = (int64_t)1 << 31;
+
+}  // namespace
+
+extern "C" {
+
+int psdf_abi_version(void) { return PSDF_ABI_VERSION; }
+
+const char* psdf_last_error(void) { return g_err; }
+
+int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
+                        const float* rays_o, const float* rays_d, float* rgb, float* aux,
+                        float* depth_wsum, void* stream) {
+  int rc;
+  if ((rc = check_field(field)) || (rc = check_opts(opts))) return rc;
+  if (B < 0 || B > kMaxRays) return fail(PSDF_EINVAL, "B=%lld out of range", (long long)B);
+  if (B == 0) return ok();
+  if ((rc = check_f32(rays_o, "rays_o")) || (rc = check_f32(rays_d, "rays_d")) ||
+      (rc = check_f32(rgb, "rgb")))
+    return rc;
+  if ((aux && !aligned(aux, 4)) || (depth_wsum && !aligned(depth_wsum, 4)))
+    return fail(PSDF_EALIGN, "aux/depth_wsum misaligned");
+  psdf::RenderArgs a = render_args(field, opts, B, rays_o, rays_d);
+  a.rgb = rgb;
+  a.aux = aux;
+  a.depth_wsum = depth_wsum;
+  return hip_status(psdf::launch_render_forward(a, field->sdf_dtype, field->feat_dtype,
+                                                field->mlp_dtype, field->sh_coeffs,
+                                                static_cast<hipStream_t>(stream)),
+                    "render_forward launch");
+}
+
+int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
+                         const float* rays_o, const float* rays_d, const float* aux,
+                         const float* dL_drgb, const psdf_grads* grads, void* stream) {
+  int rc;
+  if ((rc = check_field(field)) || (rc = check_opts(opts))) return rc;
+  if (B < 0 || B > kMaxRays) return fail(PSDF_EINVAL, "B=%lld out of range", (long long)B);
+  if (!grads) return fail(PSDF_EINVAL, "grads is NULL");
+  if (B == 0) return ok();
+  if ((rc = check_f32(rays_o, "rays_o")) || (rc = check_f32(rays_d, "rays_d")) ||
+      (rc = check_f32(aux, "aux")) || (rc = check_f32(dL_drgb, "dL_drgb")))
+    return rc;
+  const float* gp[4] = {grads->sdf, grads->feat, grads->probes, grads->mlp};
+  for (const float* p : gp)
+    if (p && !aligned(p, 4)) return fail(PSDF_EALIGN, "gradient buffer misaligned");
+  psdf::RenderArgs a = render_args(field, opts, B, rays_o, rays_d);
+  a.aux_in = aux;
+  a.dL = dL_drgb;
+  a.g_sdf = grads->sdf;
+  a.g_feat = grads->feat;
+  a.g_probes = grads->probes;
+  a.g_mlp = grads->mlp;
+  return hip_status(psdf::launch_render_backward(a, field->sdf_dtype, field->feat_dtype,
+                                                 field->mlp_dtype, field->sh_coeffs,
+                                                 static_cast<hipStream_t>(stream)),
+                    "render_backward launch");
+}
+
+int psdf_l1_loss(int64_t B, const float* rgb, const float* target, float* dL_drgb, float* loss,
+                 void* stream) {
+  int rc;
+  if (B < 0 || B > kMaxRays) return fail(PSDF_EINVAL, "B=%lld out of range", (long long)B);
+  if (B == 0) return ok();
+  if ((rc = check_f32(rgb, "rgb")) || (rc = check_f32(target, "target")) ||
+      (rc = check_f32(dL_drgb, "dL_drgb")))
+    return rc;
+  if (loss && !aligned(loss, 4)) return fail(PSDF_EALIGN, "loss misaligned");
+  return hip_status(psdf::launch_l1_loss(B, rgb, target, dL_drgb, loss,
+                                         static_cast<hipStream_t>(stream)),
+                    "l1_loss launch");
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
+int psdf_grid_step(const psdf_step_args* s, void* stream) {
+  if (!s) return fail(PSDF_EINVAL, "args is NULL");
+  if (s->struct_size != sizeof(psdf_step_args))
+    return fail(PSDF_EINVAL, "args.struct_size %u != %zu", s->struct_size, sizeof(psdf_step_args));
+  if (s->R < 2 || s->R > 1024 || s->P < 2 || s->P > 1024 || s->n_feat < 1 || s->n_pc < 1 ||
+      s->n_mlp < 0)
+    return fail(PSDF_EINVAL, "bad sizes R=%d P=%d n_feat=%d n_pc=%d n_mlp=%d", s->R, s->P,
+                s->n_feat, s->n_pc, s->n_mlp);
+  const double r3 = (double)s->R * s->R * s->R, p3 = (double)s->P * s->P * s->P;
+  if (r3 * s->n_feat >= 2147483648.0 || p3 * s->n_pc >= 2147483648.0)
+    return fail(PSDF_EINVAL, "grid too large for 32-bit element indices");
+  if (s->step < 1) return fail(PSDF_EINVAL, "step must be >= 1 (got %lld)", (long long)s->step);
+  if (!(s->beta1 >= 0.f && s->beta1 < 1.f && s->beta2 >= 0.f && s->beta2 < 1.f && s->eps >= 0.f))
+    return fail(PSDF_EINVAL, "Adam hyper-parameters out of range");
+  const void* req[] = {s->sdf_in, s->sdf_out, s->feat_in, s->feat_out, s->probes_in, s->probes_out,
+                       s->g_sdf, s->g_feat, s->g_probes, s->m_sdf, s->v_sdf, s->m_feat, s->v_feat,
+                       s->m_probes, s->v_probes};
+  for (const void* p : req) {
+    if (!p) return fail(PSDF_EINVAL, "a required step buffer is NULL");
+    if (!aligned(p, 4)) return fail(PSDF_EALIGN, "a step buffer is misaligned");
+  }
+  if (s->n_mlp > 0 && (!s->mlp || !s->g_mlp || !s->m_mlp || !s->v_mlp))
+    return fail(PSDF_EINVAL, "MLP step buffers are NULL");
+  const size_t bs = (size_t)r3 * 4, bf = (size_t)r3 * s->n_feat * 4, bp = (size_t)p3 * s->n_pc * 4;
+  if (overlap(s->sdf_in, bs, s->sdf_out, bs) || overlap(s->feat_in, bf, s->feat_out, bf) ||
+      overlap(s->probes_in, bp, s->probes_out, bp))
+    return fail(PSDF_EINVAL, "grid step is out of place: *_in and *_out must not overlap");
+  const void* halves[] = {s->sdf_half_out, s->feat_half_out, s->probes_half_out};
+  for (const void* p : halves)
+    if (p && !aligned(p, 2)) return fail(PSDF_EALIGN, "FP16 copy misaligned");
+  if (s->losses && !aligned(s->losses, 4)) return fail(PSDF_EALIGN, "losses misaligned");
+
+  psdf::StepArgs a{};
+  a.R = s->R;
+  a.P = s->P;
+  a.n_feat = s->n_feat;
+  a.n_pc = s->n_pc;
+  a.n_mlp = s->n_mlp;
+  a.h = (float)(2.0 / (s->R - 1));
+  a.lr_sdf = s->lr_sdf;
+  a.lr_feat = s->lr_feat;
+  a.lr_probe = s->lr_probe;
+  a.lr_mlp = s->lr_mlp;
+  a.beta1 = s->beta1;
+  a.beta2 = s->beta2;
+  a.eps = s->eps;
+  a.bc1 = (float)(1.0 - std::pow((double)s->beta1, (double)s->step));
+  a.bc2 = (float)(1.0 - std::pow((double)s->beta2, (double)s->step));
+  a.lambda_eik = s->lambda_eik;
+  a.lambda_tv_feat = s->lambda_tv_feat;
+  a.lambda_tv_probe = s->lambda_tv_probe;
+  a.sdf_in = s->sdf_in;
+  a.sdf_out = s->sdf_out;
+  a.feat_in = s->feat_in;
+  a.feat_out = s->feat_out;
+  a.probes_in = s->probes_in;
+  a.probes_out = s->probes_out;
+  a.mlp = s->mlp;
+  a.g_sdf = s->g_sdf;
+  a.g_feat = s->g_feat;
+  a.g_probes = s->g_probes;
+  a.g_mlp = s->g_mlp;
+  a.m_sdf = s->m_sdf;
+  a.v_sdf = s->v_sdf;
+  a.m_feat = s->m_feat;
+  a.v_feat = s->v_feat;
+  a.m_probes = s->m_probes;
+  a.v_probes = s->v_probes;
+  a.m_mlp = s->m_mlp;
+  a.v_mlp = s->v_mlp;
+  a.sdf_half = s->sdf_half_out;
+  a.feat_half = s->feat_half_out;
+  a.probes_half = s->probes_half_out;
+  a.losses = s->losses;
+  return hip_status(psdf::launch_grid_step(a, static_cast<hipStream_t>(stream)),
+                    "grid_step launch");
+}
+
+int psdf_render_sphere_trace(const psdf_field* field, const psdf_trace_opts* opts, int32_t V,
+                             const float* cams, int32_t W, int32_t H, float* out, void* stream) {
+  int rc;
+  if ((rc = check_field(field))) return rc;
+  if (!opts) return fail(PSDF_EINVAL, "opts is NULL");
+  if (opts->struct_size != sizeof(psdf_trace_opts))
+    return fail(PSDF_EINVAL, "trace opts.struct_size %u != %zu", opts->struct_size,
+                sizeof(psdf_trace_opts));
+  if (!(opts->eps > 0.f) || !std::isfinite(opts->eps) || opts->max_steps < 1 ||
+      opts->max_steps > 100000 || (opts->flags & ~7))
+    return fail(PSDF_EINVAL, "trace opts out of range");
+  if (V < 0 || W < 0 || H < 0 || V > 65535 || W > 65535 * 16 || H > 65535 * 16)
+    return fail(PSDF_EINVAL, "bad image size V=%d W=%d H=%d", V, W, H);
+  if ((int64_t)V * W * H == 0) return ok();
+  if ((rc = check_f32(cams, "cams")) || (rc = check_f32(out, "out"))) return rc;
+  psdf::TraceArgs a{};
+  a.R = field->R;
+  a.P = field->P;
+  a.h = (float)(2.0 / (field->R - 1));
+  a.inv_h = (float)((field->R - 1) / 2.0);
+  a.inv_hp = (float)((field->P - 1) / 2.0);
+  a.sdf = field->sdf;
+  a.feat = field->feat;
+  a.probes = field->probes;
+  a.mlp = field->mlp;
+  a.eps = opts->eps;
+  a.max_steps = opts->max_steps;
+  a.flags = opts->flags;
+  a.V = V;
+  a.W = W;
+  a.H = H;
+  a.cams = cams;
+  a.out = out;
+  return hip_status(psdf::launch_sphere_trace(a, field->sdf_dtype, field->feat_dtype,
+                                              field->mlp_dtype, field->sh_coeffs,
+                                              static_cast<hipStream_t>(stream)),
+                    "sphere_trace launch");
+}
+
+}  // extern "C"

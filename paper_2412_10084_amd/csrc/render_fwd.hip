@@ -1,0 +1,171 @@
+// Forward render of the ProbeSDF step (Sec. 3.3: c = sum_i T_i alpha_i C_i,
+// NeuS opacity of Eq. neus; colour model of Sec. 3.1-3.2 and Sec. 4).
+//
+// One ray per lane marches its N samples: trilinear SDF, skip rule, log-domain
+// opacity and transmittance.  Transmittance and weights depend on the SDF only,
+// so the march never waits for colour: each shaded sample (active, alpha > 0)
+// is pushed with its weight into a per-wave ring in LDS, and whenever 64 are
+// queued the whole wave shades them together, one sample per lane (FD normal,
+// spatial features, probe coefficients contracted with the SH basis of the
+// ray's view direction, MLP).  The weighted colours are then summed per ray by
+// the ray's own lane, in sample order.
+#include "dispatch.h"
+#include "shade.h"
+
+namespace psdf {
+
+struct FwdLds {
+  RayD ray[64];
+  int next[RING];   // sequence number of the same ray's next entry
+  int key[RING];    // (sample index << 6) | ray lane
+  float w[RING];    // compositing weight T_i alpha_i
+  float wc[RING][3];
+};
+
+template <typename ST, typename FT, int NSH, int M>
+__device__ __forceinline__ void fwd_batch(const RenderArgs& a, const Geo& G, FwdLds& L,
+                                          MlpLds<M>& ML, const MlpFrag<M>& frag, int lane, int head,
+                                          int n, float rgb[3], int& my_first, int& my_cnt) {
+  const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
+  const FT* __restrict__ feat = static_cast<const FT*>(a.feat);
+  const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
+  wave_sync();
+  const bool ve = lane < n;
+  const int slot = (head + lane) & (RING - 1);
+  float z[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) z[j] = 0.f;
+  float w = 0.f;
+  if (ve) {
+    const int key = L.key[slot];
+    const RayD r = L.ray[key & 63];
+    w = L.w[slot];
+    double x[3];
+    sample_pos(r, sample_t(r, key >> 6), x);
+    const float v[3] = {(float)-r.d[0], (float)-r.d[1], (float)-r.d[2]};
+    float Y[NSH];
+    sh_basis<NSH>(v[0], v[1], v[2], Y);
+    Normal nm;
+    shade_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, Y, z, nm);
+  }
+  float out[3];
+  if constexpr (M == MLP_F32) {
+    float pre[HID], hid[HID];
+    mlp_lane<M>(a.mlp, z, pre, hid, out);
+  } else {
+    mlp_wave<M>(frag, ML, lane, z, out);
+  }
+  if (ve) {
+    L.wc[slot][0] = w * sigmoidf(out[0]);
+    L.wc[slot][1] = w * sigmoidf(out[1]);
+    L.wc[slot][2] = w * sigmoidf(out[2]);
+  }
+  wave_sync();
+  // each ray's lane adds its own entries of this batch, in sample order
+  while (my_cnt > 0 && my_first < head + n) {
+    const int s = my_first & (RING - 1);
+    rgb[0] += L.wc[s][0];
+    rgb[1] += L.wc[s][1];
+    rgb[2] += L.wc[s][2];
+    if (--my_cnt > 0) my_first = L.next[s];
+  }
+  wave_sync();
+}
+
+template <typename ST, typename FT, int NSH, int M>
+__global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a) {
+  __shared__ FwdLds lds[WAVES];
+  __shared__ MlpLds<M> mlds[M == MLP_F32 ? 1 : WAVES];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  FwdLds& L = lds[wv];
+  MlpLds<M>& ML = mlds[M == MLP_F32 ? 0 : wv];
+  const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
+  const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
+  MlpFrag<M> frag;
+  if constexpr (M != MLP_F32) mlp_frag_load<M>(a.mlp, lane, frag);
+
+  const int64_t ray = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  const bool valid = ray < a.B;
+  float ro[3] = {0.f, 0.f, 0.f}, rd[3] = {0.f, 0.f, 1.f};
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ro[k] = a.rays_o[3 * ray + k];
+      rd[k] = a.rays_d[3 * ray + k];
+    }
+  }
+  RayD r;
+  const bool hit = ray_setup_d(ro[0], ro[1], ro[2], rd[0], rd[1], rd[2], a.N, r) && valid;
+  L.ray[lane] = r;
+
+  float rgb[3] = {0.f, 0.f, 0.f};
+  float wsum = 0.f, depth = 0.f, logT = 0.f;
+  int my_first = 0, my_last = 0, my_cnt = 0;
+  int head = 0, tail = 0;  // wave-uniform ring cursors (sequence numbers)
+  double x[3];
+  sample_pos(r, sample_t(r, 0), x);
+  float s_cur = hit ? tri1(sdf, a.R, cell_d(x, a.R, G.inv_h)) : 0.f;
+  float l_cur = log_sigmoid(a.tau * s_cur);
+  for (int i = 0;; ++i) {
+    const bool stepping = i < a.N - 1;  // wave-uniform
+    if (stepping) {
+      sample_pos(r, sample_t(r, i + 1), x);
+      const float s_nx = hit ? tri1(sdf, a.R, cell_d(x, a.R, G.inv_h)) : 0.f;
+      const float l_nx = log_sigmoid(a.tau * s_nx);
+      const bool active = hit && (a.skip_thr <= 0.f || fabsf(s_cur) <= a.skip_thr);
+      const float dl = l_nx - l_cur;
+      const bool shaded = active && dl < 0.f;
+      const uint64_t mask = __ballot(shaded);
+      if (shaded) {
+        const float w = expf(logT) * -expm1f(dl);
+        wsum += w;
+        depth = fmaf(w, (float)(sample_t(r, i) + 0.5 * r.dt), depth);
+        logT += dl;
+        const int seq = tail + lane_rank(mask);
+        const int slot = seq & (RING - 1);
+        L.key[slot] = (i << 6) | lane;
+        L.w[slot] = w;
+        if (my_cnt > 0) L.next[my_last & (RING - 1)] = seq;
+        else my_first = seq;
+        my_last = seq;
+        ++my_cnt;
+      }
+      tail += __popcll(mask);
+      s_cur = s_nx;
+      l_cur = l_nx;
+    }
+    const int pending = tail - head;
+    if (pending >= 64 || (!stepping && pending > 0)) {
+      const int n = min(64, pending);
+      fwd_batch<ST, FT, NSH, M>(a, G, L, ML, frag, lane, head, n, rgb, my_first, my_cnt);
+      head += n;
+    } else if (!stepping) {
+      break;
+    }
+  }
+  if (valid) {
+    a.rgb[3 * ray + 0] = rgb[0];
+    a.rgb[3 * ray + 1] = rgb[1];
+    a.rgb[3 * ray + 2] = rgb[2];
+    if (a.aux) {
+      a.aux[4 * ray + 0] = rgb[0];
+      a.aux[4 * ray + 1] = rgb[1];
+      a.aux[4 * ray + 2] = rgb[2];
+      a.aux[4 * ray + 3] = logT;
+    }
+    if (a.depth_wsum) {
+      a.depth_wsum[2 * ray + 0] = depth;
+      a.depth_wsum[2 * ray + 1] = wsum;
+    }
+  }
+}
+
+hipError_t launch_render_forward(const RenderArgs& a, int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
+                                 hipStream_t s) {
+  const dim3 grid((unsigned)((a.B + BLOCK - 1) / BLOCK));
+  PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,
+      hipLaunchKernelGGL((render_fwd_kernel<ST, FT, NSH, M>), grid, dim3(BLOCK), 0, s, a))));
+  return hipGetLastError();
+}
+
+}  // namespace psdf

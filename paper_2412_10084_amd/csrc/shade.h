@@ -1,0 +1,422 @@
+// Per-sample shading of the ProbeSDF render step and its reverse mode, the
+// per-ray setup, and the wave-level MLP / weight-gradient helpers shared by the
+// forward, backward and sphere-tracing kernels.
+//
+// Precision: ray parameters, sample positions and cell coordinates are FP64
+// (the opacity multiplies SDF errors by tau, so an FP32 position at t ~ 3
+// would dominate the error budget); interpolation weights are rounded to FP32
+// once; every value read from the grids and every downstream quantity is FP32.
+#pragma once
+
+#include "device.h"
+#include "kernels.h"
+
+namespace psdf {
+
+constexpr int BLOCK = 256;
+constexpr int WAVES = BLOCK / 64;
+
+// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
+// (and its L2) works on one contiguous range of rays.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned G) {
+  const unsigned x = b & 7u, j = b >> 3, q = G >> 3, r = G & 7u;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// ---------------------------------------------------------------------------
+// ray setup in FP64: unit direction, ray / cube interval, sample spacing
+// ---------------------------------------------------------------------------
+struct RayD {
+  double o[3], d[3];
+  double tn, dt;
+};
+
+__device__ __forceinline__ bool ray_setup_d(float ox, float oy, float oz, float dx, float dy,
+                                            float dz, int N, RayD& r) {
+  const double ddx = dx, ddy = dy, ddz = dz;
+  const double dn = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+  r.o[0] = ox;
+  r.o[1] = oy;
+  r.o[2] = oz;
+  r.d[0] = ddx / dn;
+  r.d[1] = ddy / dn;
+  r.d[2] = ddz / dn;
+  double t0 = -INFINITY, t1 = INFINITY;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double ta = (-1.0 - r.o[k]) / r.d[k];
+    const double tb = (1.0 - r.o[k]) / r.d[k];
+    t0 = fmax(t0, fmin(ta, tb));
+    t1 = fmin(t1, fmax(ta, tb));
+  }
+  t0 = fmax(t0, 0.0);
+  const bool hit = t1 > t0;
+  r.tn = t0;
+  r.dt = hit ? (t1 - t0) / (double)N : 0.0;
+  return hit;
+}
+
+__device__ __forceinline__ void sample_pos(const RayD& r, double ti, double x[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) x[k] = fmin(fmax(fma(ti, r.d[k], r.o[k]), -1.0), 1.0);
+}
+
+__device__ __forceinline__ double sample_t(const RayD& r, int i) {
+  return fma((double)i + 0.5, r.dt, r.tn);
+}
+
+// align-corners cell of an FP64 point; the weights are rounded to FP32 once
+__device__ __forceinline__ void axis_cell_d(double x, double inv_h, double kmax, int& k, float& f) {
+  const double u = (x + 1.0) * inv_h;
+  const double fl = fmin(fmax(floor(u), 0.0), kmax);
+  k = (int)fl;
+  f = (float)(u - fl);
+}
+
+__device__ __forceinline__ Cell cell_d(const double x[3], int R, double inv_h) {
+  Cell c;
+  int kx, ky, kz;
+  const double kmax = (double)(R - 2);
+  axis_cell_d(x[0], inv_h, kmax, kx, c.fx);
+  axis_cell_d(x[1], inv_h, kmax, ky, c.fy);
+  axis_cell_d(x[2], inv_h, kmax, kz, c.fz);
+  c.base = (kz * R + ky) * R + kx;
+  return c;
+}
+
+// grid geometry handed to the shading code
+struct Geo {
+  int R, P;
+  double h, inv_h, inv_hp;
+  int flags;
+};
+
+// ---------------------------------------------------------------------------
+// shading inputs z = [F_s, F_a, c, c^2, c^4] of one sample at FP64 position x
+// ---------------------------------------------------------------------------
+struct Normal {
+  float n[3];
+  float gn;
+  float c;
+};
+
+template <typename ST>
+__device__ __forceinline__ void sdf_normal(const ST* __restrict__ sdf, const Geo& G,
+                                           const double x[3], Normal& nm) {
+  float g[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+    xp[a] = fmin(x[a] + G.h, 1.0);
+    xm[a] = fmax(x[a] - G.h, -1.0);
+    const float sp = tri1(sdf, G.R, cell_d(xp, G.R, G.inv_h));
+    const float sm = tri1(sdf, G.R, cell_d(xm, G.R, G.inv_h));
+    g[a] = (sp - sm) / (float)(xp[a] - xm[a]);
+  }
+  nm.gn = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  const float inv = 1.0f / fmaxf(nm.gn, 1e-30f);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) nm.n[a] = g[a] * inv;
+}
+
+template <typename ST, typename FT, int NSH>
+__device__ __forceinline__ void shade_inputs(const ST* __restrict__ sdf, const FT* __restrict__ feat,
+                                             const FT* __restrict__ probes, const Geo& G,
+                                             const double x[3], const float v[3], const float* Y,
+                                             float z[NIN], Normal& nm) {
+  sdf_normal(sdf, G, x, nm);
+  nm.c = (G.flags & FLAG_NV_ONE) ? 1.0f : nm.n[0] * v[0] + nm.n[1] * v[1] + nm.n[2] * v[2];
+  z[0] = z[1] = z[2] = 0.0f;
+  if (!(G.flags & FLAG_NO_FS)) {
+    const Cell cs = cell_d(x, G.R, G.inv_h);
+    float w[8];
+    corner_w(cs, w);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int node = cs.base + corner_off(c, G.R);
+#pragma unroll
+      for (int ch = 0; ch < NF; ++ch) z[ch] = fmaf(w[c], ld1(feat, node * NF + ch), z[ch]);
+    }
+  }
+  z[3] = z[4] = z[5] = z[6] = 0.0f;
+  if (!(G.flags & FLAG_NO_FA)) {
+    const Cell cp = cell_d(x, G.P, G.inv_hp);
+    float w[8];
+    corner_w(cp, w);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int off = (cp.base + corner_off(c, G.P)) * (NSH * NA);
+      float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+#pragma unroll
+      for (int j = 0; j < NSH; ++j) {
+        const float4 b = ld4(probes, off + 4 * j);
+        q0 = fmaf(Y[j], b.x, q0);
+        q1 = fmaf(Y[j], b.y, q1);
+        q2 = fmaf(Y[j], b.z, q2);
+        q3 = fmaf(Y[j], b.w, q3);
+      }
+      z[3] = fmaf(w[c], q0, z[3]);
+      z[4] = fmaf(w[c], q1, z[4]);
+      z[5] = fmaf(w[c], q2, z[5]);
+      z[6] = fmaf(w[c], q3, z[6]);
+    }
+  }
+  const float c = nm.c, c2 = c * c;
+  z[7] = c;
+  z[8] = c2;
+  z[9] = c2 * c2;
+}
+
+__device__ __forceinline__ void scatter8(float* g, int R, const Cell& c, float val) {
+  float w[8];
+  corner_w(c, w);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) atomic_add_f32(g + c.base + corner_off(q, R), val * w[q]);
+}
+
+// Reverse mode of shade_inputs: dL/dz scattered into the grids with FP32 atomics.
+template <int NSH>
+__device__ __forceinline__ void shade_inputs_backward(const Geo& G, const double x[3],
+                                                      const float v[3], const float* Y,
+                                                      const Normal& nm, const float dz[NIN],
+                                                      float* g_sdf, float* g_feat, float* g_probes) {
+  if (!(G.flags & FLAG_NO_FS) && g_feat) {
+    const Cell cs = cell_d(x, G.R, G.inv_h);
+    float w[8];
+    corner_w(cs, w);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int node = cs.base + corner_off(c, G.R);
+#pragma unroll
+      for (int ch = 0; ch < NF; ++ch) atomic_add_f32(g_feat + node * NF + ch, w[c] * dz[ch]);
+    }
+  }
+  if (!(G.flags & FLAG_NO_FA) && g_probes) {
+    const Cell cp = cell_d(x, G.P, G.inv_hp);
+    float w[8];
+    corner_w(cp, w);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      float* gp = g_probes + (cp.base + corner_off(c, G.P)) * (NSH * NA);
+#pragma unroll
+      for (int j = 0; j < NSH; ++j) {
+        const float wy = w[c] * Y[j];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) atomic_add_f32(gp + 4 * j + k, wy * dz[3 + k]);
+      }
+    }
+  }
+  if (!(G.flags & FLAG_NV_ONE) && g_sdf) {
+    const float c = nm.c;
+    const float dc = dz[7] + 2.0f * c * dz[8] + 4.0f * c * c * c * dz[9];
+    float dg[3];
+    if (nm.gn >= 1e-30f) {
+      const float s = dc / nm.gn;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dg[a] = s * (v[a] - c * nm.n[a]);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dg[a] = dc * v[a] / 1e-30f;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+      xp[a] = fmin(x[a] + G.h, 1.0);
+      xm[a] = fmax(x[a] - G.h, -1.0);
+      const float coef = dg[a] / (float)(xp[a] - xm[a]);
+      scatter8(g_sdf, G.R, cell_d(xp, G.R, G.inv_h), coef);
+      scatter8(g_sdf, G.R, cell_d(xm, G.R, G.inv_h), -coef);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-aggregated probe-gradient scatter.  The probe grid is coarse, so the
+// shaded samples of one batch (neighbouring rays, consecutive samples) share
+// few probe cells.  Each distinct cell of the batch gets an LDS slot; for each
+// of the 8 corners the lanes add their n_sh x n_ang products w_c Y_j dF_a into
+// the slot with LDS atomics, and the slot's lane issues one global atomic per
+// coefficient, instead of one per sample.
+// ---------------------------------------------------------------------------
+template <int NSH>
+struct ProbeAcc {
+  float acc[64][NSH * NA + 1];  // +1: rows start on different banks
+  int key[64];                  // base node of the slot's cell
+};
+
+template <int NSH>
+__device__ __forceinline__ void probe_acc_clear(ProbeAcc<NSH>& A, int lane) {
+#pragma unroll
+  for (int q = 0; q < NSH * NA; ++q) A.acc[lane][q] = 0.f;
+}
+
+// Call with the whole wave.  Leaves the accumulator rows zero.
+template <int NSH>
+__device__ __forceinline__ void probe_scatter_wave(ProbeAcc<NSH>& A, int lane, bool ve,
+                                                   const Cell& cp, int P, const float* Y,
+                                                   const float* dFa, float* g_probes) {
+  const int mykey = ve ? cp.base : -1;
+  int slot = 0, U = 0;
+  uint64_t todo = __ballot(ve);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int k = __builtin_amdgcn_readlane(mykey, leader);
+    const bool m = ve && mykey == k;
+    if (m) slot = U;
+    if (lane == leader) A.key[U] = k;
+    todo &= ~__ballot(m);
+    ++U;
+  }
+  float w[8];
+  corner_w(cp, w);
+  wave_sync();
+#pragma unroll 1
+  for (int c = 0; c < 8; ++c) {
+    if (ve) {
+#pragma unroll
+      for (int j = 0; j < NSH; ++j) {
+        const float wy = w[c] * Y[j];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) atomicAdd(&A.acc[slot][NA * j + k], wy * dFa[k]);
+      }
+    }
+    wave_sync();
+    if (lane < U) {
+      float* gp = g_probes + (A.key[lane] + corner_off(c, P)) * (NSH * NA);
+#pragma unroll
+      for (int q = 0; q < NSH * NA; ++q) {
+        const float val = A.acc[lane][q];
+        A.acc[lane][q] = 0.f;
+        if (val != 0.f) atomic_add_f32(gp + q, val);
+      }
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wave-batched MLP on MFMA (reduced precision).  The 64 samples of a batch are
+// four 16-sample blocks; with samples on the MFMA's N dimension the first
+// layer's output fragment is exactly the second layer's B operand:
+//   H^T (16 hidden x 16 samples) = W1 (16 x 16 padded inputs) . Z^T
+//   O^T (16 padded out x 16)     = W2 (16 padded x 16 hidden) . relu(H^T + b1)
+// ---------------------------------------------------------------------------
+template <int M> struct MType;
+template <> struct MType<MLP_F16> {
+  typedef _Float16 t;
+  typedef h4 v;
+  static __device__ __forceinline__ f4 mma(h4 a, h4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct MType<MLP_BF16> {
+  typedef __bf16 t;
+  typedef b4 v;
+  static __device__ __forceinline__ f4 mma(b4 a, b4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+// F32 mode keeps the per-lane MLP; the fragment types are unused placeholders
+template <> struct MType<MLP_F32> : MType<MLP_F16> {};
+
+template <int M>
+struct MlpFrag {
+  typename MType<M>::v a1, a2;
+  float b1r[4], b2r[4];
+};
+
+template <int M>
+__device__ __forceinline__ void mlp_frag_load(const float* __restrict__ W, int lane, MlpFrag<M>& f) {
+  typedef typename MType<M>::t T;
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int k = 4 * g + r;
+    f.a1[r] = (T)(k < NIN ? W[i * NIN + k] : 0.0f);
+    f.b1r[r] = W[OFF_B1 + k];
+    f.a2[r] = (T)(i < 3 ? W[OFF_W2 + i * HID + k] : 0.0f);
+    f.b2r[r] = k < 3 ? W[OFF_B2 + k] : 0.0f;
+  }
+}
+
+template <int M>
+struct MlpLds {
+  typename MType<M>::t zs[64][16];
+  float cs[64][4];
+};
+
+template <int M>
+__device__ __forceinline__ void mlp_wave(const MlpFrag<M>& f, MlpLds<M>& L, int lane,
+                                         const float z[NIN], float out[3]) {
+  typedef typename MType<M>::t T;
+  typedef typename MType<M>::v V4;
+  const int i = lane & 15, g = lane >> 4;
+  const V4 z0 = {(T)z[0], (T)z[1], (T)z[2], (T)z[3]};
+  const V4 z1 = {(T)z[4], (T)z[5], (T)z[6], (T)z[7]};
+  const V4 z2 = {(T)z[8], (T)z[9], (T)0.0f, (T)0.0f};
+  const V4 z3 = {(T)0.0f, (T)0.0f, (T)0.0f, (T)0.0f};
+  *reinterpret_cast<V4*>(&L.zs[lane][0]) = z0;
+  *reinterpret_cast<V4*>(&L.zs[lane][4]) = z1;
+  *reinterpret_cast<V4*>(&L.zs[lane][8]) = z2;
+  *reinterpret_cast<V4*>(&L.zs[lane][12]) = z3;
+  wave_sync();
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const V4 bz = *reinterpret_cast<const V4*>(&L.zs[16 * b + i][4 * g]);
+    f4 d = {0.f, 0.f, 0.f, 0.f};
+    d = MType<M>::mma(f.a1, bz, d);
+    V4 hb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hb[r] = (T)fmaxf(d[r] + f.b1r[r], 0.0f);
+    f4 o = {0.f, 0.f, 0.f, 0.f};
+    o = MType<M>::mma(f.a2, hb, o);
+    if (g == 0) {
+      L.cs[16 * b + i][0] = o[0] + f.b2r[0];
+      L.cs[16 * b + i][1] = o[1] + f.b2r[1];
+      L.cs[16 * b + i][2] = o[2] + f.b2r[2];
+    }
+  }
+  wave_sync();
+  out[0] = L.cs[lane][0];
+  out[1] = L.cs[lane][1];
+  out[2] = L.cs[lane][2];
+  wave_sync();
+}
+
+// MLP weight gradients: sum over the batch of (row vector) x (column vector) as
+// 16x16 tiles on FP32 MFMA with K = samples.
+struct DwLds {
+  float st[64][36];  // row stride 36 floats: 16-byte rows, spread banks
+};
+
+__device__ __forceinline__ void dw_accumulate(DwLds& L, int lane, const float a[16],
+                                              const float b[16], f4& acc) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    *reinterpret_cast<float4*>(&L.st[lane][4 * q]) =
+        make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+    *reinterpret_cast<float4*>(&L.st[lane][16 + 4 * q]) =
+        make_float4(b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]);
+  }
+  wave_sync();
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(L.st[4 * t + g][i], L.st[4 * t + g][16 + i], acc, 0,
+                                                 0, 0);
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// per-wave queue of shaded samples (a ring of 128 entries).  A lane pushes at
+// most one entry per march step; entries of one ray are linked in order.
+// ---------------------------------------------------------------------------
+constexpr int RING = 128;
+
+// number of lower lanes set in a wave mask
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+}  // namespace psdf

@@ -1,0 +1,140 @@
+"""The C-ABI library loads, exports every symbol include/probesdf.h declares,
+and rejects bad arguments on the host before any HIP call (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2412_10084_amd as ps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000  # a well-aligned non-NULL address; never dereferenced on these paths
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "probesdf.h")).read()
+    return sorted(set(re.findall(r"\b(psdf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = ps.lib()
+    names = _declared()
+    assert set(names) == set(ps.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.psdf_abi_version() == ps.ABI_VERSION
+
+
+def _field(**kw):
+    f = ps._Field(C.sizeof(ps._Field), 64, 16, 3, 9, 4, 16, 0, 0, 0, FAKE, FAKE, FAKE, FAKE)
+    for k, v in kw.items():
+        setattr(f, k, v)
+    return f
+
+
+def _opts(**kw):
+    o = ps._RenderOpts(C.sizeof(ps._RenderOpts), 64, 64.0, 0.0, 0)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _fwd(f, o, B=0):
+    L = ps.lib()
+    return L.psdf_render_forward(C.byref(f) if f is not None else None,
+                                 C.byref(o) if o is not None else None, B, FAKE, FAKE, FAKE, None,
+                                 None, None)
+
+
+def test_empty_batch_ok():
+    assert _fwd(_field(), _opts(), 0) == ps.OK
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(struct_size=12), ps.EINVAL),
+    (dict(R=1), ps.EINVAL),
+    (dict(P=4096), ps.EINVAL),
+    (dict(n_feat=4), ps.EUNSUPPORTED),
+    (dict(sh_coeffs=5), ps.EUNSUPPORTED),
+    (dict(mlp_hidden=32), ps.EUNSUPPORTED),
+    (dict(feat_dtype=2), ps.EUNSUPPORTED),
+    (dict(mlp_dtype=7), ps.EUNSUPPORTED),
+    (dict(sdf=None), ps.EINVAL),
+    (dict(probes=FAKE + 4), ps.EALIGN),
+    (dict(sdf=FAKE + 2), ps.EALIGN),
+    (dict(R=1000), ps.EINVAL),  # 1000^3 * 3 >= 2^31
+])
+def test_field_validation(kw, code):
+    assert _fwd(_field(**kw), _opts()) == code
+    assert ps.last_error() != ""
+
+
+@pytest.mark.parametrize("kw", [dict(n_samples=1), dict(n_samples=5000), dict(tau=0.0),
+                                dict(tau=float("nan")), dict(flags=8), dict(struct_size=3)])
+def test_opts_validation(kw):
+    assert _fwd(_field(), _opts(**kw)) == ps.EINVAL
+
+
+def test_null_descriptors_and_negative_batch():
+    assert _fwd(None, _opts()) == ps.EINVAL
+    assert _fwd(_field(), None) == ps.EINVAL
+    assert _fwd(_field(), _opts(), -1) == ps.EINVAL
+    L = ps.lib()
+    assert L.psdf_render_forward(C.byref(_field()), C.byref(_opts()), 10, None, FAKE, FAKE, None,
+                                 None, None) == ps.EINVAL
+    assert L.psdf_render_forward(C.byref(_field()), C.byref(_opts()), 10, FAKE + 1, FAKE, FAKE,
+                                 None, None, None) == ps.EALIGN
+
+
+def test_backward_requires_grads_and_aux():
+    L = ps.lib()
+    g = ps._Grads(FAKE, FAKE, FAKE, FAKE)
+    assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, FAKE, FAKE,
+                                  None, None) == ps.EINVAL
+    assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, None, FAKE,
+                                  C.byref(g), None) == ps.EINVAL
+    g.probes = FAKE + 2
+    assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, FAKE, FAKE,
+                                  C.byref(g), None) == ps.EALIGN
+
+
+def _step_args(**kw):
+    names = [n for n, _ in ps._StepArgs._fields_]
+    a = ps._StepArgs()
+    a.struct_size = C.sizeof(ps._StepArgs)
+    a.R, a.P, a.n_feat, a.n_pc, a.n_mlp, a.step = 8, 4, 3, 36, 227, 1
+    a.lr_sdf = a.lr_feat = a.lr_probe = a.lr_mlp = 0.01
+    a.beta1, a.beta2, a.eps = 0.9, 0.995, 1e-8
+    base = 0x100000
+    for i, n in enumerate(names[17:]):
+        setattr(a, n, base + i * 0x100000)  # disjoint buffers
+    a.sdf_half_out = a.feat_half_out = a.probes_half_out = a.losses = None
+    for k, v in kw.items():
+        setattr(a, k, v)
+    return a
+
+
+def test_grid_step_validation():
+    L = ps.lib()
+    bad = _step_args(step=0)
+    assert L.psdf_grid_step(C.byref(bad), None) == ps.EINVAL
+    a = _step_args()
+    a.sdf_out = a.sdf_in + 16  # overlapping in/out
+    assert L.psdf_grid_step(C.byref(a), None) == ps.EINVAL
+    assert "out of place" in ps.last_error()
+    assert L.psdf_grid_step(C.byref(_step_args(beta1=1.0)), None) == ps.EINVAL
+    assert L.psdf_grid_step(C.byref(_step_args(g_feat=None)), None) == ps.EINVAL
+    assert L.psdf_grid_step(None, None) == ps.EINVAL
+
+
+def test_sphere_trace_and_loss_validation():
+    L = ps.lib()
+    to = ps._TraceOpts(C.sizeof(ps._TraceOpts), 1e-3, 256, 0)
+    assert L.psdf_render_sphere_trace(C.byref(_field()), C.byref(to), 0, FAKE, 64, 64, FAKE,
+                                      None) == ps.OK
+    to.eps = 0.0
+    assert L.psdf_render_sphere_trace(C.byref(_field()), C.byref(to), 1, FAKE, 64, 64, FAKE,
+                                      None) == ps.EINVAL
+    assert L.psdf_l1_loss(0, None, None, None, None, None) == ps.OK
+    assert L.psdf_l1_loss(5, FAKE, None, FAKE, None, None) == ps.EINVAL
