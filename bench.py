@@ -134,16 +134,7 @@ def time_inference(torch, ps, wl, steps, warmup):
     """Sphere-traced inference, FP16 grids 512^3 / 128^3, 16 views at 1920x1080."""
     import numpy as np
     w = wl.WORKLOADS["trace512"]
-    g = torch.Generator(device="cuda").manual_seed(0)
-    R, P = w.R, w.P
-    a = torch.linspace(-1.0, 1.0, R, device="cuda", dtype=torch.float64)
-    z, y, x = torch.meshgrid(a, a, a, indexing="ij")
-    sdf = (torch.sqrt(x * x + y * y + z * z) - 0.5).half()
-    del x, y, z
-    feat = (torch.randn((R, R, R, 3), generator=g, device="cuda") * 0.1).half()
-    probes = (torch.randn((P, P, P, w.n_sh, 4), generator=g, device="cuda") * 0.1).half()
-    mlp = torch.from_numpy(wl.xavier_uniform_mlp(np.random.default_rng(0))).cuda()
-    fld = ps.Field(sdf, feat, probes, mlp, 0)
+    fld = gpu_field(torch, ps, wl, w, 0, feat_half=True, sdf_half=True)
     cams = torch.from_numpy(np.stack([c.as_array() for c in wl.fibonacci_cameras(w.views, w.W, w.H)])).cuda()
     out = torch.empty((w.views, w.H, w.W, 3), device="cuda")
     for _ in range(warmup):
@@ -161,6 +152,116 @@ def time_inference(torch, ps, wl, steps, warmup):
     log(f"inference: {ms:.3f} ms per launch of {w.views} views")
     return dict(workload="trace512", ms_per_frame=ms / w.views, rays_per_s=rays / (ms * 1e-3),
                 views=w.views, W=w.W, H=w.H, grids="fp16 512^3 / 128^3", mlp="f32")
+
+
+def gpu_field(torch, ps, wl, w, seed, shape="sphere", feat_half=False, sdf_half=False,
+              mlp_dtype=0):
+    """Seeded synthetic field generated on the GPU (large grids; no oracle needed)."""
+    import numpy as np
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    R, P = w.R, w.P
+    a = torch.linspace(-1.0, 1.0, R, device="cuda", dtype=torch.float64)
+    sdf = torch.empty((R, R, R), device="cuda", dtype=torch.float32)
+    for k in range(R):  # slice by slice keeps the FP64 temporaries small
+        y, x = torch.meshgrid(a, a, indexing="ij")
+        if shape == "sphere":
+            v = torch.sqrt(x * x + y * y + a[k] * a[k]) - 0.5
+        else:
+            v = torch.sqrt((torch.sqrt(x * x + y * y) - 0.5) ** 2 + a[k] * a[k]) - 0.2
+        sdf[k] = v.float()
+    feat = torch.randn((R, R, R, 3), generator=g, device="cuda") * 0.1
+    probes = torch.randn((P, P, P, w.n_sh, 4), generator=g, device="cuda") * 0.1
+    mlp = torch.from_numpy(wl.xavier_uniform_mlp(np.random.default_rng(seed))).cuda()
+    if feat_half:
+        feat, probes = feat.half(), probes.half()
+    if sdf_half:
+        sdf = sdf.half()
+    return ps.Field(sdf, feat, probes, mlp, mlp_dtype)
+
+
+def time_fwd_bwd_512(torch, ps, wl, steps, warmup):
+    """mixed512: forward + L1 + backward at 512^3 / 128^3, 2^20 rays, N = 64, no skip,
+    FP32 and FP16 storage with the MLP on FP16 MFMA (and BF16)."""
+    import numpy as np
+    w = wl.WORKLOADS["mixed512"]
+    o, d = wl.workload_rays(w)
+    do, dd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    B = o.shape[0]
+    opts = ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels)
+    tgt = torch.empty((B, 3), device="cuda")
+    tf = gpu_field(torch, ps, wl, w, 1, shape="torus")
+    ps.render_forward(tf, opts, do, dd, tgt)
+    del tf
+    out = {}
+    base = gpu_field(torch, ps, wl, w, 0)
+    for label, half, mdt in (("fp32", False, 0), ("fp16", True, 1), ("bf16", True, 2)):
+        fld = ps.Field(base.sdf, base.feat.half() if half else base.feat,
+                       base.probes.half() if half else base.probes, base.mlp, mdt)
+        rgb = torch.empty((B, 3), device="cuda")
+        aux = torch.empty((B, 4), device="cuda")
+        dL = torch.empty((B, 3), device="cuda")
+        grads = {k: torch.zeros(v.shape, device="cuda", dtype=torch.float32) for k, v in
+                 dict(sdf=fld.sdf, feat=fld.feat, probes=fld.probes, mlp=fld.mlp).items()}
+        def step():
+            ps.render_forward(fld, opts, do, dd, rgb, aux)
+            ps.l1_loss(rgb, tgt, dL)
+            ps.render_backward(fld, opts, do, dd, aux, dL, grads)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        tf_ms = tb_ms = 0.0
+        for _ in range(steps):
+            e[0].record()
+            ps.render_forward(fld, opts, do, dd, rgb, aux)
+            e[1].record()
+            ps.l1_loss(rgb, tgt, dL)
+            e[2].record()
+            ps.render_backward(fld, opts, do, dd, aux, dL, grads)
+            e[3].record()
+            torch.cuda.synchronize()
+            tf_ms += e[0].elapsed_time(e[1])
+            tb_ms += e[2].elapsed_time(e[3])
+        tf_ms /= steps
+        tb_ms /= steps
+        out[label] = {"fwd_ms": tf_ms, "bwd_ms": tb_ms,
+                      "fwd_bwd_rays_per_s": B / ((tf_ms + tb_ms) * 1e-3)}
+        log(f"mixed512 {label}: fwd {tf_ms:.3f} ms, bwd {tb_ms:.3f} ms")
+        del fld, grads
+        torch.cuda.empty_cache()
+    out["ratio_fp16_vs_fp32"] = out["fp16"]["fwd_bwd_rays_per_s"] / out["fp32"]["fwd_bwd_rays_per_s"]
+    out["ratio_bf16_vs_fp32"] = out["bf16"]["fwd_bwd_rays_per_s"] / out["fp32"]["fwd_bwd_rays_per_s"]
+    out["config"] = {"R": w.R, "P": w.P, "rays": B, "samples": w.n_samples, "skip_voxels": 0}
+    return out
+
+
+def time_iter512(torch, ps, wl, iters, warmup):
+    """iter512: full training iteration (forward, L1, backward, grid step over all
+    512^3 x 4 + 128^3 x 36 + 227 parameters) at 2^20 rays, N = 128, skip 4 voxels."""
+    w = wl.WORKLOADS["iter512"]
+    o, d = wl.workload_rays(w)
+    st = dict(o=torch.from_numpy(o).cuda(), d=torch.from_numpy(d).cuda(), B=o.shape[0], half={},
+              mlp_dtype=0)
+    f0 = gpu_field(torch, ps, wl, w, 0)
+    st["master"] = dict(sdf=f0.sdf, feat=f0.feat, probes=f0.probes, mlp=f0.mlp)
+    st["spare"] = {k: torch.empty_like(v) for k, v in st["master"].items() if k != "mlp"}
+    st["grads"] = {k: torch.zeros_like(v) for k, v in st["master"].items()}
+    st["m"] = {k: torch.zeros_like(v) for k, v in st["master"].items()}
+    st["v"] = {k: torch.zeros_like(v) for k, v in st["master"].items()}
+    B = st["B"]
+    for k in ("rgb", "dL", "target"):
+        st[k] = torch.empty((B, 3), device="cuda")
+    st["aux"] = torch.empty((B, 4), device="cuda")
+    st["loss"] = torch.empty(1, device="cuda")
+    tf = gpu_field(torch, ps, wl, w, 1, shape="torus")
+    ps.render_forward(tf, ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels), st["o"], st["d"],
+                      st["target"])
+    del tf
+    ms, kern = time_training(torch, ps, w, st, iters, warmup, "iter512")
+    return {"ms_per_iteration": ms, "iterations": iters, "kernels_ms": kern,
+            "rays_per_s": B / (ms * 1e-3),
+            "params": w.R ** 3 * 4 + w.P ** 3 * w.n_sh * 4 + 227,
+            "grid_step_GBps": 32.0 * (w.R ** 3 * 4 + w.P ** 3 * w.n_sh * 4) / (kern["grid_step"] * 1e-3) / 1e9}
 
 
 def cpu_baseline(wl, w, field, rays, n_rays=16384):
@@ -275,6 +376,13 @@ def main():
                            "speedup_vs_fp32": ms / msm}
         log("inference (sphere trace, 16 x 1080p) ...")
         result["inference"] = time_inference(torch, ps, wl, max(2, args.steps // 4), 1)
+        torch.cuda.empty_cache()
+        log("mixed512 (fp32 vs fp16/bf16 MFMA, 512^3 / 128^3, 2^20 rays) ...")
+        result["mixed512"] = time_fwd_bwd_512(torch, ps, wl, max(2, args.steps // 4), 1)
+        torch.cuda.empty_cache()
+        log("iter512 (full iteration, 100 iterations) ...")
+        result["iter512"] = time_iter512(torch, ps, wl, 100, 2)
+        torch.cuda.empty_cache()
 
     if args.calib_copy:
         x = torch.empty(1 << 28, device="cuda")

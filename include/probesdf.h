@@ -168,6 +168,8 @@ int psdf_l1_loss(int64_t B, const float* rgb, const float* target, float* dL_drg
  * then bias-corrected Adam (Kingma & Ba, Algorithm 1) with `step` >= 1.
  * Grids are updated OUT OF PLACE (the stencils read neighbours): *_in and
  * *_out must not overlap; the MLP is updated in place.  Gradients are zeroed.
+ * Alignment: the grid buffers (params, gradients, moments) 16 bytes, FP16
+ * copies 8 bytes, MLP buffers 4 bytes.
  * Optional FP16 render copies (round to nearest even) of the new sdf, feat
  * and probes are written when their pointers are non-NULL.  `losses` [3]
  * (nullable, device) receives (L_eik, L_feat, L_probe) of the input

@@ -205,17 +205,20 @@ int psdf_grid_step(const psdf_step_args* s, void* stream) {
                        s->m_probes, s->v_probes};
   for (const void* p : req) {
     if (!p) return fail(PSDF_EINVAL, "a required step buffer is NULL");
-    if (!aligned(p, 4)) return fail(PSDF_EALIGN, "a step buffer is misaligned");
+    if (!aligned(p, 16)) return fail(PSDF_EALIGN, "step buffers must be 16-byte aligned");
   }
   if (s->n_mlp > 0 && (!s->mlp || !s->g_mlp || !s->m_mlp || !s->v_mlp))
     return fail(PSDF_EINVAL, "MLP step buffers are NULL");
+  if (s->n_mlp > 0 && (!aligned(s->mlp, 4) || !aligned(s->g_mlp, 4) || !aligned(s->m_mlp, 4) ||
+                       !aligned(s->v_mlp, 4)))
+    return fail(PSDF_EALIGN, "MLP step buffers misaligned");
   const size_t bs = (size_t)r3 * 4, bf = (size_t)r3 * s->n_feat * 4, bp = (size_t)p3 * s->n_pc * 4;
   if (overlap(s->sdf_in, bs, s->sdf_out, bs) || overlap(s->feat_in, bf, s->feat_out, bf) ||
       overlap(s->probes_in, bp, s->probes_out, bp))
     return fail(PSDF_EINVAL, "grid step is out of place: *_in and *_out must not overlap");
   const void* halves[] = {s->sdf_half_out, s->feat_half_out, s->probes_half_out};
   for (const void* p : halves)
-    if (p && !aligned(p, 2)) return fail(PSDF_EALIGN, "FP16 copy misaligned");
+    if (p && !aligned(p, 8)) return fail(PSDF_EALIGN, "FP16 copies must be 8-byte aligned");
   if (s->losses && !aligned(s->losses, 4)) return fail(PSDF_EALIGN, "losses misaligned");
 
   psdf::StepArgs a{};

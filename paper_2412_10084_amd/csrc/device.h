@@ -48,34 +48,16 @@ __device__ __forceinline__ float4 ld4(const _Float16* __restrict__ p, int i) {
   return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
 }
 
-__device__ __forceinline__ float clamp1(float x) { return fminf(fmaxf(x, -1.0f), 1.0f); }
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
 
 // ---------------------------------------------------------------------------
-// align-corners cell of a point: per axis u = (x+1)/h, k0 = clamp(floor u, 0, R-2)
+// align-corners cell of a point: per axis u = (x+1)/h, k0 = clamp(floor u, 0, R-2),
+// weights f = u - k0 (computed in FP64, see shade.h)
 // ---------------------------------------------------------------------------
 struct Cell {
   int base;  // flat index of corner (k0x, k0y, k0z)
   float fx, fy, fz;
 };
-
-__device__ __forceinline__ void axis_cell(float x, float inv_h, float kmax, int& k, float& f) {
-  float u = (x + 1.0f) * inv_h;
-  float fl = fminf(fmaxf(floorf(u), 0.0f), kmax);
-  k = (int)fl;
-  f = u - fl;
-}
-
-__device__ __forceinline__ Cell cell_at(float px, float py, float pz, int R, float inv_h) {
-  Cell c;
-  int kx, ky, kz;
-  const float kmax = (float)(R - 2);
-  axis_cell(px, inv_h, kmax, kx, c.fx);
-  axis_cell(py, inv_h, kmax, ky, c.fy);
-  axis_cell(pz, inv_h, kmax, kz, c.fz);
-  c.base = (kz * R + ky) * R + kx;
-  return c;
-}
 
 // corner c = dx + 2 dy + 4 dz
 __device__ __forceinline__ int corner_off(int c, int R) {
@@ -95,14 +77,26 @@ __device__ __forceinline__ void corner_w(const Cell& c, float w[8]) {
   w[7] = c.fx * a3;
 }
 
-// Scalar trilinear value: two x-adjacent corners are neighbours in memory.
+// two x-adjacent nodes in one load (unaligned 8- or 4-byte global load)
+__device__ __forceinline__ float2 ld2(const float* __restrict__ p, int i) {
+  float2 v;
+  __builtin_memcpy(&v, p + i, sizeof(v));
+  return v;
+}
+__device__ __forceinline__ float2 ld2(const _Float16* __restrict__ p, int i) {
+  _Float16 h[2];
+  __builtin_memcpy(h, p + i, sizeof(h));
+  return make_float2((float)h[0], (float)h[1]);
+}
+
+// Scalar trilinear value; x-adjacent corners are neighbours in memory and are
+// fetched as pairs (the cell's k0x <= R-2, so b + 1 stays inside the row).
 template <typename T>
 __device__ __forceinline__ float tri1(const T* __restrict__ g, int R, const Cell& c) {
   const int b = c.base, RR = R * R;
-  const float v000 = ld1(g, b), v100 = ld1(g, b + 1);
-  const float v010 = ld1(g, b + R), v110 = ld1(g, b + R + 1);
-  const float v001 = ld1(g, b + RR), v101 = ld1(g, b + RR + 1);
-  const float v011 = ld1(g, b + RR + R), v111 = ld1(g, b + RR + R + 1);
+  const float2 p00 = ld2(g, b), p10 = ld2(g, b + R), p01 = ld2(g, b + RR), p11 = ld2(g, b + RR + R);
+  const float v000 = p00.x, v100 = p00.y, v010 = p10.x, v110 = p10.y;
+  const float v001 = p01.x, v101 = p01.y, v011 = p11.x, v111 = p11.y;
   const float a0 = lerpf(v000, v100, c.fx), a1 = lerpf(v010, v110, c.fx);
   const float a2 = lerpf(v001, v101, c.fx), a3 = lerpf(v011, v111, c.fx);
   const float b0 = lerpf(a0, a1, c.fy), b1 = lerpf(a2, a3, c.fy);

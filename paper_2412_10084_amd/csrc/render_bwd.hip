@@ -23,9 +23,12 @@ namespace psdf {
 template <int NSH>
 struct BwdLds {
   union {
-    DwLds dw;           // MLP weight-gradient staging
-    ProbeAcc<NSH> pa;   // probe-gradient aggregation (rows kept zero between uses)
+    DwLds dw;            // MLP weight-gradient staging
+    ProbeAcc<NSH> pa;    // probe-gradient aggregation
+    float sc[64][65];    // per-entry scatter rows: SDF patch, feature corners
   } u;
+  int k0[64][3];         // per entry: SDF cell (patch origin + 1)
+  int fb[64];            // per entry: feature cell base node
   RayD ray[64];
   float dL[64][3];
   int next[RING];
@@ -95,17 +98,17 @@ __device__ __forceinline__ void bwd_batch(const RenderArgs& a, const Geo& G, Bwd
   }
   wave_sync();
   float dout[3] = {0.f, 0.f, 0.f};
+  float gs0 = 0.f;  // dL/ds_i through the opacity
   if (ve) {
     const float gdl = L.gdl[slot];
     const float w = L.w[slot];
     const int rl = key & 63, si = key >> 6;
-    // opacity path: s_i and s_{i+1}
     if (a.g_sdf) {
-      const float s0 = L.s0[slot], s1 = L.s1[slot];
-      scatter8(a.g_sdf, G.R, cell_d(x, G.R, G.inv_h), -a.tau * sigmoidf(-a.tau * s0) * gdl);
+      gs0 = -a.tau * sigmoidf(-a.tau * L.s0[slot]) * gdl;
+      // s_{i+1} lies a sample further along the ray: scattered directly
       double x1[3];
       sample_pos(r, sample_t(r, si + 1), x1);
-      scatter8(a.g_sdf, G.R, cell_d(x1, G.R, G.inv_h), a.tau * sigmoidf(-a.tau * s1) * gdl);
+      scatter8(a.g_sdf, G.R, cell_d(x1, G.R, G.inv_h), a.tau * sigmoidf(-a.tau * L.s1[slot]) * gdl);
     }
     dout[0] = w * L.dL[rl][0] * C0 * (1.f - C0);
     dout[1] = w * L.dL[rl][1] * C1 * (1.f - C1);
@@ -120,23 +123,64 @@ __device__ __forceinline__ void bwd_batch(const RenderArgs& a, const Geo& G, Bwd
     for (int c = 0; c < 3; ++c) acc = fmaf(mrnd<M>(W[OFF_W2 + c * HID + k]), dout[c], acc);
     dpre[k] = pre[k] > 0.f ? acc : 0.f;
   }
-  float dfa[4] = {0.f, 0.f, 0.f, 0.f};
-  if (ve) {
-    float dz[NIN];
+  float dz[NIN];
 #pragma unroll
-    for (int j = 0; j < NIN; ++j) {
-      float acc = 0.f;
+  for (int j = 0; j < NIN; ++j) {
+    float acc = 0.f;
 #pragma unroll
-      for (int k = 0; k < HID; ++k) acc = fmaf(mrnd<M>(W[k * NIN + j]), dpre[k], acc);
-      dz[j] = acc;
-    }
-    shade_inputs_backward<NSH>(G, x, v, Y, nm, dz, a.g_sdf, a.g_feat, nullptr);
-    dfa[0] = dz[3];
-    dfa[1] = dz[4];
-    dfa[2] = dz[5];
-    dfa[3] = dz[6];
+    for (int k = 0; k < HID; ++k) acc = fmaf(mrnd<M>(W[k * NIN + j]), dpre[k], acc);
+    dz[j] = ve ? acc : 0.f;
   }
+  // SDF: opacity path at s_i and the normal path, in the entry's 4x4x4 patch
+  if (a.g_sdf) {
+    float* row = L.u.sc[lane];
+#pragma unroll
+    for (int q = 0; q < 64; ++q) row[q] = 0.f;
+    if (ve) {
+      int k0[3];
+      cell_k(x, G.R, G.inv_h, k0);
+      L.k0[lane][0] = k0[0];
+      L.k0[lane][1] = k0[1];
+      L.k0[lane][2] = k0[2];
+      if (gs0 != 0.f) patch_add(row, k0, x, G.R, G.inv_h, gs0);
+      if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch(row, k0, G, x, v, nm, dz);
+    }
+    wave_sync();
+    const int px = lane & 3, py = (lane >> 2) & 3, pz = lane >> 4;
+    for (int e = 0; e < n; ++e) {
+      const float val = L.u.sc[e][lane];
+      const int nx = L.k0[e][0] - 1 + px, ny = L.k0[e][1] - 1 + py, nz = L.k0[e][2] - 1 + pz;
+      if (val != 0.f && nx >= 0 && ny >= 0 && nz >= 0 && nx < G.R && ny < G.R && nz < G.R)
+        atomic_add_f32(a.g_sdf + (nz * G.R + ny) * G.R + nx, val);
+    }
+    wave_sync();
+  }
+  // spatial features: 8 corners x 3 channels, flushed item-major (x-neighbour
+  // corners are 6 contiguous floats)
+  if (!(G.flags & FLAG_NO_FS) && a.g_feat) {
+    if (ve) {
+      const Cell cs = cell_d(x, G.R, G.inv_h);
+      float wc[8];
+      corner_w(cs, wc);
+      L.fb[lane] = cs.base;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int ch = 0; ch < NF; ++ch) L.u.sc[lane][c * NF + ch] = wc[c] * dz[ch];
+    }
+    wave_sync();
+    for (int k = lane; k < n * 8 * NF; k += 64) {
+      const int e = k / (8 * NF), q = k - e * (8 * NF);
+      const int c = q / NF, ch = q - c * NF;
+      const float val = L.u.sc[e][q];
+      if (val != 0.f) atomic_add_f32(a.g_feat + (L.fb[e] + corner_off(c, G.R)) * NF + ch, val);
+    }
+    wave_sync();
+  }
+  // probes: aggregated per distinct probe cell of the batch
   if (!(G.flags & FLAG_NO_FA) && a.g_probes) {
+    probe_acc_clear<NSH>(L.u.pa, lane);
+    const float dfa[4] = {dz[3], dz[4], dz[5], dz[6]};
     probe_scatter_wave<NSH>(L.u.pa, lane, ve, ve ? cell_d(x, G.P, G.inv_hp) : Cell{0, 0.f, 0.f, 0.f},
                             G.P, Y, dfa, a.g_probes);
   }
@@ -157,8 +201,6 @@ __device__ __forceinline__ void bwd_batch(const RenderArgs& a, const Geo& G, Bwd
     db2[0] += dout[0];
     db2[1] += dout[1];
     db2[2] += dout[2];
-    // the staging overwrote the probe accumulator: clear it again
-    probe_acc_clear<NSH>(L.u.pa, lane);
   }
   wave_sync();
 }
@@ -168,7 +210,6 @@ __global__ void __launch_bounds__(BLOCK) render_bwd_kernel(RenderArgs a) {
   __shared__ BwdLds<NSH> lds[WAVES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   BwdLds<NSH>& L = lds[wv];
-  probe_acc_clear<NSH>(L.u.pa, lane);
   const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
 
@@ -200,15 +241,15 @@ __global__ void __launch_bounds__(BLOCK) render_bwd_kernel(RenderArgs a) {
   float logT = 0.f;
   int my_first = 0, my_last = 0, my_cnt = 0;
   int head = 0, tail = 0;
-  double x[3];
-  sample_pos(r, sample_t(r, 0), x);
-  float s_cur = hit ? tri1(sdf, a.R, cell_d(x, a.R, G.inv_h)) : 0.f;
+  MarchU mu;
+  march_init(r, G.inv_h, mu);
+  float s_cur = hit ? tri1(sdf, a.R, march_cell(mu, a.R)) : 0.f;
   float l_cur = log_sigmoid(a.tau * s_cur);
   for (int i = 0;; ++i) {
     const bool stepping = i < a.N - 1;  // wave-uniform
     if (stepping) {
-      sample_pos(r, sample_t(r, i + 1), x);
-      const float s_nx = hit ? tri1(sdf, a.R, cell_d(x, a.R, G.inv_h)) : 0.f;
+      march_step(mu);
+      const float s_nx = hit ? tri1(sdf, a.R, march_cell(mu, a.R)) : 0.f;
       const float l_nx = log_sigmoid(a.tau * s_nx);
       const bool active = hit && (a.skip_thr <= 0.f || fabsf(s_cur) <= a.skip_thr);
       const float dl = l_nx - l_cur;

@@ -102,15 +102,15 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a) {
   float wsum = 0.f, depth = 0.f, logT = 0.f;
   int my_first = 0, my_last = 0, my_cnt = 0;
   int head = 0, tail = 0;  // wave-uniform ring cursors (sequence numbers)
-  double x[3];
-  sample_pos(r, sample_t(r, 0), x);
-  float s_cur = hit ? tri1(sdf, a.R, cell_d(x, a.R, G.inv_h)) : 0.f;
+  MarchU mu;
+  march_init(r, G.inv_h, mu);
+  float s_cur = hit ? tri1(sdf, a.R, march_cell(mu, a.R)) : 0.f;
   float l_cur = log_sigmoid(a.tau * s_cur);
   for (int i = 0;; ++i) {
     const bool stepping = i < a.N - 1;  // wave-uniform
     if (stepping) {
-      sample_pos(r, sample_t(r, i + 1), x);
-      const float s_nx = hit ? tri1(sdf, a.R, cell_d(x, a.R, G.inv_h)) : 0.f;
+      march_step(mu);
+      const float s_nx = hit ? tri1(sdf, a.R, march_cell(mu, a.R)) : 0.f;
       const float l_nx = log_sigmoid(a.tau * s_nx);
       const bool active = hit && (a.skip_thr <= 0.f || fabsf(s_cur) <= a.skip_thr);
       const float dl = l_nx - l_cur;

@@ -65,6 +65,47 @@ __device__ __forceinline__ double sample_t(const RayD& r, int i) {
   return fma((double)i + 0.5, r.dt, r.tn);
 }
 
+// March state: the continuous cell coordinate u = (x+1)/h of the current sample,
+// advanced by du = dt d / h per sample (FP64; after N <= 4096 steps the drift is
+// ~1e-12 of a cell, far below the FP32 rounding of the weights).
+struct MarchU {
+  double u[3], du[3];
+};
+
+__device__ __forceinline__ void march_init(const RayD& r, double inv_h, MarchU& m) {
+  double x[3];
+  sample_pos(r, sample_t(r, 0), x);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    m.u[k] = (x[k] + 1.0) * inv_h;
+    m.du[k] = r.dt * r.d[k] * inv_h;
+  }
+}
+
+__device__ __forceinline__ Cell march_cell(const MarchU& m, int R) {
+  Cell c;
+  int k[3];
+  float f[3];
+  const double umax = (double)(R - 1), kmax = (double)(R - 2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = fmin(fmax(m.u[a], 0.0), umax);  // the cube clamp, in cell units
+    const double fl = fmin(floor(u), kmax);
+    k[a] = (int)fl;
+    f[a] = (float)(u - fl);
+  }
+  c.fx = f[0];
+  c.fy = f[1];
+  c.fz = f[2];
+  c.base = (k[2] * R + k[1]) * R + k[0];
+  return c;
+}
+
+__device__ __forceinline__ void march_step(MarchU& m) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m.u[k] += m.du[k];
+}
+
 // align-corners cell of an FP64 point; the weights are rounded to FP32 once
 __device__ __forceinline__ void axis_cell_d(double x, double inv_h, double kmax, int& k, float& f) {
   const double u = (x + 1.0) * inv_h;
@@ -174,69 +215,18 @@ __device__ __forceinline__ void scatter8(float* g, int R, const Cell& c, float v
   for (int q = 0; q < 8; ++q) atomic_add_f32(g + c.base + corner_off(q, R), val * w[q]);
 }
 
-// Reverse mode of shade_inputs: dL/dz scattered into the grids with FP32 atomics.
-template <int NSH>
-__device__ __forceinline__ void shade_inputs_backward(const Geo& G, const double x[3],
-                                                      const float v[3], const float* Y,
-                                                      const Normal& nm, const float dz[NIN],
-                                                      float* g_sdf, float* g_feat, float* g_probes) {
-  if (!(G.flags & FLAG_NO_FS) && g_feat) {
-    const Cell cs = cell_d(x, G.R, G.inv_h);
-    float w[8];
-    corner_w(cs, w);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int node = cs.base + corner_off(c, G.R);
-#pragma unroll
-      for (int ch = 0; ch < NF; ++ch) atomic_add_f32(g_feat + node * NF + ch, w[c] * dz[ch]);
-    }
-  }
-  if (!(G.flags & FLAG_NO_FA) && g_probes) {
-    const Cell cp = cell_d(x, G.P, G.inv_hp);
-    float w[8];
-    corner_w(cp, w);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      float* gp = g_probes + (cp.base + corner_off(c, G.P)) * (NSH * NA);
-#pragma unroll
-      for (int j = 0; j < NSH; ++j) {
-        const float wy = w[c] * Y[j];
-#pragma unroll
-        for (int k = 0; k < NA; ++k) atomic_add_f32(gp + 4 * j + k, wy * dz[3 + k]);
-      }
-    }
-  }
-  if (!(G.flags & FLAG_NV_ONE) && g_sdf) {
-    const float c = nm.c;
-    const float dc = dz[7] + 2.0f * c * dz[8] + 4.0f * c * c * c * dz[9];
-    float dg[3];
-    if (nm.gn >= 1e-30f) {
-      const float s = dc / nm.gn;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) dg[a] = s * (v[a] - c * nm.n[a]);
-    } else {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) dg[a] = dc * v[a] / 1e-30f;
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
-      xp[a] = fmin(x[a] + G.h, 1.0);
-      xm[a] = fmax(x[a] - G.h, -1.0);
-      const float coef = dg[a] / (float)(xp[a] - xm[a]);
-      scatter8(g_sdf, G.R, cell_d(xp, G.R, G.inv_h), coef);
-      scatter8(g_sdf, G.R, cell_d(xm, G.R, G.inv_h), -coef);
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Wave-aggregated probe-gradient scatter.  The probe grid is coarse, so the
-// shaded samples of one batch (neighbouring rays, consecutive samples) share
-// few probe cells.  Each distinct cell of the batch gets an LDS slot; for each
-// of the 8 corners the lanes add their n_sh x n_ang products w_c Y_j dF_a into
-// the slot with LDS atomics, and the slot's lane issues one global atomic per
-// coefficient, instead of one per sample.
+// Gradient scatter.  FP32 atomics are executed per 64-byte line: a wave
+// instruction whose lanes hit consecutive floats costs about as much as one
+// whose lanes hit a single float each in different lines, so every scatter
+// below arranges its lanes over contiguous runs of the destination grid.
+//
+// Probes: the grid is coarse, so the shaded samples of one batch (neighbouring
+// rays, consecutive samples) share few probe cells.  Each distinct cell of the
+// batch gets an LDS slot; for each of the 8 corners the lanes add their
+// n_sh x n_ang products w_c Y_j dF_a into the slot with LDS atomics, and the
+// slots are flushed coefficient-major, one global atomic per coefficient of
+// each distinct node instead of one per sample.
 // ---------------------------------------------------------------------------
 template <int NSH>
 struct ProbeAcc {
@@ -281,16 +271,83 @@ __device__ __forceinline__ void probe_scatter_wave(ProbeAcc<NSH>& A, int lane, b
       }
     }
     wave_sync();
-    if (lane < U) {
-      float* gp = g_probes + (A.key[lane] + corner_off(c, P)) * (NSH * NA);
-#pragma unroll
-      for (int q = 0; q < NSH * NA; ++q) {
-        const float val = A.acc[lane][q];
-        A.acc[lane][q] = 0.f;
-        if (val != 0.f) atomic_add_f32(gp + q, val);
-      }
+    // flush coefficient-major: consecutive lanes hit consecutive floats of a node
+    const int nitems = U * (NSH * NA);
+    for (int k = lane; k < nitems; k += 64) {
+      const int sl = k / (NSH * NA), q = k - sl * (NSH * NA);
+      const float val = A.acc[sl][q];
+      A.acc[sl][q] = 0.f;
+      if (val != 0.f) atomic_add_f32(g_probes + (A.key[sl] + corner_off(c, P)) * (NSH * NA) + q, val);
     }
     wave_sync();
+  }
+}
+
+// SDF: every node an entry's SDF gradient touches (the 8 corners of its cell
+// for the opacity path, the six FD stencil cells for the normal) lies in the
+// 4x4x4 node patch [k0-1, k0+2]^3 around its cell k0 (clamped stencil points
+// fall back onto k0 or k0+1).  The entry accumulates into its own LDS patch
+// row; the patch is flushed one entry per wave instruction (16 x-runs of 4).
+__device__ __forceinline__ void cell_k(const double x[3], int R, double inv_h, int k[3]) {
+  const double kmax = (double)(R - 2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) k[a] = (int)fmin(fmax(floor((x[a] + 1.0) * inv_h), 0.0), kmax);
+}
+
+// add val * trilinear weights of the cell of point y into the patch of cell k0
+__device__ __forceinline__ void patch_add(float* row, const int k0[3], const double y[3], int R,
+                                          double inv_h, float val) {
+  int k[3];
+  float f[3];
+  const double kmax = (double)(R - 2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // same cell rule as everywhere, then kept within one cell of k0: only an FP64
+    // rounding of u at an integer can step further, and moving the cell by one
+    // with f shifted by one puts the weights on the same nodes
+    const double u = (y[a] + 1.0) * inv_h;
+    double fl = fmin(fmax(floor(u), 0.0), kmax);
+    fl = fmin(fmax(fl, (double)(k0[a] - 1)), (double)(k0[a] + 1));
+    k[a] = (int)fl;
+    f[a] = (float)(u - fl);
+  }
+  // k[a] - k0[a] + 1 is in [0, 2] per axis, so o + 21 <= 63
+  const int o = (k[2] - k0[2] + 1) * 16 + (k[1] - k0[1] + 1) * 4 + (k[0] - k0[0] + 1);
+  const float gx = 1.0f - f[0], gy = 1.0f - f[1], gz = 1.0f - f[2];
+  row[o + 0] += val * gx * gy * gz;
+  row[o + 1] += val * f[0] * gy * gz;
+  row[o + 4] += val * gx * f[1] * gz;
+  row[o + 5] += val * f[0] * f[1] * gz;
+  row[o + 16] += val * gx * gy * f[2];
+  row[o + 17] += val * f[0] * gy * f[2];
+  row[o + 20] += val * gx * f[1] * f[2];
+  row[o + 21] += val * f[0] * f[1] * f[2];
+}
+
+// SDF gradient of the normal path (c = n.v, n = g/|g|, g the FD gradient) into
+// the patch row
+__device__ __forceinline__ void normal_backward_patch(float* row, const int k0[3], const Geo& G,
+                                                      const double x[3], const float v[3],
+                                                      const Normal& nm, const float dz[NIN]) {
+  const float c = nm.c;
+  const float dc = dz[7] + 2.0f * c * dz[8] + 4.0f * c * c * c * dz[9];
+  float dg[3];
+  if (nm.gn >= 1e-30f) {
+    const float sc = dc / nm.gn;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dg[a] = sc * (v[a] - c * nm.n[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dg[a] = dc * v[a] / 1e-30f;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+    xp[a] = fmin(x[a] + G.h, 1.0);
+    xm[a] = fmax(x[a] - G.h, -1.0);
+    const float coef = dg[a] / (float)(xp[a] - xm[a]);
+    patch_add(row, k0, xp, G.R, G.inv_h, coef);
+    patch_add(row, k0, xm, G.R, G.inv_h, -coef);
   }
 }
 

@@ -1,14 +1,15 @@
 // Fused optimiser step over the ProbeSDF parameters: regulariser gradients
-// (eikonal on the SDF, squared-difference smoothness on the features and on
-// the probe coefficients; Sec. 3.3, Eqs. eikonal_reg, smooth_features,
-// smooth_probes) added to the accumulated render gradient, then Adam
-// (Sec. 3.4; moments as in the supplementary scheduling section).
+// (eikonal on the SDF, squared-difference smoothness on the features and on the
+// probe coefficients; Sec. 3.3, Eqs. eikonal_reg, smooth_features,
+// smooth_probes) added to the accumulated render gradient, then Adam (Sec. 3.4;
+// moments as in the supplementary scheduling section).
 //
-// Each grid is one streaming pass: a thread owns one parameter, gathers the
-// regulariser gradient of that parameter from its stencil (so no scatter and no
-// atomics), applies Adam, writes the new value to a separate output buffer
-// (neighbours still read the old one), writes the moments back, zeroes the
-// gradient and optionally writes an FP16 copy.
+// Each grid is one streaming pass launched as (row chunk, j, k): a thread owns
+// one parameter (four for probes), gathers the regulariser gradient of that
+// parameter from its stencil (no scatter, no atomics), applies Adam, writes the
+// new value to a separate output buffer (neighbours still read the old one),
+// writes the moments back, zeroes the gradient and optionally writes an FP16
+// copy.  Index arithmetic divides only by compile-time constants.
 #include "device.h"
 #include "kernels.h"
 
@@ -37,49 +38,46 @@ __device__ __forceinline__ void block_add(float val, float* dst) {
   }
 }
 
-// central-difference gradient of node (i,j,k); valid only for interior nodes
-__device__ __forceinline__ void cd_grad(const float* __restrict__ s, int R, int n, float inv2h,
-                                        float g[3]) {
-  const int RR = R * R;
-  g[0] = (s[n + 1] - s[n - 1]) * inv2h;
-  g[1] = (s[n + R] - s[n - R]) * inv2h;
-  g[2] = (s[n + RR] - s[n - RR]) * inv2h;
-}
-
-// dL_eik/dg at node (i,j,k) times 1/(coef): 2(|g|-1)/|g| g, zero off the interior
-__device__ __forceinline__ float eik_q(const float* __restrict__ s, int R, int i, int j, int k,
-                                       float inv2h, int axis) {
+// ---------------------------------------------------------------------------
+// SDF: eikonal gradient in gather form.  With g_n the central-difference
+// gradient of interior node n and q_n = 2 (|g_n| - 1) g_n / |g_n| (0 off the
+// interior or for g_n = 0), dL/ds_m = lambda/M * sum_a (q_{m-e_a,a} - q_{m+e_a,a}) / 2h.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float eik_q(const float* __restrict__ s, int R, int RR, int i, int j,
+                                       int k, float inv2h, int axis) {
   if (i < 1 || j < 1 || k < 1 || i > R - 2 || j > R - 2 || k > R - 2) return 0.f;
-  float g[3];
-  cd_grad(s, R, (k * R + j) * R + i, inv2h, g);
-  const float gn = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  const int n = (k * R + j) * R + i;
+  const float gx = (s[n + 1] - s[n - 1]) * inv2h;
+  const float gy = (s[n + R] - s[n - R]) * inv2h;
+  const float gz = (s[n + RR] - s[n - RR]) * inv2h;
+  const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
   if (!(gn > 0.f)) return 0.f;
-  return 2.0f * (gn - 1.0f) / gn * g[axis];
+  const float ga = axis == 0 ? gx : (axis == 1 ? gy : gz);
+  return 2.0f * (gn - 1.0f) / gn * ga;
 }
 
 __global__ void __launch_bounds__(SBLOCK) step_sdf_kernel(StepArgs a) {
-  const int R = a.R;
-  const int64_t n_nodes = (int64_t)R * R * R;
-  const int64_t n64 = (int64_t)blockIdx.x * SBLOCK + threadIdx.x;
-  const bool valid = n64 < n_nodes;
-  const int n = valid ? (int)n64 : 0;
-  const int i = n % R, j = (n / R) % R, k = n / (R * R);
+  const int R = a.R, RR = R * R;
+  const int i = blockIdx.x * SBLOCK + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  const bool valid = i < R;
   const float inv2h = 0.5f / a.h;
   const float M = (float)(R - 2) * (float)(R - 2) * (float)(R - 2);
   const float coef = a.lambda_eik / M;
   float loss = 0.f;
   if (valid) {
+    const int n = (k * R + j) * R + i;
     const float* __restrict__ s = a.sdf_in;
     float G = a.g_sdf[n];
     if (a.lambda_eik != 0.f && R >= 3) {
-      float ge = eik_q(s, R, i - 1, j, k, inv2h, 0) - eik_q(s, R, i + 1, j, k, inv2h, 0) +
-                 eik_q(s, R, i, j - 1, k, inv2h, 1) - eik_q(s, R, i, j + 1, k, inv2h, 1) +
-                 eik_q(s, R, i, j, k - 1, inv2h, 2) - eik_q(s, R, i, j, k + 1, inv2h, 2);
+      const float ge = eik_q(s, R, RR, i - 1, j, k, inv2h, 0) - eik_q(s, R, RR, i + 1, j, k, inv2h, 0) +
+                       eik_q(s, R, RR, i, j - 1, k, inv2h, 1) - eik_q(s, R, RR, i, j + 1, k, inv2h, 1) +
+                       eik_q(s, R, RR, i, j, k - 1, inv2h, 2) - eik_q(s, R, RR, i, j, k + 1, inv2h, 2);
       G += coef * ge * inv2h;
-      if (i >= 1 && j >= 1 && k >= 1 && i <= R - 2 && j <= R - 2 && k <= R - 2) {
-        float g[3];
-        cd_grad(s, R, n, inv2h, g);
-        const float e = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) - 1.0f;
+      if (a.losses && i >= 1 && j >= 1 && k >= 1 && i <= R - 2 && j <= R - 2 && k <= R - 2) {
+        const float gx = (s[n + 1] - s[n - 1]) * inv2h;
+        const float gy = (s[n + R] - s[n - R]) * inv2h;
+        const float gz = (s[n + RR] - s[n - RR]) * inv2h;
+        const float e = sqrtf(gx * gx + gy * gy + gz * gz) - 1.0f;
         loss = e * e;
       }
     }
@@ -94,41 +92,113 @@ __global__ void __launch_bounds__(SBLOCK) step_sdf_kernel(StepArgs a) {
   if (a.losses) block_add(loss * coef, a.losses + 0);
 }
 
-// smoothness + Adam on a grid with C channels per node
-__global__ void __launch_bounds__(SBLOCK) step_tv_kernel(int R, int C, float lambda, float lr,
-                                                         const float* __restrict__ F_in,
-                                                         float* F_out, float* g, float* m_, float* v_,
-                                                         _Float16* half_out, float* loss_dst,
-                                                         StepArgs a) {
-  const int64_t n_el = (int64_t)R * R * R * C;
-  const int64_t e64 = (int64_t)blockIdx.x * SBLOCK + threadIdx.x;
-  const bool valid = e64 < n_el;
-  const int e = valid ? (int)e64 : 0;
-  const int node = e / C;
-  const int i = node % R, j = (node / R) % R, k = node / (R * R);
+// ---------------------------------------------------------------------------
+// smoothness + Adam on a grid with C channels per node:
+// dL/dF_{m,c} = 2 lambda / (3 R^2 (R-1) C) * sum over existing neighbours nb of (F_m - F_nb)
+// ---------------------------------------------------------------------------
+struct TvArgs {
+  int R;
+  float lambda, lr;
+  const float* F_in;
+  float* F_out;
+  float* g;
+  float* m;
+  float* v;
+  _Float16* half_out;
+  float* loss_dst;
+};
+
+template <int C>  // channels per node; one float per thread
+__global__ void __launch_bounds__(SBLOCK) step_tv_kernel(TvArgs t, StepArgs a) {
+  const int R = t.R, rowlen = R * C;
+  const int xi = blockIdx.x * SBLOCK + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  const bool valid = xi < rowlen;
   const float npairs = 3.0f * (float)R * (float)R * (float)(R - 1);
-  const float scale = lambda / (npairs * (float)C);
+  const float scale = t.lambda / (npairs * (float)C);
   float loss = 0.f;
   if (valid) {
-    const float f = F_in[e];
+    const int i = xi / C;
+    const int e = (k * R + j) * rowlen + xi;
+    const int sy = rowlen, sz = R * rowlen;
+    const float* __restrict__ F = t.F_in;
+    const float f = F[e];
     float acc = 0.f;
-    const int sx = C, sy = R * C, sz = R * R * C;
-    if (i > 0) acc += f - F_in[e - sx];
-    if (i < R - 1) { const float d = F_in[e + sx] - f; acc -= d; loss += d * d; }
-    if (j > 0) acc += f - F_in[e - sy];
-    if (j < R - 1) { const float d = F_in[e + sy] - f; acc -= d; loss += d * d; }
-    if (k > 0) acc += f - F_in[e - sz];
-    if (k < R - 1) { const float d = F_in[e + sz] - f; acc -= d; loss += d * d; }
-    const float G = g[e] + 2.0f * scale * acc;
-    float m = m_[e], v = v_[e];
-    const float p = adam_update(f, G, m, v, lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
-    F_out[e] = p;
-    m_[e] = m;
-    v_[e] = v;
-    g[e] = 0.f;
-    if (half_out) half_out[e] = (_Float16)p;
+    if (i > 0) acc += f - F[e - C];
+    if (i < R - 1) { const float d = F[e + C] - f; acc -= d; loss += d * d; }
+    if (j > 0) acc += f - F[e - sy];
+    if (j < R - 1) { const float d = F[e + sy] - f; acc -= d; loss += d * d; }
+    if (k > 0) acc += f - F[e - sz];
+    if (k < R - 1) { const float d = F[e + sz] - f; acc -= d; loss += d * d; }
+    const float G = t.g[e] + 2.0f * scale * acc;
+    float m = t.m[e], v = t.v[e];
+    const float p = adam_update(f, G, m, v, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    t.F_out[e] = p;
+    t.m[e] = m;
+    t.v[e] = v;
+    t.g[e] = 0.f;
+    if (t.half_out) t.half_out[e] = (_Float16)p;
   }
-  if (loss_dst) block_add(loss * scale, loss_dst);
+  if (t.loss_dst) block_add(loss * scale, t.loss_dst);
+}
+
+// four consecutive channels of one node per thread (C a multiple of 4)
+__device__ __forceinline__ float4 ld4g(const float* p, int e) {
+  return *reinterpret_cast<const float4*>(p + e);
+}
+__device__ __forceinline__ void st4g(float* p, int e, float4 v) {
+  *reinterpret_cast<float4*>(p + e) = v;
+}
+
+template <int C>
+__global__ void __launch_bounds__(SBLOCK) step_tv4_kernel(TvArgs t, StepArgs a) {
+  static_assert(C % 4 == 0, "vector path needs C % 4 == 0");
+  const int R = t.R, rowlen = R * C;
+  const int xi = (blockIdx.x * SBLOCK + threadIdx.x) * 4, j = blockIdx.y, k = blockIdx.z;
+  const bool valid = xi < rowlen;
+  const float npairs = 3.0f * (float)R * (float)R * (float)(R - 1);
+  const float scale = t.lambda / (npairs * (float)C);
+  float loss = 0.f;
+  if (valid) {
+    const int i = xi / C;
+    const int e = (k * R + j) * rowlen + xi;
+    const int sy = rowlen, sz = R * rowlen;
+    const float* __restrict__ F = t.F_in;
+    const float4 f = ld4g(F, e);
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto back = [&](int off) {
+      const float4 b = ld4g(F, e - off);
+      acc.x += f.x - b.x; acc.y += f.y - b.y; acc.z += f.z - b.z; acc.w += f.w - b.w;
+    };
+    auto fwd = [&](int off) {
+      const float4 b = ld4g(F, e + off);
+      const float dx = b.x - f.x, dy = b.y - f.y, dz = b.z - f.z, dw = b.w - f.w;
+      acc.x -= dx; acc.y -= dy; acc.z -= dz; acc.w -= dw;
+      loss += dx * dx + dy * dy + dz * dz + dw * dw;
+    };
+    if (i > 0) back(C);
+    if (i < R - 1) fwd(C);
+    if (j > 0) back(sy);
+    if (j < R - 1) fwd(sy);
+    if (k > 0) back(sz);
+    if (k < R - 1) fwd(sz);
+    const float4 g = ld4g(t.g, e);
+    float4 m = ld4g(t.m, e), v = ld4g(t.v, e);
+    const float s2 = 2.0f * scale;
+    float4 p;
+    p.x = adam_update(f.x, g.x + s2 * acc.x, m.x, v.x, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.y = adam_update(f.y, g.y + s2 * acc.y, m.y, v.y, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.z = adam_update(f.z, g.z + s2 * acc.z, m.z, v.z, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.w = adam_update(f.w, g.w + s2 * acc.w, m.w, v.w, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    st4g(t.F_out, e, p);
+    st4g(t.m, e, m);
+    st4g(t.v, e, v);
+    st4g(t.g, e, make_float4(0.f, 0.f, 0.f, 0.f));
+    if (t.half_out) {
+      h4 hv = {(_Float16)p.x, (_Float16)p.y, (_Float16)p.z, (_Float16)p.w};
+      *reinterpret_cast<h4*>(t.half_out + e) = hv;
+    }
+  }
+  if (t.loss_dst) block_add(loss * scale, t.loss_dst);
 }
 
 __global__ void __launch_bounds__(SBLOCK) step_mlp_kernel(StepArgs a) {
@@ -147,23 +217,70 @@ __global__ void zero3_kernel(float* p) {
   if (threadIdx.x < 3) p[threadIdx.x] = 0.f;
 }
 
+// any channel count: one float per thread, runtime division
+__global__ void __launch_bounds__(SBLOCK) step_tv_any_kernel(TvArgs t, int C, StepArgs a) {
+  const int R = t.R, rowlen = R * C;
+  const int xi = blockIdx.x * SBLOCK + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  const bool valid = xi < rowlen;
+  const float npairs = 3.0f * (float)R * (float)R * (float)(R - 1);
+  const float scale = t.lambda / (npairs * (float)C);
+  float loss = 0.f;
+  if (valid) {
+    const int i = xi / C;
+    const int e = (k * R + j) * rowlen + xi;
+    const int sy = rowlen, sz = R * rowlen;
+    const float* __restrict__ F = t.F_in;
+    const float f = F[e];
+    float acc = 0.f;
+    if (i > 0) acc += f - F[e - C];
+    if (i < R - 1) { const float d = F[e + C] - f; acc -= d; loss += d * d; }
+    if (j > 0) acc += f - F[e - sy];
+    if (j < R - 1) { const float d = F[e + sy] - f; acc -= d; loss += d * d; }
+    if (k > 0) acc += f - F[e - sz];
+    if (k < R - 1) { const float d = F[e + sz] - f; acc -= d; loss += d * d; }
+    float m = t.m[e], v = t.v[e];
+    const float p = adam_update(f, t.g[e] + 2.0f * scale * acc, m, v, t.lr, a.beta1, a.beta2,
+                                a.eps, a.bc1, a.bc2);
+    t.F_out[e] = p;
+    t.m[e] = m;
+    t.v[e] = v;
+    t.g[e] = 0.f;
+    if (t.half_out) t.half_out[e] = (_Float16)p;
+  }
+  if (t.loss_dst) block_add(loss * scale, t.loss_dst);
+}
+
+static void launch_tv(const TvArgs& t, int C, const StepArgs& a, hipStream_t s) {
+  const unsigned R = (unsigned)t.R;
+  const unsigned rowlen = R * (unsigned)C;
+  if (C % 4 == 0 && (C == 4 || C == 16 || C == 36 || C == 64)) {
+    const dim3 grid((rowlen / 4 + SBLOCK - 1) / SBLOCK, R, R);
+    switch (C) {
+      case 4: hipLaunchKernelGGL(step_tv4_kernel<4>, grid, dim3(SBLOCK), 0, s, t, a); break;
+      case 16: hipLaunchKernelGGL(step_tv4_kernel<16>, grid, dim3(SBLOCK), 0, s, t, a); break;
+      case 36: hipLaunchKernelGGL(step_tv4_kernel<36>, grid, dim3(SBLOCK), 0, s, t, a); break;
+      default: hipLaunchKernelGGL(step_tv4_kernel<64>, grid, dim3(SBLOCK), 0, s, t, a); break;
+    }
+    return;
+  }
+  const dim3 grid((rowlen + SBLOCK - 1) / SBLOCK, R, R);
+  if (C == 3) hipLaunchKernelGGL(step_tv_kernel<3>, grid, dim3(SBLOCK), 0, s, t, a);
+  else hipLaunchKernelGGL(step_tv_any_kernel, grid, dim3(SBLOCK), 0, s, t, C, a);
+}
+
 hipError_t launch_grid_step(const StepArgs& a, hipStream_t s) {
   if (a.losses) hipLaunchKernelGGL(zero3_kernel, dim3(1), dim3(64), 0, s, a.losses);
-  const int64_t ns = (int64_t)a.R * a.R * a.R;
-  hipLaunchKernelGGL(step_sdf_kernel, dim3((unsigned)((ns + SBLOCK - 1) / SBLOCK)), dim3(SBLOCK), 0,
-                     s, a);
-  const int64_t nf = ns * a.n_feat;
-  hipLaunchKernelGGL(step_tv_kernel, dim3((unsigned)((nf + SBLOCK - 1) / SBLOCK)), dim3(SBLOCK), 0,
-                     s, a.R, a.n_feat, a.lambda_tv_feat, a.lr_feat, a.feat_in, a.feat_out, a.g_feat,
-                     a.m_feat, a.v_feat, static_cast<_Float16*>(a.feat_half),
-                     a.losses ? a.losses + 1 : nullptr, a);
-  const int64_t np = (int64_t)a.P * a.P * a.P * a.n_pc;
-  hipLaunchKernelGGL(step_tv_kernel, dim3((unsigned)((np + SBLOCK - 1) / SBLOCK)), dim3(SBLOCK), 0,
-                     s, a.P, a.n_pc, a.lambda_tv_probe, a.lr_probe, a.probes_in, a.probes_out,
-                     a.g_probes, a.m_probes, a.v_probes, static_cast<_Float16*>(a.probes_half),
-                     a.losses ? a.losses + 2 : nullptr, a);
-  hipLaunchKernelGGL(step_mlp_kernel, dim3((unsigned)((a.n_mlp + SBLOCK - 1) / SBLOCK)),
-                     dim3(SBLOCK), 0, s, a);
+  const unsigned R = (unsigned)a.R;
+  hipLaunchKernelGGL(step_sdf_kernel, dim3((R + SBLOCK - 1) / SBLOCK, R, R), dim3(SBLOCK), 0, s, a);
+  TvArgs tf{a.R, a.lambda_tv_feat, a.lr_feat, a.feat_in, a.feat_out, a.g_feat, a.m_feat, a.v_feat,
+            static_cast<_Float16*>(a.feat_half), a.losses ? a.losses + 1 : nullptr};
+  launch_tv(tf, a.n_feat, a, s);
+  TvArgs tp{a.P, a.lambda_tv_probe, a.lr_probe, a.probes_in, a.probes_out, a.g_probes, a.m_probes,
+            a.v_probes, static_cast<_Float16*>(a.probes_half), a.losses ? a.losses + 2 : nullptr};
+  launch_tv(tp, a.n_pc, a, s);
+  if (a.n_mlp > 0)
+    hipLaunchKernelGGL(step_mlp_kernel, dim3((unsigned)((a.n_mlp + SBLOCK - 1) / SBLOCK)),
+                       dim3(SBLOCK), 0, s, a);
   return hipGetLastError();
 }
 

@@ -126,6 +126,9 @@ def test_grid_step_validation():
     assert L.psdf_grid_step(C.byref(_step_args(beta1=1.0)), None) == ps.EINVAL
     assert L.psdf_grid_step(C.byref(_step_args(g_feat=None)), None) == ps.EINVAL
     assert L.psdf_grid_step(None, None) == ps.EINVAL
+    a = _step_args()
+    a.m_feat = a.m_feat + 4  # grid buffers must be 16-byte aligned
+    assert L.psdf_grid_step(C.byref(a), None) == ps.EALIGN
 
 
 def test_sphere_trace_and_loss_validation():
