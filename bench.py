@@ -58,11 +58,14 @@ class KernelTimer:
         return {k: sum(v) / len(v) for k, v in out.items()}
 
 
-def make_state(torch, ps, wl, w, feat_half=False, mlp_dtype=0, seed=0):
+def make_state(torch, ps, wl, w, feat_half=False, mlp_dtype=0, seed=0, order="image"):
     import numpy as np
     f = wl.random_field(seed, w.R, w.P, n_sh=w.n_sh)
     ft = wl.random_field(seed + 1, w.R, w.P, n_sh=w.n_sh, shape="torus")
-    o, d = wl.workload_rays(w)
+    if order == "shuffled":
+        o, d = wl.shuffled(*wl.workload_rays(w), seed=2)
+    else:
+        o, d = wl.workload_rays(w, order)
     cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     master = dict(sdf=cu(f.sdf), feat=cu(f.feat), probes=cu(f.probes), mlp=cu(f.mlp))
     spare = {k: torch.empty_like(v) for k, v in master.items() if k != "mlp"}
@@ -264,6 +267,42 @@ def time_iter512(torch, ps, wl, iters, warmup):
             "grid_step_GBps": 32.0 * (w.R ** 3 * 4 + w.P ** 3 * w.n_sh * 4) / (kern["grid_step"] * 1e-3) / 1e9}
 
 
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2412_10084_amd", "csrc", "*"))):
+        if p.endswith((".hip", ".h", ".cpp")):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+TRAFFIC_KERNELS = {
+    "render_backward": ("void psdf::render_bwd_kernel<float, float, 9, 0>",),
+    "render_forward": ("void psdf::render_fwd_kernel<float, float, 9, 0>",),
+    "grid_step": ("psdf::step_sdf_kernel", "void psdf::step_tv_kernel<3>", "void psdf::step_tv4_kernel<36>",
+                  "psdf::step_mlp_kernel"),
+}
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
+    the kernels changed since the counters were taken (source hash mismatch)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_train256.txt")
+    if not os.path.exists(path) or kernel not in TRAFFIC_KERNELS:
+        return None
+    total, found, ok = 0.0, 0, False
+    for line in open(path):
+        if line.startswith("# kernel source hash:"):
+            ok = line.split(":", 1)[1].strip() == kernel_source_hash()
+        elif line[:1] != "#" and line.strip():
+            parts = line.split(None, 4)
+            if len(parts) == 5 and parts[4].startswith(TRAFFIC_KERNELS[kernel]):
+                total += float(parts[3])
+                found += 1
+    return total if ok and found else None
+
+
 def cpu_baseline(wl, w, field, rays, n_rays=16384):
     """FP64 oracle on the host cores: forward + L1 + backward on a ray sample,
     plus one full oracle grid step, scaled to a step over the whole batch."""
@@ -362,8 +401,10 @@ def main():
     if per_launch is not None:
         ach = per_launch / (kern[dom] * 1e-3) / 1e9
         result["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                              "algorithmic_bytes_per_launch": per_launch}
+                              "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                              "traffic": measured_traffic(dom),
+                              "algorithmic_bytes_per_launch": per_launch,
+                              "launch_ms": kern[dom]}
 
     if not args.no_extras:
         log("mixed precision (fp16 storage, fp16 MFMA MLP) ...")
@@ -374,6 +415,14 @@ def main():
         result["mixed"] = {"rays_per_s": B / (msm * 1e-3), "ms_per_step": msm, "kernels_ms": kernm,
                            "dtype": "f16 storage, f16 MFMA MLP, f32 accumulate",
                            "speedup_vs_fp32": ms / msm}
+        for order in ("tile8", "shuffled"):
+            log(f"ray order {order} ...")
+            sto, _, _ = make_state(torch, ps, wl, w, order=order)
+            mso, kerno = time_training(torch, ps, w, sto, args.steps, args.warmup, order)
+            result[f"order_{order}"] = {"rays_per_s": B / (mso * 1e-3), "ms_per_step": mso,
+                                        "kernels_ms": kerno}
+            del sto
+            torch.cuda.empty_cache()
         log("inference (sphere trace, 16 x 1080p) ...")
         result["inference"] = time_inference(torch, ps, wl, max(2, args.steps // 4), 1)
         torch.cuda.empty_cache()

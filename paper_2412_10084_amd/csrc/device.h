@@ -34,6 +34,24 @@ constexpr int FLAG_NO_FS = 1;
 constexpr int FLAG_NO_FA = 2;
 constexpr int FLAG_NV_ONE = 4;
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2);
+// remap a linear block id so that each XCD works on one contiguous range.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned G) {
+  const unsigned x = b & 7u, j = b >> 3, q = G >> 3, r = G & 7u;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// the same for a 3D grid: returns the remapped (x, y, z) block coordinates
+__device__ __forceinline__ void xcd_block3(unsigned& bx, unsigned& by, unsigned& bz) {
+  const unsigned G = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned Lp = xcd_block(L, G);
+  bx = Lp % gridDim.x;
+  const unsigned t = Lp / gridDim.x;
+  by = t % gridDim.y;
+  bz = t / gridDim.y;
+}
+
 // ---------------------------------------------------------------------------
 // storage loads (FP32 or FP16 grids, FP32 math)
 // ---------------------------------------------------------------------------

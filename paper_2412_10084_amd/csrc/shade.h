@@ -16,13 +16,6 @@ namespace psdf {
 constexpr int BLOCK = 256;
 constexpr int WAVES = BLOCK / 64;
 
-// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
-// (and its L2) works on one contiguous range of rays.
-__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned G) {
-  const unsigned x = b & 7u, j = b >> 3, q = G >> 3, r = G & 7u;
-  return x * q + (x < r ? x : r) + j;
-}
-
 // ---------------------------------------------------------------------------
 // ray setup in FP64: unit direction, ray / cube interval, sample spacing
 // ---------------------------------------------------------------------------

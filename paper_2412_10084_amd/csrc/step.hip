@@ -58,7 +58,9 @@ __device__ __forceinline__ float eik_q(const float* __restrict__ s, int R, int R
 
 __global__ void __launch_bounds__(SBLOCK) step_sdf_kernel(StepArgs a) {
   const int R = a.R, RR = R * R;
-  const int i = blockIdx.x * SBLOCK + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  unsigned bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int i = bx * SBLOCK + threadIdx.x, j = by, k = bz;
   const bool valid = i < R;
   const float inv2h = 0.5f / a.h;
   const float M = (float)(R - 2) * (float)(R - 2) * (float)(R - 2);
@@ -111,7 +113,9 @@ struct TvArgs {
 template <int C>  // channels per node; one float per thread
 __global__ void __launch_bounds__(SBLOCK) step_tv_kernel(TvArgs t, StepArgs a) {
   const int R = t.R, rowlen = R * C;
-  const int xi = blockIdx.x * SBLOCK + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  unsigned bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int xi = bx * SBLOCK + threadIdx.x, j = by, k = bz;
   const bool valid = xi < rowlen;
   const float npairs = 3.0f * (float)R * (float)R * (float)(R - 1);
   const float scale = t.lambda / (npairs * (float)C);
@@ -153,7 +157,9 @@ template <int C>
 __global__ void __launch_bounds__(SBLOCK) step_tv4_kernel(TvArgs t, StepArgs a) {
   static_assert(C % 4 == 0, "vector path needs C % 4 == 0");
   const int R = t.R, rowlen = R * C;
-  const int xi = (blockIdx.x * SBLOCK + threadIdx.x) * 4, j = blockIdx.y, k = blockIdx.z;
+  unsigned bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int xi = (bx * SBLOCK + threadIdx.x) * 4, j = by, k = bz;
   const bool valid = xi < rowlen;
   const float npairs = 3.0f * (float)R * (float)R * (float)(R - 1);
   const float scale = t.lambda / (npairs * (float)C);
@@ -220,7 +226,9 @@ __global__ void zero3_kernel(float* p) {
 // any channel count: one float per thread, runtime division
 __global__ void __launch_bounds__(SBLOCK) step_tv_any_kernel(TvArgs t, int C, StepArgs a) {
   const int R = t.R, rowlen = R * C;
-  const int xi = blockIdx.x * SBLOCK + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  unsigned bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int xi = bx * SBLOCK + threadIdx.x, j = by, k = bz;
   const bool valid = xi < rowlen;
   const float npairs = 3.0f * (float)R * (float)R * (float)(R - 1);
   const float scale = t.lambda / (npairs * (float)C);
