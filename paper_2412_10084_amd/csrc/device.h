@@ -107,6 +107,26 @@ __device__ __forceinline__ float2 ld2(const _Float16* __restrict__ p, int i) {
   return make_float2((float)h[0], (float)h[1]);
 }
 
+// The four corner pairs of a cell, fetched ahead of their use (software
+// pipelining of the march).
+struct CellVals {
+  float2 p00, p10, p01, p11;
+  float fx, fy, fz;
+};
+
+template <typename T>
+__device__ __forceinline__ CellVals fetch_cell(const T* __restrict__ g, int R, const Cell& c) {
+  const int b = c.base, RR = R * R;
+  return CellVals{ld2(g, b), ld2(g, b + R), ld2(g, b + RR), ld2(g, b + RR + R), c.fx, c.fy, c.fz};
+}
+
+__device__ __forceinline__ float interp_cell(const CellVals& v) {
+  const float a0 = lerpf(v.p00.x, v.p00.y, v.fx), a1 = lerpf(v.p10.x, v.p10.y, v.fx);
+  const float a2 = lerpf(v.p01.x, v.p01.y, v.fx), a3 = lerpf(v.p11.x, v.p11.y, v.fx);
+  const float b0 = lerpf(a0, a1, v.fy), b1 = lerpf(a2, a3, v.fy);
+  return lerpf(b0, b1, v.fz);
+}
+
 // Scalar trilinear value; x-adjacent corners are neighbours in memory and are
 // fetched as pairs (the cell's k0x <= R-2, so b + 1 stays inside the row).
 template <typename T>

@@ -244,12 +244,21 @@ __global__ void __launch_bounds__(BLOCK) render_bwd_kernel(RenderArgs a) {
   MarchU mu;
   march_init(r, G.inv_h, mu);
   float s_cur = hit ? tri1(sdf, a.R, march_cell(mu, a.R)) : 0.f;
+  // software pipelining: the corners of sample i+1 are in flight while sample i
+  // is processed
+  march_step(mu);
+  CellVals nxt{};
+  if (hit) nxt = fetch_cell(sdf, a.R, march_cell(mu, a.R));
   float l_cur = log_sigmoid(a.tau * s_cur);
   for (int i = 0;; ++i) {
     const bool stepping = i < a.N - 1;  // wave-uniform
     if (stepping) {
-      march_step(mu);
-      const float s_nx = hit ? tri1(sdf, a.R, march_cell(mu, a.R)) : 0.f;
+      const CellVals cur = nxt;
+      if (hit && i + 2 < a.N) {
+        march_step(mu);
+        nxt = fetch_cell(sdf, a.R, march_cell(mu, a.R));
+      }
+      const float s_nx = hit ? interp_cell(cur) : 0.f;
       const float l_nx = log_sigmoid(a.tau * s_nx);
       const bool active = hit && (a.skip_thr <= 0.f || fabsf(s_cur) <= a.skip_thr);
       const float dl = l_nx - l_cur;

@@ -207,6 +207,70 @@ __global__ void __launch_bounds__(SBLOCK) step_tv4_kernel(TvArgs t, StepArgs a) 
   if (t.loss_dst) block_add(loss * scale, t.loss_dst);
 }
 
+// three channels per node, four consecutive floats per thread (R % 4 == 0, so a
+// row of 3R floats is whole float4s): the x-neighbours of element k are k -/+ 3
+// floats away and come from the previous / current / next float4 of the row.
+__global__ void __launch_bounds__(SBLOCK) step_tv3v_kernel(TvArgs t, StepArgs a) {
+  constexpr int C = 3;
+  const int R = t.R, rowlen = R * C;
+  unsigned bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int xi = (bx * SBLOCK + threadIdx.x) * 4, j = by, k = bz;
+  const bool valid = xi < rowlen;
+  const float npairs = 3.0f * (float)R * (float)R * (float)(R - 1);
+  const float scale = t.lambda / (npairs * (float)C);
+  float loss = 0.f;
+  if (valid) {
+    const int e = (k * R + j) * rowlen + xi;
+    const int sy = rowlen, sz = R * rowlen;
+    const float* __restrict__ F = t.F_in;
+    const float4 f4v = ld4g(F, e);
+    const float4 pv = xi >= 4 ? ld4g(F, e - 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 nv = xi + 8 <= rowlen ? ld4g(F, e + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float f[4] = {f4v.x, f4v.y, f4v.z, f4v.w};
+    const float xm[4] = {pv.y, pv.z, pv.w, f4v.x};  // element q - 3
+    const float xp[4] = {f4v.w, nv.x, nv.y, nv.z};  // element q + 3
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = (xi + q) / C;
+      if (i > 0) acc[q] += f[q] - xm[q];
+      if (i < R - 1) { const float d = xp[q] - f[q]; acc[q] -= d; loss += d * d; }
+    }
+    auto yz = [&](int off, bool back, bool fwd) {
+      if (back) {
+        const float4 b = ld4g(F, e - off);
+        acc[0] += f[0] - b.x; acc[1] += f[1] - b.y; acc[2] += f[2] - b.z; acc[3] += f[3] - b.w;
+      }
+      if (fwd) {
+        const float4 b = ld4g(F, e + off);
+        const float d0 = b.x - f[0], d1 = b.y - f[1], d2 = b.z - f[2], d3 = b.w - f[3];
+        acc[0] -= d0; acc[1] -= d1; acc[2] -= d2; acc[3] -= d3;
+        loss += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+      }
+    };
+    yz(sy, j > 0, j < R - 1);
+    yz(sz, k > 0, k < R - 1);
+    const float4 g = ld4g(t.g, e);
+    float4 m = ld4g(t.m, e), v = ld4g(t.v, e);
+    const float s2 = 2.0f * scale;
+    float4 p;
+    p.x = adam_update(f[0], g.x + s2 * acc[0], m.x, v.x, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.y = adam_update(f[1], g.y + s2 * acc[1], m.y, v.y, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.z = adam_update(f[2], g.z + s2 * acc[2], m.z, v.z, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.w = adam_update(f[3], g.w + s2 * acc[3], m.w, v.w, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    st4g(t.F_out, e, p);
+    st4g(t.m, e, m);
+    st4g(t.v, e, v);
+    st4g(t.g, e, make_float4(0.f, 0.f, 0.f, 0.f));
+    if (t.half_out) {
+      h4 hv = {(_Float16)p.x, (_Float16)p.y, (_Float16)p.z, (_Float16)p.w};
+      *reinterpret_cast<h4*>(t.half_out + e) = hv;
+    }
+  }
+  if (t.loss_dst) block_add(loss * scale, t.loss_dst);
+}
+
 __global__ void __launch_bounds__(SBLOCK) step_mlp_kernel(StepArgs a) {
   const int e = blockIdx.x * SBLOCK + threadIdx.x;
   if (e < a.n_mlp) {
@@ -269,6 +333,11 @@ static void launch_tv(const TvArgs& t, int C, const StepArgs& a, hipStream_t s) 
       case 36: hipLaunchKernelGGL(step_tv4_kernel<36>, grid, dim3(SBLOCK), 0, s, t, a); break;
       default: hipLaunchKernelGGL(step_tv4_kernel<64>, grid, dim3(SBLOCK), 0, s, t, a); break;
     }
+    return;
+  }
+  if (C == 3 && R % 4 == 0) {
+    const dim3 grid4((rowlen / 4 + SBLOCK - 1) / SBLOCK, R, R);
+    hipLaunchKernelGGL(step_tv3v_kernel, grid4, dim3(SBLOCK), 0, s, t, a);
     return;
   }
   const dim3 grid((rowlen + SBLOCK - 1) / SBLOCK, R, R);
