@@ -82,6 +82,8 @@ def make_state(torch, ps, wl, w, feat_half=False, mlp_dtype=0, seed=0, order="im
     st["aux"] = torch.empty((B, 4), device="cuda")
     st["dL"] = torch.empty((B, 3), device="cuda")
     st["loss"] = torch.empty(1, device="cuda")
+    # brick bounds of the initial SDF; every grid step writes those of the next one
+    st["bounds"] = ps.sdf_bounds(master["sdf"])
     # target image: the torus field rendered by the same forward kernel
     tfield = ps.Field(cu(ft.sdf), cu(ft.feat), cu(ft.probes), cu(ft.mlp))
     st["target"] = torch.empty((B, 3), device="cuda")
@@ -95,9 +97,10 @@ def make_state(torch, ps, wl, w, feat_half=False, mlp_dtype=0, seed=0, order="im
 def train_step(ps, w, st, step, timer):
     p = st["master"]
     if st["half"]:
-        fld = ps.Field(p["sdf"], st["half"]["feat"], st["half"]["probes"], p["mlp"], st["mlp_dtype"])
+        fld = ps.Field(p["sdf"], st["half"]["feat"], st["half"]["probes"], p["mlp"], st["mlp_dtype"],
+                       st["bounds"])
     else:
-        fld = ps.Field(p["sdf"], p["feat"], p["probes"], p["mlp"], st["mlp_dtype"])
+        fld = ps.Field(p["sdf"], p["feat"], p["probes"], p["mlp"], st["mlp_dtype"], st["bounds"])
     opts = ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels)
     timer.run("render_forward", lambda: ps.render_forward(fld, opts, st["o"], st["d"], st["rgb"],
                                                            st["aux"]))
@@ -106,7 +109,8 @@ def train_step(ps, w, st, step, timer):
                                                              st["dL"], st["grads"]))
     out = dict(st["spare"], mlp=p["mlp"])
     timer.run("grid_step", lambda: ps.grid_step(p, out, st["grads"], st["m"], st["v"], step,
-                                                ps.StepOpts(), half_out=st["half"] or None))
+                                                ps.StepOpts(), half_out=st["half"] or None,
+                                                bounds_out=st["bounds"]))
     # ping-pong the grids (the step is out of place)
     st["spare"] = {k: p[k] for k in ("sdf", "feat", "probes")}
     st["master"] = dict(sdf=out["sdf"], feat=out["feat"], probes=out["probes"], mlp=p["mlp"])
@@ -256,6 +260,7 @@ def time_iter512(torch, ps, wl, iters, warmup):
         st[k] = torch.empty((B, 3), device="cuda")
     st["aux"] = torch.empty((B, 4), device="cuda")
     st["loss"] = torch.empty(1, device="cuda")
+    st["bounds"] = ps.sdf_bounds(f0.sdf)
     tf = gpu_field(torch, ps, wl, w, 1, shape="torus")
     ps.render_forward(tf, ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels), st["o"], st["d"],
                       st["target"])
@@ -281,7 +286,7 @@ TRAFFIC_KERNELS = {
     "render_backward": ("void psdf::render_bwd_kernel<float, float, 9, 0>",),
     "render_forward": ("void psdf::render_fwd_kernel<float, float, 9, 0>",),
     "grid_step": ("psdf::step_sdf_kernel", "void psdf::step_tv_kernel<3>", "void psdf::step_tv4_kernel<36>",
-                  "psdf::step_mlp_kernel"),
+                  "psdf::step_mlp_kernel", "void psdf::sdf_bounds_kernel<float>"),
 }
 
 

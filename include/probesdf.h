@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define PSDF_ABI_VERSION 1
+#define PSDF_ABI_VERSION 2
 
 #define PSDF_OK 0
 #define PSDF_EINVAL (-1)       /* null pointer, bad size or shape, aliasing */
@@ -84,8 +84,22 @@ typedef enum { PSDF_F32 = 0, PSDF_F16 = 1, PSDF_BF16 = 2 } psdf_dtype;
  * mlp_dtype F32 | F16 | BF16 (the precision the MLP computes in; weights are
  * always passed FP32 and rounded to nearest-even on use).
  * Alignment: sdf, feat 4 bytes (2 for FP16); probes 16 bytes (8 for FP16);
- * mlp 4 bytes.
+ * mlp 4 bytes; sdf_bounds 8 bytes.
+ *
+ * sdf_bounds (nullable) enables empty-space skipping of the march: FP32
+ * [nb][nb][nb][2] with nb = PSDF_BRICKS(R), x fastest; entry (bx, by, bz)
+ * holds the min and max of the sdf nodes [8b, min(8b + 8, R - 1)] on each
+ * axis, i.e. of every node that the cells [8b, 8b + 7] interpolate.  A sample
+ * whose brick has min > thr or max < -thr (thr = skip_voxels * h, widened by a
+ * 1e-6 relative margin that covers FP32 interpolation rounding) cannot pass the
+ * skip rule, so its corners are not read.  Results are identical with and
+ * without bounds.  They must describe exactly the sdf array they travel with
+ * (as read, i.e. after FP16 rounding): write them with psdf_sdf_bounds or with
+ * psdf_grid_step's sdf_bounds_out; stale bounds give wrong images.
  */
+#define PSDF_BRICK 8
+#define PSDF_BRICKS(R) (((R) - 2) / PSDF_BRICK + 1)
+
 typedef struct psdf_field {
   uint32_t struct_size; /* sizeof(psdf_field) */
   int32_t R;
@@ -101,6 +115,7 @@ typedef struct psdf_field {
   const void* feat;
   const void* probes;
   const float* mlp;
+  const float* sdf_bounds; /* nullable, see above */
 } psdf_field;
 
 typedef struct psdf_render_opts {
@@ -173,7 +188,9 @@ int psdf_l1_loss(int64_t B, const float* rgb, const float* target, float* dL_drg
  * Optional FP16 render copies (round to nearest even) of the new sdf, feat
  * and probes are written when their pointers are non-NULL.  `losses` [3]
  * (nullable, device) receives (L_eik, L_feat, L_probe) of the input
- * parameters.
+ * parameters.  `sdf_bounds_out` (nullable, [PSDF_BRICKS(R)^3][2], 8-byte
+ * aligned) receives the brick bounds of the new sdf as the renderer will read
+ * it: of the FP16 copy when sdf_half_out is set, else of sdf_out.
  */
 typedef struct psdf_step_args {
   uint32_t struct_size; /* sizeof(psdf_step_args) */
@@ -206,9 +223,20 @@ typedef struct psdf_step_args {
   void* feat_half_out;
   void* probes_half_out;
   float* losses;         /* nullable [3] */
+  float* sdf_bounds_out; /* nullable */
 } psdf_step_args;
 
 int psdf_grid_step(const psdf_step_args* args, void* stream);
+
+/*
+ * psdf_sdf_bounds -- brick bounds of an sdf grid for psdf_field.sdf_bounds (an
+ * acceleration structure for the skip rule of Sec. 3.3; not part of the model).
+ *   sdf     [R][R][R] FP32 or FP16 (sdf_dtype), 2 <= R <= 1024
+ *   bounds  [PSDF_BRICKS(R)^3][2] FP32 out, 8-byte aligned
+ * NaN nodes are ignored (an all-NaN brick gets min = +inf, max = -inf, so its
+ * samples are skipped, as the skip rule leaves a NaN sample inactive).
+ */
+int psdf_sdf_bounds(int32_t R, int32_t sdf_dtype, const void* sdf, float* bounds, void* stream);
 
 /*
  * psdf_render_sphere_trace -- inference render of V pinhole views.  The paper

@@ -18,12 +18,14 @@ LIB_PATH = os.path.join(HERE, "libprobesdf.so")
 F32, F16, BF16 = 0, 1, 2
 FLAG_NO_FS, FLAG_NO_FA, FLAG_NV_ONE = 1, 2, 4
 OK, EINVAL, EALIGN, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
-ABI_VERSION = 1
+ABI_VERSION = 2
+BRICK = 8
 
 N_FEAT, N_ANG, HIDDEN, N_MLP = 3, 4, 16, 227
 
 EXPORTS = ("psdf_render_forward", "psdf_render_backward", "psdf_l1_loss", "psdf_grid_step",
-           "psdf_render_sphere_trace", "psdf_last_error", "psdf_abi_version")
+           "psdf_render_sphere_trace", "psdf_sdf_bounds", "psdf_last_error",
+           "psdf_abi_version")
 
 
 class PsdfError(RuntimeError):
@@ -37,7 +39,7 @@ class _Field(C.Structure):
                 ("n_feat", C.c_int32), ("sh_coeffs", C.c_int32), ("n_ang", C.c_int32),
                 ("mlp_hidden", C.c_int32), ("sdf_dtype", C.c_int32), ("feat_dtype", C.c_int32),
                 ("mlp_dtype", C.c_int32), ("sdf", C.c_void_p), ("feat", C.c_void_p),
-                ("probes", C.c_void_p), ("mlp", C.c_void_p)]
+                ("probes", C.c_void_p), ("mlp", C.c_void_p), ("sdf_bounds", C.c_void_p)]
 
 
 class _RenderOpts(C.Structure):
@@ -62,7 +64,7 @@ class _StepArgs(C.Structure):
             "sdf_in", "sdf_out", "feat_in", "feat_out", "probes_in", "probes_out", "mlp",
             "g_sdf", "g_feat", "g_probes", "g_mlp", "m_sdf", "v_sdf", "m_feat", "v_feat",
             "m_probes", "v_probes", "m_mlp", "v_mlp", "sdf_half_out", "feat_half_out",
-            "probes_half_out", "losses")]
+            "probes_half_out", "losses", "sdf_bounds_out")]
 
 
 class _TraceOpts(C.Structure):
@@ -87,6 +89,7 @@ def lib():
         L.psdf_l1_loss.argtypes = [i64, vp, vp, vp, vp, vp]
         L.psdf_grid_step.argtypes = [vp, vp]
         L.psdf_render_sphere_trace.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp]
+        L.psdf_sdf_bounds.argtypes = [i32, i32, vp, vp, vp]
         L.psdf_last_error.restype = C.c_char_p
         L.psdf_last_error.argtypes = []
         L.psdf_abi_version.restype = C.c_int
@@ -129,12 +132,15 @@ def _stream(stream):
 @dataclass
 class Field:
     """Device tensors of one scene.  sdf (R,R,R) f32|f16; feat (R,R,R,3) f32|f16;
-    probes (P,P,P,sh,4) same dtype as feat; mlp (227,) f32."""
+    probes (P,P,P,sh,4) same dtype as feat; mlp (227,) f32; bounds: optional brick
+    bounds of exactly this sdf (sdf_bounds() or grid_step(bounds_out=...)) that let
+    the march skip samples the skip rule leaves inactive."""
     sdf: object
     feat: object
     probes: object
     mlp: object
     mlp_dtype: int = F32
+    bounds: object = None
 
     @staticmethod
     def _dt(t) -> int:
@@ -147,7 +153,8 @@ class Field:
         sh = self.probes.shape[3]
         return _Field(C.sizeof(_Field), R, P, self.feat.shape[-1], sh, self.probes.shape[-1],
                       HIDDEN, self._dt(self.sdf), self._dt(self.feat), self.mlp_dtype,
-                      _ptr(self.sdf), _ptr(self.feat), _ptr(self.probes), _ptr(self.mlp))
+                      _ptr(self.sdf), _ptr(self.feat), _ptr(self.probes), _ptr(self.mlp),
+                      _ptr(self.bounds))
 
 
 @dataclass
@@ -202,10 +209,29 @@ def l1_loss(rgb, target, dL_drgb, loss=None, stream=None) -> None:
                               _stream(stream)))
 
 
+def n_bricks(R: int) -> int:
+    """Bricks per axis of the sdf bounds of an R^3 grid."""
+    return (R - 2) // BRICK + 1
+
+
+def sdf_bounds(sdf, out=None, stream=None):
+    """Brick bounds (nb, nb, nb, 2) FP32 of an (R, R, R) sdf tensor; returns `out`."""
+    import torch
+    R = sdf.shape[0]
+    if out is None:
+        nb = n_bricks(R)
+        out = torch.empty((nb, nb, nb, 2), device=sdf.device, dtype=torch.float32)
+    dt = Field._dt(sdf)
+    _check(lib().psdf_sdf_bounds(R, dt, _ptr(sdf), _ptr(out), _stream(stream)))
+    return out
+
+
 def grid_step(params_in: dict, params_out: dict, grads: dict, m: dict, v: dict, step: int,
-              opts: StepOpts, half_out: Optional[dict] = None, losses=None, stream=None) -> None:
+              opts: StepOpts, half_out: Optional[dict] = None, losses=None, stream=None,
+              bounds_out=None) -> None:
     """params_*: dict sdf, feat, probes (grids, out of place) and mlp (in place, taken from
-    params_in); grads/m/v: dicts with the same keys; half_out: optional FP16 copies."""
+    params_in); grads/m/v: dicts with the same keys; half_out: optional FP16 copies;
+    bounds_out: optional brick bounds of the new sdf (of its FP16 copy when given)."""
     half_out = half_out or {}
     R = params_in["sdf"].shape[0]
     P = params_in["probes"].shape[0]
@@ -220,7 +246,8 @@ def grid_step(params_in: dict, params_out: dict, grads: dict, m: dict, v: dict, 
                   _ptr(grads["probes"]), _ptr(grads["mlp"]), _ptr(m["sdf"]), _ptr(v["sdf"]),
                   _ptr(m["feat"]), _ptr(v["feat"]), _ptr(m["probes"]), _ptr(v["probes"]),
                   _ptr(m["mlp"]), _ptr(v["mlp"]), _ptr(half_out.get("sdf")),
-                  _ptr(half_out.get("feat")), _ptr(half_out.get("probes")), _ptr(losses))
+                  _ptr(half_out.get("feat")), _ptr(half_out.get("probes")), _ptr(losses),
+                  _ptr(bounds_out))
     _check(lib().psdf_grid_step(C.byref(a), _stream(stream)))
 
 
@@ -240,7 +267,7 @@ def render(field: Field, opts: RenderOpts, rays_o, rays_d):
     field.feat, field.probes and field.mlp (FP32 tensors) through the HIP
     backward kernel."""
     return _RenderFn.apply(field.sdf, field.feat, field.probes, field.mlp, field.mlp_dtype, opts,
-                           rays_o, rays_d)
+                           rays_o, rays_d, field.bounds)
 
 
 def _make_autograd():
@@ -248,20 +275,21 @@ def _make_autograd():
 
     class RenderFn(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, sdf, feat, probes, mlp, mlp_dtype, opts, rays_o, rays_d):
+        def forward(ctx, sdf, feat, probes, mlp, mlp_dtype, opts, rays_o, rays_d, bounds):
             B = rays_o.shape[0]
             rgb = torch.empty((B, 3), device=rays_o.device, dtype=torch.float32)
             aux = torch.empty((B, 4), device=rays_o.device, dtype=torch.float32)
-            fld = Field(sdf, feat, probes, mlp, mlp_dtype)
+            fld = Field(sdf, feat, probes, mlp, mlp_dtype, bounds)
             render_forward(fld, opts, rays_o, rays_d, rgb, aux)
             ctx.save_for_backward(sdf, feat, probes, mlp, rays_o, rays_d, aux)
+            ctx.bounds = bounds
             ctx.mlp_dtype, ctx.opts = mlp_dtype, opts
             return rgb
 
         @staticmethod
         def backward(ctx, g_rgb):
             sdf, feat, probes, mlp, rays_o, rays_d, aux = ctx.saved_tensors
-            fld = Field(sdf, feat, probes, mlp, ctx.mlp_dtype)
+            fld = Field(sdf, feat, probes, mlp, ctx.mlp_dtype, ctx.bounds)
             gs = torch.zeros(sdf.shape, device=sdf.device, dtype=torch.float32)
             gf = torch.zeros(feat.shape, device=sdf.device, dtype=torch.float32)
             gp = torch.zeros(probes.shape, device=sdf.device, dtype=torch.float32)
@@ -269,7 +297,7 @@ def _make_autograd():
             render_backward(fld, ctx.opts, rays_o, rays_d, aux, g_rgb.contiguous(),
                             dict(sdf=gs, feat=gf, probes=gp, mlp=gm))
             return (gs.to(sdf.dtype), gf.to(feat.dtype), gp.to(probes.dtype), gm, None, None,
-                    None, None)
+                    None, None, None)
 
     return RenderFn
 

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libprobesdf.so")
 
-SOURCES = ["abi.cpp", "render_fwd.hip", "render_bwd.hip", "trace.hip", "loss.hip", "step.hip"]
+SOURCES = ["abi.cpp", "render_fwd.hip", "render_bwd.hip", "trace.hip", "loss.hip", "step.hip",
+           "bounds.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

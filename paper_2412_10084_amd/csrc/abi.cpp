@@ -60,6 +60,8 @@ int check_field(const psdf_field* f) {
     return fail(PSDF_EALIGN, "sdf/feat/mlp misaligned");
   if (!aligned(f->probes, f->feat_dtype == PSDF_F32 ? 16 : 8))
     return fail(PSDF_EALIGN, "probes must be %d-byte aligned", f->feat_dtype == PSDF_F32 ? 16 : 8);
+  if (f->sdf_bounds && !aligned(f->sdf_bounds, 8))
+    return fail(PSDF_EALIGN, "sdf_bounds must be 8-byte aligned");
   return PSDF_OK;
 }
 
@@ -101,6 +103,7 @@ psdf::RenderArgs render_args(const psdf_field* f, const psdf_render_opts* o, int
   a.feat = f->feat;
   a.probes = f->probes;
   a.mlp = f->mlp;
+  a.bounds = f->sdf_bounds;
   a.N = o->n_samples;
   a.tau = o->tau;
   a.skip_thr = o->skip_voxels > 0.f ? (float)(o->skip_voxels * (2.0 / (f->R - 1))) : 0.f;
@@ -220,6 +223,8 @@ int psdf_grid_step(const psdf_step_args* s, void* stream) {
   for (const void* p : halves)
     if (p && !aligned(p, 8)) return fail(PSDF_EALIGN, "FP16 copies must be 8-byte aligned");
   if (s->losses && !aligned(s->losses, 4)) return fail(PSDF_EALIGN, "losses misaligned");
+  if (s->sdf_bounds_out && !aligned(s->sdf_bounds_out, 8))
+    return fail(PSDF_EALIGN, "sdf_bounds_out must be 8-byte aligned");
 
   psdf::StepArgs a{};
   a.R = s->R;
@@ -263,8 +268,21 @@ int psdf_grid_step(const psdf_step_args* s, void* stream) {
   a.feat_half = s->feat_half_out;
   a.probes_half = s->probes_half_out;
   a.losses = s->losses;
+  a.sdf_bounds = s->sdf_bounds_out;
   return hip_status(psdf::launch_grid_step(a, static_cast<hipStream_t>(stream)),
                     "grid_step launch");
+}
+
+int psdf_sdf_bounds(int32_t R, int32_t sdf_dtype, const void* sdf, float* bounds, void* stream) {
+  if (R < 2 || R > 1024) return fail(PSDF_EINVAL, "R=%d outside [2, 1024]", R);
+  if (sdf_dtype != PSDF_F32 && sdf_dtype != PSDF_F16)
+    return fail(PSDF_EUNSUPPORTED, "sdf_dtype %d", sdf_dtype);
+  if (!sdf || !bounds) return fail(PSDF_EINVAL, "sdf/bounds is NULL");
+  if (!aligned(sdf, dt_size(sdf_dtype)) || !aligned(bounds, 8))
+    return fail(PSDF_EALIGN, "sdf/bounds misaligned");
+  return hip_status(psdf::launch_sdf_bounds(sdf, R, sdf_dtype, bounds,
+                                            static_cast<hipStream_t>(stream)),
+                    "sdf_bounds launch");
 }
 
 int psdf_render_sphere_trace(const psdf_field* field, const psdf_trace_opts* opts, int32_t V,

@@ -17,6 +17,7 @@ struct RenderArgs {
   const void* feat;
   const void* probes;
   const float* mlp;
+  const float* bounds;  // brick bounds of sdf, nullable
   // options
   int N;
   float tau;
@@ -80,6 +81,7 @@ struct StepArgs {
   void* feat_half;
   void* probes_half;
   float* losses;
+  float* sdf_bounds;  // brick bounds of the new sdf (of sdf_half when set), nullable
 };
 
 // dtype codes as in the public header
@@ -92,5 +94,6 @@ hipError_t launch_sphere_trace(const TraceArgs& a, int sdf_dt, int feat_dt, int 
 hipError_t launch_l1_loss(int64_t B, const float* rgb, const float* target, float* dL,
                           float* loss, hipStream_t s);
 hipError_t launch_grid_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_sdf_bounds(const void* sdf, int R, int sdf_dt, float* bounds, hipStream_t s);
 
 }  // namespace psdf

@@ -241,28 +241,22 @@ __global__ void __launch_bounds__(BLOCK) render_bwd_kernel(RenderArgs a) {
   float logT = 0.f;
   int my_first = 0, my_last = 0, my_cnt = 0;
   int head = 0, tail = 0;
-  MarchU mu;
-  march_init(r, G.inv_h, mu);
-  float s_cur = hit ? tri1(sdf, a.R, march_cell(mu, a.R)) : 0.f;
-  // software pipelining: the corners of sample i+1 are in flight while sample i
-  // is processed
-  march_step(mu);
-  CellVals nxt{};
-  if (hit) nxt = fetch_cell(sdf, a.R, march_cell(mu, a.R));
-  float l_cur = log_sigmoid(a.tau * s_cur);
+  const Bricks K = make_bricks(a.bounds, a.R, a.skip_thr);
+  MarchState ms;
+  march_begin(sdf, a.R, K, r, G.inv_h, hit, a.N, ms);
   for (int i = 0;; ++i) {
     const bool stepping = i < a.N - 1;  // wave-uniform
     if (stepping) {
-      const CellVals cur = nxt;
-      if (hit && i + 2 < a.N) {
-        march_step(mu);
-        nxt = fetch_cell(sdf, a.R, march_cell(mu, a.R));
+      float s_i, s_n;
+      bool may;
+      march_next(sdf, a.R, K, hit, i, a.N, ms, s_i, s_n, may);
+      const bool active = may && (a.skip_thr <= 0.f || fabsf(s_i) <= a.skip_thr);
+      bool shaded = false;
+      float dl = 0.f;
+      if (active) {
+        dl = log_sigmoid(a.tau * s_n) - log_sigmoid(a.tau * s_i);
+        shaded = dl < 0.f;
       }
-      const float s_nx = hit ? interp_cell(cur) : 0.f;
-      const float l_nx = log_sigmoid(a.tau * s_nx);
-      const bool active = hit && (a.skip_thr <= 0.f || fabsf(s_cur) <= a.skip_thr);
-      const float dl = l_nx - l_cur;
-      const bool shaded = active && dl < 0.f;
       const uint64_t mask = __ballot(shaded);
       if (shaded) {
         const float T = expf(logT);
@@ -271,8 +265,8 @@ __global__ void __launch_bounds__(BLOCK) render_bwd_kernel(RenderArgs a) {
         L.key[slot] = (i << 6) | lane;
         L.w[slot] = T * -expm1f(dl);
         L.T[slot] = T;
-        L.s0[slot] = s_cur;
-        L.s1[slot] = s_nx;
+        L.s0[slot] = s_i;
+        L.s1[slot] = s_n;
         if (my_cnt > 0) L.next[my_last & (RING - 1)] = seq;
         else my_first = seq;
         my_last = seq;
@@ -280,8 +274,6 @@ __global__ void __launch_bounds__(BLOCK) render_bwd_kernel(RenderArgs a) {
         logT += dl;
       }
       tail += __popcll(mask);
-      s_cur = s_nx;
-      l_cur = l_nx;
     }
     const int pending = tail - head;
     if (pending >= 64 || (!stepping && pending > 0)) {

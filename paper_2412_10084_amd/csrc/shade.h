@@ -99,6 +99,133 @@ __device__ __forceinline__ void march_step(MarchU& m) {
   for (int k = 0; k < 3; ++k) m.u[k] += m.du[k];
 }
 
+// ---------------------------------------------------------------------------
+// Empty-space skipping.  Brick bounds hold, per block of 8^3 cells, the min and
+// max of the SDF nodes those cells interpolate.  A trilinear value is a convex
+// combination of its corners, so a sample whose brick has min > thr or
+// max < -thr cannot pass the skip rule |s| <= thr; its corners are not read
+// unless the previous sample is active and needs s_{i+1} for its opacity.
+// The FP32 interpolation stays within 9 ulp of max |corner| of the convex
+// value, which the 1e-6 relative margin covers, so skipping never changes a
+// result.
+// ---------------------------------------------------------------------------
+constexpr int BRICK_SHIFT = 3;
+
+struct Bricks {
+  const float2* __restrict__ b;  // [nb][nb][nb] (min, max); nullptr: no skipping
+  int nb;
+  float thr;
+};
+
+__device__ __forceinline__ Bricks make_bricks(const float* bounds, int R, float skip_thr) {
+  Bricks k;
+  k.b = skip_thr > 0.f ? reinterpret_cast<const float2*>(bounds) : nullptr;
+  k.nb = ((R - 2) >> BRICK_SHIFT) + 1;
+  k.thr = skip_thr;
+  return k;
+}
+
+// cell of the march coordinate and the flat index of its brick
+__device__ __forceinline__ Cell march_cell_b(const MarchU& m, int R, int nb, int& brick) {
+  Cell c;
+  int k[3];
+  float f[3];
+  const double umax = (double)(R - 1), kmax = (double)(R - 2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = fmin(fmax(m.u[a], 0.0), umax);
+    const double fl = fmin(floor(u), kmax);
+    k[a] = (int)fl;
+    f[a] = (float)(u - fl);
+  }
+  c.fx = f[0];
+  c.fy = f[1];
+  c.fz = f[2];
+  c.base = (k[2] * R + k[1]) * R + k[0];
+  brick = ((k[2] >> BRICK_SHIFT) * nb + (k[1] >> BRICK_SHIFT)) * nb + (k[0] >> BRICK_SHIFT);
+  return c;
+}
+
+__device__ __forceinline__ float2 brick_load(const Bricks& K, bool on, int brick) {
+  if (!K.b) return make_float2(0.f, 0.f);
+  return K.b[on ? brick : 0];
+}
+
+// may a sample in a brick with these bounds pass the skip rule
+__device__ __forceinline__ bool brick_may(const Bricks& K, float2 mm) {
+  if (!K.b) return true;
+  const float t = K.thr + 1e-6f * fmaxf(fabsf(mm.x), fabsf(mm.y));
+  return mm.x <= t && mm.y >= -t;
+}
+
+// corners of a cell when `need`, else of node 0 (one shared line, value unused)
+template <typename T>
+__device__ __forceinline__ CellVals fetch_cell_if(const T* __restrict__ g, int R, const Cell& c,
+                                                  bool need) {
+  Cell q = c;
+  q.base = need ? c.base : 0;
+  return fetch_cell(g, R, q);
+}
+
+// March of one ray per lane over samples i = 0 .. N-1 with loads in flight
+// ahead of use: the bounds of sample i+2 and the corners of sample i+1.
+//   s0 = s_i (valid when m0), v1 = corners of sample i+1 (fetched when m0 || m1)
+struct MarchState {
+  MarchU mu;
+  Cell c2;
+  int k2;
+  float2 b2;
+  CellVals v1;
+  float s0;
+  bool m0, m1;
+};
+
+template <typename ST>
+__device__ __forceinline__ void march_begin(const ST* __restrict__ sdf, int R, const Bricks& K,
+                                            const RayD& r, double inv_h, bool hit, int N,
+                                            MarchState& M) {
+  march_init(r, inv_h, M.mu);
+  int k0, k1;
+  const Cell c0 = march_cell_b(M.mu, R, K.nb, k0);
+  march_step(M.mu);
+  const Cell c1 = march_cell_b(M.mu, R, K.nb, k1);
+  const float2 b0 = brick_load(K, hit, k0), b1 = brick_load(K, hit, k1);
+  march_step(M.mu);
+  M.c2 = march_cell_b(M.mu, R, K.nb, M.k2);
+  M.b2 = brick_load(K, hit && N > 2, M.k2);
+  M.m0 = hit && brick_may(K, b0);
+  M.m1 = hit && N > 1 && brick_may(K, b1);
+  Cell q0 = c0;
+  q0.base = M.m0 ? c0.base : 0;
+  M.s0 = tri1(sdf, R, q0);
+  M.v1 = fetch_cell_if(sdf, R, c1, M.m0 || M.m1);
+}
+
+// Step i (0 <= i < N-1): returns s_i, s_{i+1} and whether sample i may be
+// active, and moves the state to sample i+1.
+template <typename ST>
+__device__ __forceinline__ void march_next(const ST* __restrict__ sdf, int R, const Bricks& K,
+                                           bool hit, int i, int N, MarchState& M, float& s_i,
+                                           float& s_n, bool& may_i) {
+  const CellVals cur = M.v1;
+  bool m2 = false;
+  if (i + 2 < N) {  // wave-uniform
+    m2 = hit && brick_may(K, M.b2);
+    M.v1 = fetch_cell_if(sdf, R, M.c2, M.m1 || m2);
+    if (i + 3 < N) {
+      march_step(M.mu);
+      M.c2 = march_cell_b(M.mu, R, K.nb, M.k2);
+      M.b2 = brick_load(K, hit, M.k2);
+    }
+  }
+  s_i = M.s0;
+  may_i = M.m0;
+  s_n = interp_cell(cur);
+  M.s0 = s_n;
+  M.m0 = M.m1;
+  M.m1 = m2;
+}
+
 // align-corners cell of an FP64 point; the weights are rounded to FP32 once
 __device__ __forceinline__ void axis_cell_d(double x, double inv_h, double kmax, int& k, float& f) {
   const double u = (x + 1.0) * inv_h;

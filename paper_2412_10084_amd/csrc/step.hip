@@ -358,6 +358,12 @@ hipError_t launch_grid_step(const StepArgs& a, hipStream_t s) {
   if (a.n_mlp > 0)
     hipLaunchKernelGGL(step_mlp_kernel, dim3((unsigned)((a.n_mlp + SBLOCK - 1) / SBLOCK)),
                        dim3(SBLOCK), 0, s, a);
+  if (a.sdf_bounds) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return a.sdf_half ? launch_sdf_bounds(a.sdf_half, a.R, 1, a.sdf_bounds, s)
+                      : launch_sdf_bounds(a.sdf_out, a.R, 0, a.sdf_bounds, s);
+  }
   return hipGetLastError();
 }
 

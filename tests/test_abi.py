@@ -64,6 +64,7 @@ def test_empty_batch_ok():
     (dict(probes=FAKE + 4), ps.EALIGN),
     (dict(sdf=FAKE + 2), ps.EALIGN),
     (dict(R=1000), ps.EINVAL),  # 1000^3 * 3 >= 2^31
+    (dict(sdf_bounds=FAKE + 4), ps.EALIGN),
 ])
 def test_field_validation(kw, code):
     assert _fwd(_field(**kw), _opts()) == code
@@ -141,3 +142,23 @@ def test_sphere_trace_and_loss_validation():
                                       None) == ps.EINVAL
     assert L.psdf_l1_loss(0, None, None, None, None, None) == ps.OK
     assert L.psdf_l1_loss(5, FAKE, None, FAKE, None, None) == ps.EINVAL
+
+
+def test_sdf_bounds_validation():
+    L = ps.lib()
+    assert L.psdf_sdf_bounds(1, 0, FAKE, FAKE, None) == ps.EINVAL
+    assert L.psdf_sdf_bounds(2000, 0, FAKE, FAKE, None) == ps.EINVAL
+    assert L.psdf_sdf_bounds(64, 2, FAKE, FAKE, None) == ps.EUNSUPPORTED
+    assert L.psdf_sdf_bounds(64, 0, None, FAKE, None) == ps.EINVAL
+    assert L.psdf_sdf_bounds(64, 0, FAKE, None, None) == ps.EINVAL
+    assert L.psdf_sdf_bounds(64, 0, FAKE + 2, FAKE, None) == ps.EALIGN
+    assert L.psdf_sdf_bounds(64, 0, FAKE, FAKE + 4, None) == ps.EALIGN
+    assert ps.n_bricks(2) == 1 and ps.n_bricks(9) == 1 and ps.n_bricks(10) == 2
+    assert ps.n_bricks(256) == 32 and ps.n_bricks(257) == 32 and ps.n_bricks(258) == 33
+
+
+def test_grid_step_bounds_alignment():
+    L = ps.lib()
+    a = _step_args()
+    a.sdf_bounds_out = a.sdf_bounds_out + 4
+    assert L.psdf_grid_step(C.byref(a), None) == ps.EALIGN

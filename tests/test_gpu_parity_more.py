@@ -18,12 +18,16 @@ pytestmark = pytest.mark.gpu
 # The GPU runs the whole batch (the benchmark's launch); the oracle evaluates a
 # sample of rays, and the backward carries loss gradient on that sample only.
 # ---------------------------------------------------------------------------
-def test_train256_full_size_sampled():
+@pytest.mark.parametrize("bounds", [True, False])
+def test_train256_full_size_sampled(bounds):
+    import paper_2412_10084_amd as ps
     w = wl.WORKLOADS["train256"]
     f = scene(0, w.R, w.P)
     o, d = rays(w.views, w.W, w.H)
     assert o.shape[0] == 1 << 18
     fld = device_field(f)
+    if bounds:  # empty-space skipping, as the benchmark runs it
+        fld.bounds = ps.sdf_bounds(fld.sdf)
     got = gpu_forward(fld, o, d, w.n_samples, skip=w.skip_voxels)
     rng = np.random.default_rng(7)
     idx = np.sort(rng.choice(o.shape[0], 3000, replace=False))
