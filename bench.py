@@ -58,6 +58,12 @@ class KernelTimer:
         return {k: sum(v) / len(v) for k, v in out.items()}
 
 
+def ws_samples(w, B):
+    """Room for shaded samples in the backward workspace: with the skip rule about one
+    sample per ray is shaded (train256: 1.09), so 8 per ray; without it up to N - 1."""
+    return 8 * B if w.skip_voxels > 0 else (w.n_samples - 1) * B
+
+
 def make_state(torch, ps, wl, w, feat_half=False, mlp_dtype=0, seed=0, order="image"):
     import numpy as np
     f = wl.random_field(seed, w.R, w.P, n_sh=w.n_sh)
@@ -84,6 +90,7 @@ def make_state(torch, ps, wl, w, feat_half=False, mlp_dtype=0, seed=0, order="im
     st["loss"] = torch.empty(1, device="cuda")
     # brick bounds of the initial SDF; every grid step writes those of the next one
     st["bounds"] = ps.sdf_bounds(master["sdf"])
+    st["ws"] = ps.backward_workspace(B, w.P, ws_samples(w, B))
     # target image: the torus field rendered by the same forward kernel
     tfield = ps.Field(cu(ft.sdf), cu(ft.feat), cu(ft.probes), cu(ft.mlp))
     st["target"] = torch.empty((B, 3), device="cuda")
@@ -106,7 +113,8 @@ def train_step(ps, w, st, step, timer):
                                                            st["aux"]))
     timer.run("l1_loss", lambda: ps.l1_loss(st["rgb"], st["target"], st["dL"], st["loss"]))
     timer.run("render_backward", lambda: ps.render_backward(fld, opts, st["o"], st["d"], st["aux"],
-                                                             st["dL"], st["grads"]))
+                                                             st["dL"], st["grads"],
+                                                             workspace=st["ws"]))
     out = dict(st["spare"], mlp=p["mlp"])
     timer.run("grid_step", lambda: ps.grid_step(p, out, st["grads"], st["m"], st["v"], step,
                                                 ps.StepOpts(), half_out=st["half"] or None,
@@ -201,6 +209,7 @@ def time_fwd_bwd_512(torch, ps, wl, steps, warmup):
     del tf
     out = {}
     base = gpu_field(torch, ps, wl, w, 0)
+    ws = ps.backward_workspace(B, w.P, ws_samples(w, B))
     for label, half, mdt in (("fp32", False, 0), ("fp16", True, 1), ("bf16", True, 2)):
         fld = ps.Field(base.sdf, base.feat.half() if half else base.feat,
                        base.probes.half() if half else base.probes, base.mlp, mdt)
@@ -212,7 +221,7 @@ def time_fwd_bwd_512(torch, ps, wl, steps, warmup):
         def step():
             ps.render_forward(fld, opts, do, dd, rgb, aux)
             ps.l1_loss(rgb, tgt, dL)
-            ps.render_backward(fld, opts, do, dd, aux, dL, grads)
+            ps.render_backward(fld, opts, do, dd, aux, dL, grads, workspace=ws)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -224,7 +233,7 @@ def time_fwd_bwd_512(torch, ps, wl, steps, warmup):
             e[1].record()
             ps.l1_loss(rgb, tgt, dL)
             e[2].record()
-            ps.render_backward(fld, opts, do, dd, aux, dL, grads)
+            ps.render_backward(fld, opts, do, dd, aux, dL, grads, workspace=ws)
             e[3].record()
             torch.cuda.synchronize()
             tf_ms += e[0].elapsed_time(e[1])
@@ -261,6 +270,7 @@ def time_iter512(torch, ps, wl, iters, warmup):
     st["aux"] = torch.empty((B, 4), device="cuda")
     st["loss"] = torch.empty(1, device="cuda")
     st["bounds"] = ps.sdf_bounds(f0.sdf)
+    st["ws"] = ps.backward_workspace(B, w.P, ws_samples(w, B))
     tf = gpu_field(torch, ps, wl, w, 1, shape="torus")
     ps.render_forward(tf, ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels), st["o"], st["d"],
                       st["target"])
@@ -283,7 +293,11 @@ def kernel_source_hash() -> str:
 
 
 TRAFFIC_KERNELS = {
-    "render_backward": ("void psdf::render_bwd_kernel<float, float, 9, 0>",),
+    "render_backward": ("void psdf::render_bwd_kernel<float, float, 9, 0>", "psdf::bwd_ws_clear_kernel",
+                        "void psdf::bwd_march_kernel<float>", "psdf::scan_sums_kernel",
+                        "psdf::scan_partials_kernel", "psdf::scan_offsets_kernel",
+                        "void psdf::bwd_shade_kernel<float, float, 9, 0>",
+                        "void psdf::probe_reduce_kernel<9>", "psdf::bwd_alpha_kernel"),
     "render_forward": ("void psdf::render_fwd_kernel<float, float, 9, 0>",),
     "grid_step": ("psdf::step_sdf_kernel", "void psdf::step_tv_kernel<3>", "void psdf::step_tv4_kernel<36>",
                   "psdf::step_mlp_kernel", "void psdf::sdf_bounds_kernel<float>"),

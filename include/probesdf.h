@@ -152,14 +152,31 @@ int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, i
  * field, opts and rays: given dL/drgb [B][3] and the forward's aux [B][4], ADDS
  * dL/d(sdf, feat, probes, mlp) into `grads` (Sec. 3.3: the SDF and appearance
  * are optimised by back-propagating the colour loss through the rendering
- * equation).  The march is recomputed; no per-sample state is stored.
+ * equation).  The march is recomputed; nothing is stored by the forward.
  * Gradients accumulate with FP32 atomics, so the summation order (and the last
  * bits) varies from run to run.  Gradients are defined with respect to the
  * values the forward reads (FP16 storage: the rounded values).
+ *   workspace, workspace_bytes: optional device buffer (256-byte aligned, at
+ *     least psdf_backward_workspace_bytes(B, P, 0) bytes) for the
+ *     entry-parallel schedule: a march pass writes the shaded samples there
+ *     (and counts them per probe cell), a shading pass processes them 64 per
+ *     wave whatever ray they come from and files their probe gradients by
+ *     probe cell, a pass per probe cell sums its records and adds them to the
+ *     cell's 8 corner nodes, and a per-ray pass adds the opacity gradient.
+ *     Waves of 64 rays whose samples do not fit are run by the fused schedule
+ *     afterwards, so any size gives the same gradients.  NULL: the fused
+ *     single-kernel schedule for every wave.  The workspace holds no state
+ *     between calls; calls that share one must not overlap.
  */
 int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
                          const float* rays_o, const float* rays_d, const float* aux,
-                         const float* dL_drgb, const psdf_grads* grads, void* stream);
+                         const float* dL_drgb, const psdf_grads* grads, void* workspace,
+                         int64_t workspace_bytes, void* stream);
+
+/* Bytes of a backward workspace for B rays and a P^3 probe grid with room for
+ * `max_samples` shaded samples (128 bytes each, plus 12 bytes per 64 rays and
+ * about 8 bytes per probe cell); -1 if an argument is out of range. */
+int64_t psdf_backward_workspace_bytes(int64_t B, int32_t P, int64_t max_samples);
 
 /*
  * psdf_l1_loss -- photometric loss.  The paper uses a relatively weighted L2

@@ -24,8 +24,8 @@ BRICK = 8
 N_FEAT, N_ANG, HIDDEN, N_MLP = 3, 4, 16, 227
 
 EXPORTS = ("psdf_render_forward", "psdf_render_backward", "psdf_l1_loss", "psdf_grid_step",
-           "psdf_render_sphere_trace", "psdf_sdf_bounds", "psdf_last_error",
-           "psdf_abi_version")
+           "psdf_render_sphere_trace", "psdf_sdf_bounds", "psdf_backward_workspace_bytes",
+           "psdf_last_error", "psdf_abi_version")
 
 
 class PsdfError(RuntimeError):
@@ -85,7 +85,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
         L.psdf_render_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
-        L.psdf_render_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.psdf_render_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.psdf_backward_workspace_bytes.argtypes = [i64, i32, i64]
         L.psdf_l1_loss.argtypes = [i64, vp, vp, vp, vp, vp]
         L.psdf_grid_step.argtypes = [vp, vp]
         L.psdf_render_sphere_trace.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp]
@@ -94,8 +95,9 @@ def lib():
         L.psdf_last_error.argtypes = []
         L.psdf_abi_version.restype = C.c_int
         for n in EXPORTS:
-            if n not in ("psdf_last_error", "psdf_abi_version"):
+            if n not in ("psdf_last_error", "psdf_abi_version", "psdf_backward_workspace_bytes"):
                 getattr(L, n).restype = C.c_int
+        L.psdf_backward_workspace_bytes.restype = C.c_int64
         if L.psdf_abi_version() != ABI_VERSION:
             raise RuntimeError("libprobesdf ABI version mismatch")
         _lib = L
@@ -194,14 +196,32 @@ def render_forward(field: Field, opts: RenderOpts, rays_o, rays_d, rgb, aux=None
                                      _ptr(rgb), _ptr(aux), _ptr(depth_wsum), _stream(stream)))
 
 
+def backward_workspace_bytes(B: int, P: int, max_samples: int) -> int:
+    n = lib().psdf_backward_workspace_bytes(B, P, max_samples)
+    if n < 0:
+        raise PsdfError(EINVAL, f"workspace size out of range (B={B}, P={P}, "
+                                f"max_samples={max_samples})")
+    return n
+
+
+def backward_workspace(B: int, P: int, max_samples: int, device="cuda"):
+    """A device buffer for the entry-parallel backward of B rays over a P^3 probe grid
+    with room for `max_samples` shaded samples (any size gives the same gradients;
+    waves that do not fit take the fused schedule)."""
+    import torch
+    n = backward_workspace_bytes(B, P, max_samples)
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
 def render_backward(field: Field, opts: RenderOpts, rays_o, rays_d, aux, dL_drgb, grads: dict,
-                    stream=None) -> None:
+                    stream=None, workspace=None) -> None:
     fs, op = field.cstruct(), opts.cstruct()
     g = _Grads(_ptr(grads.get("sdf")), _ptr(grads.get("feat")), _ptr(grads.get("probes")),
                _ptr(grads.get("mlp")))
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(lib().psdf_render_backward(C.byref(fs), C.byref(op), rays_o.shape[0], _ptr(rays_o),
                                       _ptr(rays_d), _ptr(aux), _ptr(dL_drgb), C.byref(g),
-                                      _stream(stream)))
+                                      _ptr(workspace), ws_bytes, _stream(stream)))
 
 
 def l1_loss(rgb, target, dL_drgb, loss=None, stream=None) -> None:

@@ -143,9 +143,17 @@ int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, i
                     "render_forward launch");
 }
 
+int64_t psdf_backward_workspace_bytes(int64_t B, int32_t P, int64_t max_samples) {
+  if (B < 0 || B > kMaxRays || P < 2 || P > 1024 || max_samples < 0 ||
+      max_samples > ((int64_t)1 << 31))
+    return -1;
+  return psdf::bwd_ws_bytes(B, P, max_samples);
+}
+
 int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
                          const float* rays_o, const float* rays_d, const float* aux,
-                         const float* dL_drgb, const psdf_grads* grads, void* stream) {
+                         const float* dL_drgb, const psdf_grads* grads, void* workspace,
+                         int64_t workspace_bytes, void* stream) {
   int rc;
   if ((rc = check_field(field)) || (rc = check_opts(opts))) return rc;
   if (B < 0 || B > kMaxRays) return fail(PSDF_EINVAL, "B=%lld out of range", (long long)B);
@@ -164,6 +172,19 @@ int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, 
   a.g_feat = grads->feat;
   a.g_probes = grads->probes;
   a.g_mlp = grads->mlp;
+  if (workspace) {
+    if (!aligned(workspace, 256)) return fail(PSDF_EALIGN, "workspace must be 256-byte aligned");
+    const int64_t need = psdf::bwd_ws_bytes(B, field->P, 0);
+    if (workspace_bytes < need || workspace_bytes > ((int64_t)1 << 40))
+      return fail(PSDF_EINVAL, "workspace_bytes=%lld outside [%lld, 2^40]",
+                  (long long)workspace_bytes, (long long)need);
+    const psdf::BwdWs ws = psdf::bwd_ws_carve(workspace, B, field->P, workspace_bytes);
+    return hip_status(psdf::launch_render_backward_split(a, ws, field->sdf_dtype,
+                                                         field->feat_dtype, field->mlp_dtype,
+                                                         field->sh_coeffs,
+                                                         static_cast<hipStream_t>(stream)),
+                      "render_backward launch");
+  }
   return hip_status(psdf::launch_render_backward(a, field->sdf_dtype, field->feat_dtype,
                                                  field->mlp_dtype, field->sh_coeffs,
                                                  static_cast<hipStream_t>(stream)),

@@ -1,0 +1,636 @@
+// Entry-parallel schedule of the ProbeSDF backward (same gradients as the
+// fused kernel in render_bwd.hip; Sec. 3.3 reverse mode).
+//
+// The fused kernel keeps a wave's march state live while it shades, so it runs
+// at one wave per SIMD, and waves whose rays cross the surface carry all the
+// shading work.  Here the work is split into passes over a caller-provided
+// workspace:
+//   1. march  -- one ray per lane, with brick skipping; the shaded samples
+//                (alpha > 0) are written as entries in chunks of 64, the chunks
+//                of one wave linked backwards, and counted per probe cell;
+//   2. scan   -- exclusive offsets of the probe-cell counts;
+//   3. shade  -- every wave takes 64 consecutive entries, whatever their rays:
+//                colour C_i (kept for pass 5), MLP reverse mode with
+//                dL/dC_i = w_i dL/drgb, the scatters into the features, the SDF
+//                (normal path) and the MLP weights, and a record of dL/dF_a filed
+//                under the sample's probe cell;
+//   4. probes -- one wave per occupied probe cell sums w_c Y_j dL/dF_a,k over
+//                the cell's records in registers (lanes = SH x angle
+//                coefficients) and adds the result to the cell's 8 corner
+//                nodes: one atomic per node coefficient per cell instead of one
+//                per sample;
+//   5. alpha  -- one wave per 64 rays walks its chunks backwards, forms the
+//                remaining colour R_i = sum_{j >= i} w_j C_j and
+//                dL/d dl_i = dL/drgb . (R_i - T_i C_i), and scatters the
+//                opacity gradient into the corners of s_i and s_{i+1}.
+// A wave whose entries do not fit into the workspace is flagged and handled by
+// the fused kernel afterwards (its partial entries are skipped; their probe
+// records carry zeros).
+#include "bwd_common.h"
+#include "dispatch.h"
+
+namespace psdf {
+
+namespace {
+constexpr int64_t kHead = 256;
+constexpr int kScan = 1024;  // items per scan block
+int64_t al256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+int64_t n_waves_of(int64_t B) { return (B + 63) / 64; }
+int64_t p3_of(int P) { return (int64_t)P * P * P; }
+int64_t nsum_of(int P) { return (p3_of(P) + kScan - 1) / kScan; }
+int64_t fixed_bytes(int64_t B, int P) {
+  return kHead + 3 * al256(n_waves_of(B) * 4) + 3 * al256(p3_of(P) * 4) + al256(nsum_of(P) * 4);
+}
+constexpr int64_t kPerSample = (int64_t)sizeof(BwdEntry) + (int64_t)sizeof(ProbeRec);
+}  // namespace
+
+int64_t bwd_ws_bytes(int64_t B, int P, int64_t cap) { return fixed_bytes(B, P) + cap * kPerSample; }
+
+int64_t bwd_ws_capacity(int64_t B, int P, int64_t bytes) {
+  // slot indices are 32-bit
+  const int64_t r = bytes - fixed_bytes(B, P);
+  return r > 0 ? min(r / kPerSample, (int64_t)INT32_MAX) : 0;
+}
+
+BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
+  char* p = static_cast<char*>(base);
+  const int64_t nw = n_waves_of(B), arr = al256(nw * 4), parr = al256(p3_of(P) * 4);
+  BwdWs w;
+  w.counter = reinterpret_cast<unsigned long long*>(p);
+  w.overflow = reinterpret_cast<int*>(p + kHead);
+  w.count = reinterpret_cast<int*>(p + kHead + arr);
+  w.last = reinterpret_cast<int*>(p + kHead + 2 * arr);
+  w.pcount = reinterpret_cast<int*>(p + kHead + 3 * arr);
+  w.pcursor = reinterpret_cast<int*>(p + kHead + 3 * arr + parr);
+  w.plist = reinterpret_cast<int*>(p + kHead + 3 * arr + 2 * parr);
+  w.psum = reinterpret_cast<int*>(p + kHead + 3 * arr + 3 * parr);
+  w.pocc = reinterpret_cast<int*>(p + 8);
+  w.cap = bwd_ws_capacity(B, P, bytes);
+  w.entries = reinterpret_cast<BwdEntry*>(p + fixed_bytes(B, P));
+  w.precs = reinterpret_cast<ProbeRec*>(p + fixed_bytes(B, P) + w.cap * (int64_t)sizeof(BwdEntry));
+  w.n_waves = nw;
+  w.P3 = p3_of(P);
+  w.nsum = nsum_of(P);
+  w.probe_bins = 0;
+  return w;
+}
+
+static_assert(sizeof(BwdEntry) == 80 && sizeof(ProbeRec) == 48, "record layouts");
+
+__global__ void __launch_bounds__(256) bwd_ws_clear_kernel(BwdWs ws) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i == 0) {
+    *ws.counter = 0;
+    *ws.pocc = 0;
+  }
+  if (i < ws.n_waves) ws.overflow[i] = 0;
+  if (ws.probe_bins && i < ws.P3) ws.pcount[i] = 0;
+}
+
+// Lanes with `on` set, grouped by equal `key`: returns the group's lane mask
+// to every member; the lowest member is the group's leader.  One iteration per
+// distinct key of the wave.
+template <typename F>
+__device__ __forceinline__ void for_each_key_group(bool on, int key, F&& f) {
+  uint64_t todo = __ballot(on);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int k = __builtin_amdgcn_readlane(key, leader);
+    const uint64_t grp = __ballot(on && key == k);
+    f(k, leader, grp);
+    todo &= ~grp;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: march and emit
+// ---------------------------------------------------------------------------
+struct EmitLds {
+  RayD ray[64];
+  int key[RING];  // (sample index << 6) | ray lane
+  float w[RING];
+  float T[RING];
+  float s0[RING];
+  float s1[RING];
+};
+
+template <typename ST>
+__global__ void __launch_bounds__(BLOCK) bwd_march_kernel(RenderArgs a, BwdWs ws) {
+  __shared__ EmitLds lds[WAVES];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  EmitLds& L = lds[wv];
+  const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
+  const unsigned lw = xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;
+  if (lw >= ws.n_waves) return;
+  const int64_t ray = (int64_t)lw * 64 + lane;
+  const bool valid = ray < a.B;
+  float ro[3] = {0.f, 0.f, 0.f}, rd[3] = {0.f, 0.f, 1.f}, dL[3] = {0.f, 0.f, 0.f};
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ro[k] = a.rays_o[3 * ray + k];
+      rd[k] = a.rays_d[3 * ray + k];
+      dL[k] = a.dL[3 * ray + k];
+    }
+  }
+  RayD r;
+  const bool hit = ray_setup_d(ro[0], ro[1], ro[2], rd[0], rd[1], rd[2], a.N, r) && valid &&
+                   (dL[0] != 0.f || dL[1] != 0.f || dL[2] != 0.f);
+  L.ray[lane] = r;
+
+  const double inv_h = 0.5 * (a.R - 1), inv_hp = 0.5 * (a.P - 1);
+  const Bricks K = make_bricks(a.bounds, a.R, a.skip_thr);
+  MarchState ms;
+  march_begin(sdf, a.R, K, r, inv_h, hit, a.N, ms);
+  float logT = 0.f;
+  int head = 0, tail = 0, total = 0, last = -1;
+  bool ovf = false;
+  for (int i = 0;; ++i) {
+    const bool stepping = i < a.N - 1;  // wave-uniform
+    if (stepping) {
+      float s_i, s_n;
+      bool may;
+      march_next(sdf, a.R, K, hit, i, a.N, ms, s_i, s_n, may);
+      const bool active = may && (a.skip_thr <= 0.f || fabsf(s_i) <= a.skip_thr);
+      bool shaded = false;
+      float dl = 0.f;
+      if (active) {
+        dl = log_sigmoid(a.tau * s_n) - log_sigmoid(a.tau * s_i);
+        shaded = dl < 0.f;
+      }
+      const uint64_t mask = __ballot(shaded);
+      if (shaded) {
+        const float T = expf(logT);
+        const int slot = (tail + lane_rank(mask)) & (RING - 1);
+        L.key[slot] = (i << 6) | lane;
+        L.w[slot] = T * -expm1f(dl);
+        L.T[slot] = T;
+        L.s0[slot] = s_i;
+        L.s1[slot] = s_n;
+        logT += dl;
+      }
+      tail += __popcll(mask);
+    }
+    const int pending = tail - head;
+    if (pending >= 64 || (!stepping && pending > 0)) {
+      const int n = min(64, pending);
+      wave_sync();
+      unsigned long long got = 0;
+      if (lane == 0) got = atomicAdd(ws.counter, (unsigned long long)n);
+      const int64_t base = (int64_t)__shfl(got, 0, 64);
+      if (base + n > ws.cap) {
+        // no room: the fused kernel takes this wave; the slots it got hold nothing
+        if (base + lane < ws.cap && lane < n) ws.entries[base + lane].lw = -1;
+        ovf = true;
+        break;
+      }
+      int pc = 0;
+      if (lane < n) {
+        const int slot = (head + lane) & (RING - 1);
+        const int key = L.key[slot];
+        const RayD& rr = L.ray[key & 63];
+        BwdEntry e;
+        sample_pos(rr, sample_t(rr, key >> 6), e.x);
+        pc = cell_d(e.x, a.P, inv_hp).base;
+        e.v[0] = (float)-rr.d[0];
+        e.v[1] = (float)-rr.d[1];
+        e.v[2] = (float)-rr.d[2];
+        e.w = L.w[slot];
+        e.T = L.T[slot];
+        e.s0 = L.s0[slot];
+        e.s1 = L.s1[slot];
+        e.ray = (int)(lw * 64u) + (key & 63);
+        e.key = key;
+        e.lw = (int)lw;
+        e.prev = last;
+        e.C[0] = e.C[1] = e.C[2] = 0.f;
+        ws.entries[base + lane] = e;
+      }
+      if (ws.probe_bins)
+        for_each_key_group(lane < n, pc, [&](int k, int leader, uint64_t grp) {
+          if (lane == leader) atomicAdd(ws.pcount + k, (int)__popcll(grp));
+        });
+      last = (int)base;
+      total += n;
+      head += n;
+      wave_sync();
+    } else if (!stepping) {
+      break;
+    }
+  }
+  if (lane == 0) {
+    ws.count[lw] = ovf ? 0 : total;
+    ws.last[lw] = ovf ? -1 : last;
+    if (ovf) ws.overflow[lw] = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: exclusive scan of the probe-cell counts (blocks of 1024 cells)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// block-wide exclusive scan of one int per thread (256 threads); returns the total
+__device__ __forceinline__ int block_excl_scan(int v, int* part, int& excl) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int inc = wave_incl_scan(v, lane);
+  if (lane == 63) part[wv] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    off += k < wv ? part[k] : 0;
+    tot += part[k];
+  }
+  __syncthreads();
+  excl = off + inc - v;
+  return tot;
+}
+
+__global__ void __launch_bounds__(256) scan_sums_kernel(BwdWs ws) {
+  __shared__ int part[4];
+  const int64_t i0 = (int64_t)blockIdx.x * kScan + threadIdx.x * 4;
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v += i0 + k < ws.P3 ? ws.pcount[i0 + k] : 0;
+  int excl;
+  const int tot = block_excl_scan(v, part, excl);
+  if (threadIdx.x == 0) ws.psum[blockIdx.x] = tot;
+}
+
+// one block: exclusive scan of the block sums in place
+__global__ void __launch_bounds__(256) scan_partials_kernel(BwdWs ws) {
+  __shared__ int part[4];
+  int carry = 0;
+  for (int64_t b0 = 0; b0 < ws.nsum; b0 += 256) {
+    const int64_t b = b0 + threadIdx.x;
+    const int v = b < ws.nsum ? ws.psum[b] : 0;
+    int excl;
+    const int tot = block_excl_scan(v, part, excl);
+    if (b < ws.nsum) ws.psum[b] = carry + excl;
+    carry += tot;
+  }
+}
+
+// offsets of every cell, and the list of occupied cells
+__global__ void __launch_bounds__(256) scan_offsets_kernel(BwdWs ws) {
+  __shared__ int part[4];
+  __shared__ int lbase;
+  const int64_t i0 = (int64_t)blockIdx.x * kScan + threadIdx.x * 4;
+  int c[4], v = 0, occ = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c[k] = i0 + k < ws.P3 ? ws.pcount[i0 + k] : 0;
+    v += c[k];
+    occ += c[k] > 0;
+  }
+  int excl, oexcl;
+  block_excl_scan(v, part, excl);
+  const int otot = block_excl_scan(occ, part, oexcl);
+  if (threadIdx.x == 0) lbase = otot > 0 ? atomicAdd(ws.pocc, otot) : 0;
+  __syncthreads();
+  int o = ws.psum[blockIdx.x] + excl, li = lbase + oexcl;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i0 + k < ws.P3) ws.pcursor[i0 + k] = o;
+    if (c[k] > 0) ws.plist[li++] = (int)(i0 + k);
+    o += c[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 3: shading reverse mode, 64 entries per wave
+// ---------------------------------------------------------------------------
+template <int NSH>
+struct ShadeLds {
+  union {
+    DwLds dw;
+    float sc[64][65];
+  } u;
+  int k0[64][3];
+  int fb[64];
+};
+
+template <typename ST, typename FT, int NSH, int M>
+__global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs ws) {
+  __shared__ ShadeLds<NSH> lds[WAVES];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  ShadeLds<NSH>& L = lds[wv];
+  const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
+  const FT* __restrict__ feat = static_cast<const FT*>(a.feat);
+  const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
+  const float* __restrict__ W = a.mlp;
+  const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
+  const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
+  const int64_t nbat = (total + 63) / 64;
+
+  f4 acc_w1 = {0.f, 0.f, 0.f, 0.f}, acc_w2 = {0.f, 0.f, 0.f, 0.f};
+  float db2[3] = {0.f, 0.f, 0.f};
+  bool any = false;
+  for (int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WAVES + wv; b < nbat;
+       b += (int64_t)gridDim.x * WAVES) {
+    any = true;
+    const int64_t e = b * 64 + lane;
+    const int n = (int)min((int64_t)64, total - b * 64);
+    BwdEntry E;
+    bool counted = false, ve = false;  // counted: holds a sample (has a probe bin slot)
+    if (lane < n) {
+      E = ws.entries[e];
+      counted = E.lw >= 0;
+      ve = counted && ws.overflow[E.lw] == 0;
+    }
+    float z[NIN];
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) z[j] = 0.f;
+    Normal nm;
+    nm.n[0] = nm.n[1] = nm.n[2] = 0.f;
+    nm.gn = 1.f;
+    nm.c = 0.f;
+    double x[3] = {0.0, 0.0, 0.0};
+    float v[3] = {0.f, 0.f, 0.f}, Y[NSH];
+#pragma unroll
+    for (int j = 0; j < NSH; ++j) Y[j] = 0.f;
+    if (ve) {
+      x[0] = E.x[0];
+      x[1] = E.x[1];
+      x[2] = E.x[2];
+      v[0] = E.v[0];
+      v[1] = E.v[1];
+      v[2] = E.v[2];
+      sh_basis<NSH>(v[0], v[1], v[2], Y);
+      shade_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, Y, z, nm);
+    }
+    float pre[HID], hid[HID], out[3];
+    mlp_lane<M>(W, z, pre, hid, out);
+    const float C0 = sigmoidf(out[0]), C1 = sigmoidf(out[1]), C2 = sigmoidf(out[2]);
+    float dout[3] = {0.f, 0.f, 0.f};
+    if (ve) {
+      ws.entries[e].C[0] = C0;
+      ws.entries[e].C[1] = C1;
+      ws.entries[e].C[2] = C2;
+      const float* dLr = a.dL + 3 * (int64_t)E.ray;
+      dout[0] = E.w * dLr[0] * C0 * (1.f - C0);
+      dout[1] = E.w * dLr[1] * C1 * (1.f - C1);
+      dout[2] = E.w * dLr[2] * C2 * (1.f - C2);
+    }
+    float dpre[HID], dz[NIN];
+    mlp_backward_lane<M>(W, dout, pre, ve, dpre, dz);
+    // SDF through the normal (the opacity path is pass 3)
+    if (a.g_sdf && !(G.flags & FLAG_NV_ONE)) {
+      float* row = L.u.sc[lane];
+#pragma unroll
+      for (int q = 0; q < 64; ++q) row[q] = 0.f;
+      if (ve) {
+        int k0[3];
+        cell_k(x, G.R, G.inv_h, k0);
+        L.k0[lane][0] = k0[0];
+        L.k0[lane][1] = k0[1];
+        L.k0[lane][2] = k0[2];
+        normal_backward_patch(row, k0, G, x, v, nm, dz);
+      }
+      wave_sync();
+      sdf_patch_flush(L.u.sc, L.k0, n, lane, G.R, a.g_sdf);
+      wave_sync();
+    }
+    if (!(G.flags & FLAG_NO_FS) && a.g_feat)
+      feat_scatter_wave(L.u.sc, L.fb, ve, cell_d(x, G.R, G.inv_h), dz, n, lane, G.R, a.g_feat);
+    if (ws.probe_bins) {
+      // file dL/dF_a under the probe cell (the cell of the stored position, as
+      // counted by the march pass)
+      double xs[3] = {0.0, 0.0, 0.0};
+      if (counted) {
+        xs[0] = E.x[0];
+        xs[1] = E.x[1];
+        xs[2] = E.x[2];
+      }
+      const Cell cp = cell_d(xs, G.P, G.inv_hp);
+      // the group leaders reserve their slots back to back; each lane then reads
+      // its leader's base
+      int first = 0, my_leader = 0;
+      uint64_t my_grp = 0;
+      for_each_key_group(counted, cp.base, [&](int k, int leader, uint64_t grp) {
+        if (lane == leader) first = atomicAdd(ws.pcursor + k, (int)__popcll(grp));
+        if ((grp >> lane) & 1ull) {
+          my_leader = leader;
+          my_grp = grp;
+        }
+      });
+      first = __shfl(first, my_leader, 64);
+      if (counted) {
+        const uint64_t grp = my_grp;
+        const int k = cp.base;
+        {
+          ProbeRec pr;
+          pr.cell = k;
+          pr.f[0] = cp.fx;
+          pr.f[1] = cp.fy;
+          pr.f[2] = cp.fz;
+          pr.v[0] = E.v[0];
+          pr.v[1] = E.v[1];
+          pr.v[2] = E.v[2];
+          pr.dfa[0] = ve ? dz[3] : 0.f;
+          pr.dfa[1] = ve ? dz[4] : 0.f;
+          pr.dfa[2] = ve ? dz[5] : 0.f;
+          pr.dfa[3] = ve ? dz[6] : 0.f;
+          pr.pad = 0.f;
+          ws.precs[first + lane_rank(grp)] = pr;
+        }
+      }
+    }
+    if (a.g_mlp) mlp_dw_wave<M>(L.u.dw, lane, ve, z, hid, dpre, dout, acc_w1, acc_w2, db2);
+    wave_sync();
+  }
+  if (any && a.g_mlp) mlp_grad_flush(a.g_mlp, lane, acc_w1, acc_w2, db2);
+}
+
+// ---------------------------------------------------------------------------
+// pass 4: probe gradient per occupied probe cell
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+template <int NSH>
+__global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs ws) {
+  const int lane = threadIdx.x & 63;
+  const int gw = (int)(blockIdx.x * WAVES + (threadIdx.x >> 6));
+  const int nw = (int)(gridDim.x * WAVES);
+  constexpr int NQ = NSH * NA;  // coefficients per node, one per lane
+  const int j = min(lane >> 2, NSH - 1), k = lane & 3;
+  const int nocc = *ws.pocc;
+  for (int oi = gw; oi < nocc; oi += nw) {
+    const int cell = ws.plist[oi];
+    const int cnt = ws.pcount[cell];
+    const int end = ws.pcursor[cell];  // advanced by the placement to offset + count
+    float acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    for (int r0 = end - cnt; r0 < end; r0 += 64) {
+      // one record per lane, then broadcast record by record
+      const int m = min(64, end - r0);
+      float f0 = 0.f, f1 = 0.f, f2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
+      float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+      if (lane < m) {
+        const ProbeRec& pr = ws.precs[r0 + lane];
+        f0 = pr.f[0];
+        f1 = pr.f[1];
+        f2 = pr.f[2];
+        v0 = pr.v[0];
+        v1 = pr.v[1];
+        v2 = pr.v[2];
+        d0 = pr.dfa[0];
+        d1 = pr.dfa[1];
+        d2 = pr.dfa[2];
+        d3 = pr.dfa[3];
+      }
+      for (int t = 0; t < m; ++t) {
+        float Y[NSH];
+        sh_basis<NSH>(rdlane(v0, t), rdlane(v1, t), rdlane(v2, t), Y);
+        float yj = Y[0];
+#pragma unroll
+        for (int q = 1; q < NSH; ++q) yj = q == j ? Y[q] : yj;
+        const float e0 = rdlane(d0, t), e1 = rdlane(d1, t), e2 = rdlane(d2, t), e3 = rdlane(d3, t);
+        const float g = yj * (k == 0 ? e0 : k == 1 ? e1 : k == 2 ? e2 : e3);
+        float w[8];
+        corner_w(Cell{0, rdlane(f0, t), rdlane(f1, t), rdlane(f2, t)}, w);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = fmaf(w[c], g, acc[c]);
+      }
+    }
+    if (lane < NQ) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (acc[c] != 0.f)
+          atomic_add_f32(a.g_probes + (int64_t)(cell + corner_off(c, a.P)) * NQ + lane, acc[c]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 5: per-ray walk and the opacity gradient
+// ---------------------------------------------------------------------------
+struct AlphaLds {
+  RayD ray[64];
+  int own[64];
+  float w[64];
+  float T[64];
+  float C[64][3];
+  float gdl[64];
+};
+
+__global__ void __launch_bounds__(BLOCK) bwd_alpha_kernel(RenderArgs a, BwdWs ws) {
+  __shared__ AlphaLds lds[WAVES];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  AlphaLds& L = lds[wv];
+  const unsigned lw = xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;
+  if (lw >= ws.n_waves || ws.overflow[lw] != 0) return;
+  const int cnt = ws.count[lw];
+  if (cnt == 0) return;
+  const int64_t ray = (int64_t)lw * 64 + lane;
+  const bool valid = ray < a.B;
+  float ro[3] = {0.f, 0.f, 0.f}, rd[3] = {0.f, 0.f, 1.f}, dL[3] = {0.f, 0.f, 0.f};
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ro[k] = a.rays_o[3 * ray + k];
+      rd[k] = a.rays_d[3 * ray + k];
+      dL[k] = a.dL[3 * ray + k];
+    }
+  }
+  RayD r;
+  ray_setup_d(ro[0], ro[1], ro[2], rd[0], rd[1], rd[2], a.N, r);
+  L.ray[lane] = r;
+  const int R = a.R;
+  const double inv_h = 0.5 * (a.R - 1);
+  float Rc[3] = {0.f, 0.f, 0.f};  // remaining colour of this lane's ray
+  int base = ws.last[lw];
+  int n = cnt - 64 * ((cnt - 1) / 64);  // the last chunk may be partial
+  while (base >= 0) {  // wave-uniform
+    wave_sync();
+    BwdEntry E;
+    E.prev = -1;
+    if (lane < n) {
+      E = ws.entries[base + lane];
+      L.own[lane] = E.key & 63;
+      L.w[lane] = E.w;
+      L.T[lane] = E.T;
+      L.C[lane][0] = E.C[0];
+      L.C[lane][1] = E.C[1];
+      L.C[lane][2] = E.C[2];
+    }
+    wave_sync();
+    for (int k = n - 1; k >= 0; --k) {
+      if (lane == L.own[k]) {
+        const float w = L.w[k], T = L.T[k];
+        const float c0 = L.C[k][0], c1 = L.C[k][1], c2 = L.C[k][2];
+        Rc[0] = fmaf(w, c0, Rc[0]);
+        Rc[1] = fmaf(w, c1, Rc[1]);
+        Rc[2] = fmaf(w, c2, Rc[2]);
+        L.gdl[k] = dL[0] * (Rc[0] - T * c0) + dL[1] * (Rc[1] - T * c1) + dL[2] * (Rc[2] - T * c2);
+      }
+    }
+    wave_sync();
+    if (lane < n) {
+      const float gdl = L.gdl[lane];
+      const RayD& rr = L.ray[E.key & 63];
+      const int si = E.key >> 6;
+      double x0[3], x1[3];
+      sample_pos(rr, sample_t(rr, si), x0);
+      sample_pos(rr, sample_t(rr, si + 1), x1);
+      scatter8(a.g_sdf, R, cell_d(x0, R, inv_h), -a.tau * sigmoidf(-a.tau * E.s0) * gdl);
+      scatter8(a.g_sdf, R, cell_d(x1, R, inv_h), a.tau * sigmoidf(-a.tau * E.s1) * gdl);
+    }
+    base = __shfl(E.prev, 0, 64);
+    n = 64;
+  }
+}
+
+hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in, int sdf_dt,
+                                        int feat_dt, int mlp_dt, int n_sh, hipStream_t s) {
+  BwdWs ws = ws_in;
+  // probe gradients go through the cell bins (one lane per node coefficient:
+  // n_sh * n_ang <= 64 for every compiled SH order)
+  ws.probe_bins = (a.g_probes && !(a.flags & FLAG_NO_FA)) ? 1 : 0;
+  const dim3 wgrid((unsigned)((a.B + BLOCK - 1) / BLOCK));
+  const int64_t nclear = max(ws.n_waves, ws.probe_bins ? ws.P3 : (int64_t)0);
+  hipLaunchKernelGGL(bwd_ws_clear_kernel, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, s,
+                     ws);
+  if (sdf_dt == 0)
+    hipLaunchKernelGGL(bwd_march_kernel<float>, wgrid, dim3(BLOCK), 0, s, a, ws);
+  else
+    hipLaunchKernelGGL(bwd_march_kernel<_Float16>, wgrid, dim3(BLOCK), 0, s, a, ws);
+  if (ws.probe_bins) {
+    hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(256), 0, s, ws);
+    hipLaunchKernelGGL(scan_offsets_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);
+  }
+  // enough waves to fill the chip; each loops over batches of 64 entries
+  const int64_t want = (ws.cap + 64 * WAVES - 1) / (64 * WAVES);
+  const dim3 sgrid((unsigned)max((int64_t)1, min(want, (int64_t)1024)));
+  PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,
+      hipLaunchKernelGGL((bwd_shade_kernel<ST, FT, NSH, M>), sgrid, dim3(BLOCK), 0, s, a, ws))));
+  if (ws.probe_bins) {
+    // one wave per occupied cell (the count is on the device: enough waves for
+    // a dense band, each looping)
+    const int64_t pw = min(ws.P3, (int64_t)16384);
+    const dim3 pgrid((unsigned)max((int64_t)1, (pw + WAVES - 1) / WAVES));
+    PSDF_SH_SWITCH(n_sh,
+        hipLaunchKernelGGL((probe_reduce_kernel<NSH>), pgrid, dim3(BLOCK), 0, s, a, ws));
+  }
+  if (a.g_sdf) hipLaunchKernelGGL(bwd_alpha_kernel, wgrid, dim3(BLOCK), 0, s, a, ws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // waves that did not fit
+  RenderArgs f = a;
+  f.todo = ws.overflow;
+  return launch_render_backward(f, sdf_dt, feat_dt, mlp_dt, n_sh, s);
+}
+
+}  // namespace psdf

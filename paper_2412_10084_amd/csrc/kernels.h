@@ -34,7 +34,54 @@ struct RenderArgs {
   float* g_feat;
   float* g_probes;
   float* g_mlp;
+  const int* todo;  // backward: nonzero entries select the 64-ray waves to run; nullptr = all
 };
+
+// One shaded sample of the entry-parallel backward (80 bytes).
+struct BwdEntry {
+  double x[3];    // sample position
+  float v[3];     // view direction (-unit ray direction)
+  float w, T;     // compositing weight T_i alpha_i and transmittance T_i
+  float s0, s1;   // s_i, s_{i+1}
+  int ray;        // ray index
+  int key;        // (sample index << 6) | lane of the ray in its wave
+  int lw;         // the ray's 64-ray wave; -1: a slot that holds no sample
+  int prev;       // first slot of the previous chunk of the same wave, -1 if none
+  float C[3];     // colour of the sample (written by the shading pass)
+};
+
+// Gradient record of one shaded sample for the probe grid, placed in probe-cell order.
+struct ProbeRec {
+  int cell;       // probe cell (flat index of its lower corner node)
+  float f[3];     // trilinear fractions in the cell
+  float v[3];     // view direction (the SH argument)
+  float dfa[4];   // dL/dF_a
+  float pad;
+};
+
+// Device workspace of the entry-parallel backward, carved from one caller buffer.
+struct BwdWs {
+  unsigned long long* counter;  // [1] slots handed out (may pass cap)
+  int* overflow;       // [n_waves] 1: the wave did not fit and runs the fused kernel
+  int* count;          // [n_waves] samples of the wave
+  int* last;           // [n_waves] first slot of the wave's last chunk, -1 if none
+  int* pcount;         // [P^3] samples per probe cell
+  int* pcursor;        // [P^3] exclusive offsets, advanced by the placement
+  int* psum;           // [nsum] scan partials
+  int* plist;          // [P^3] occupied probe cells (first *pocc entries)
+  int* pocc;           // [1]
+  BwdEntry* entries;   // [cap]
+  ProbeRec* precs;     // [cap] in probe-cell order
+  int64_t cap;
+  int64_t n_waves;
+  int64_t P3, nsum;
+  int probe_bins;      // 1: the probe gradient goes through the cell bins
+};
+
+// bytes of a workspace with room for `cap` samples; carve() lays it out
+int64_t bwd_ws_bytes(int64_t B, int P, int64_t cap);
+int64_t bwd_ws_capacity(int64_t B, int P, int64_t bytes);
+BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes);
 
 struct TraceArgs {
   int R, P;
@@ -89,6 +136,8 @@ hipError_t launch_render_forward(const RenderArgs& a, int sdf_dt, int feat_dt, i
                                  int n_sh, hipStream_t s);
 hipError_t launch_render_backward(const RenderArgs& a, int sdf_dt, int feat_dt, int mlp_dt,
                                   int n_sh, hipStream_t s);
+hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws, int sdf_dt,
+                                        int feat_dt, int mlp_dt, int n_sh, hipStream_t s);
 hipError_t launch_sphere_trace(const TraceArgs& a, int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
                                hipStream_t s);
 hipError_t launch_l1_loss(int64_t B, const float* rgb, const float* target, float* dL,

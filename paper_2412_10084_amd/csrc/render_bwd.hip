@@ -15,8 +15,8 @@
 // sample through the MLP and the interpolations and scatters the gradients
 // with FP32 atomics.  MLP weight gradients accumulate as MFMA outer-product
 // sums over the batch and are flushed once per wave.
+#include "bwd_common.h"
 #include "dispatch.h"
-#include "shade.h"
 
 namespace psdf {
 
@@ -114,23 +114,8 @@ __device__ __forceinline__ void bwd_batch(const RenderArgs& a, const Geo& G, Bwd
     dout[1] = w * L.dL[rl][1] * C1 * (1.f - C1);
     dout[2] = w * L.dL[rl][2] * C2 * (1.f - C2);
   }
-  // MLP reverse mode (per lane)
-  float dpre[HID];
-#pragma unroll
-  for (int k = 0; k < HID; ++k) {
-    float acc = 0.f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc = fmaf(mrnd<M>(W[OFF_W2 + c * HID + k]), dout[c], acc);
-    dpre[k] = pre[k] > 0.f ? acc : 0.f;
-  }
-  float dz[NIN];
-#pragma unroll
-  for (int j = 0; j < NIN; ++j) {
-    float acc = 0.f;
-#pragma unroll
-    for (int k = 0; k < HID; ++k) acc = fmaf(mrnd<M>(W[k * NIN + j]), dpre[k], acc);
-    dz[j] = ve ? acc : 0.f;
-  }
+  float dpre[HID], dz[NIN];
+  mlp_backward_lane<M>(W, dout, pre, ve, dpre, dz);
   // SDF: opacity path at s_i and the normal path, in the entry's 4x4x4 patch
   if (a.g_sdf) {
     float* row = L.u.sc[lane];
@@ -146,37 +131,12 @@ __device__ __forceinline__ void bwd_batch(const RenderArgs& a, const Geo& G, Bwd
       if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch(row, k0, G, x, v, nm, dz);
     }
     wave_sync();
-    const int px = lane & 3, py = (lane >> 2) & 3, pz = lane >> 4;
-    for (int e = 0; e < n; ++e) {
-      const float val = L.u.sc[e][lane];
-      const int nx = L.k0[e][0] - 1 + px, ny = L.k0[e][1] - 1 + py, nz = L.k0[e][2] - 1 + pz;
-      if (val != 0.f && nx >= 0 && ny >= 0 && nz >= 0 && nx < G.R && ny < G.R && nz < G.R)
-        atomic_add_f32(a.g_sdf + (nz * G.R + ny) * G.R + nx, val);
-    }
+    sdf_patch_flush(L.u.sc, L.k0, n, lane, G.R, a.g_sdf);
     wave_sync();
   }
-  // spatial features: 8 corners x 3 channels, flushed item-major (x-neighbour
-  // corners are 6 contiguous floats)
-  if (!(G.flags & FLAG_NO_FS) && a.g_feat) {
-    if (ve) {
-      const Cell cs = cell_d(x, G.R, G.inv_h);
-      float wc[8];
-      corner_w(cs, wc);
-      L.fb[lane] = cs.base;
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-#pragma unroll
-        for (int ch = 0; ch < NF; ++ch) L.u.sc[lane][c * NF + ch] = wc[c] * dz[ch];
-    }
-    wave_sync();
-    for (int k = lane; k < n * 8 * NF; k += 64) {
-      const int e = k / (8 * NF), q = k - e * (8 * NF);
-      const int c = q / NF, ch = q - c * NF;
-      const float val = L.u.sc[e][q];
-      if (val != 0.f) atomic_add_f32(a.g_feat + (L.fb[e] + corner_off(c, G.R)) * NF + ch, val);
-    }
-    wave_sync();
-  }
+  // spatial features
+  if (!(G.flags & FLAG_NO_FS) && a.g_feat)
+    feat_scatter_wave(L.u.sc, L.fb, ve, cell_d(x, G.R, G.inv_h), dz, n, lane, G.R, a.g_feat);
   // probes: aggregated per distinct probe cell of the batch
   if (!(G.flags & FLAG_NO_FA) && a.g_probes) {
     probe_acc_clear<NSH>(L.u.pa, lane);
@@ -184,24 +144,7 @@ __device__ __forceinline__ void bwd_batch(const RenderArgs& a, const Geo& G, Bwd
     probe_scatter_wave<NSH>(L.u.pa, lane, ve, ve ? cell_d(x, G.P, G.inv_hp) : Cell{0, 0.f, 0.f, 0.f},
                             G.P, Y, dfa, a.g_probes);
   }
-  if (a.g_mlp) {
-    DwLds& D = L.u.dw;
-    float zin[16], hin[16], dop[16];
-#pragma unroll
-    for (int j = 0; j < NIN; ++j) zin[j] = mrnd<M>(z[j]);
-    zin[NIN] = ve ? 1.f : 0.f;
-#pragma unroll
-    for (int j = NIN + 1; j < 16; ++j) zin[j] = 0.f;
-#pragma unroll
-    for (int k = 0; k < HID; ++k) hin[k] = mrnd<M>(hid[k]);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) dop[k] = k < 3 ? dout[k] : 0.f;
-    dw_accumulate(D, lane, dpre, zin, acc_w1);
-    dw_accumulate(D, lane, dop, hin, acc_w2);
-    db2[0] += dout[0];
-    db2[1] += dout[1];
-    db2[2] += dout[2];
-  }
+  if (a.g_mlp) mlp_dw_wave<M>(L.u.dw, lane, ve, z, hid, dpre, dout, acc_w1, acc_w2, db2);
   wave_sync();
 }
 
@@ -213,7 +156,10 @@ __global__ void __launch_bounds__(BLOCK) render_bwd_kernel(RenderArgs a) {
   const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
 
-  const int64_t ray = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  const unsigned lw = xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;  // this wave's 64 rays
+  if ((int64_t)lw * 64 >= a.B) return;
+  if (a.todo && a.todo[lw] == 0) return;  // only the listed waves (wave-uniform)
+  const int64_t ray = (int64_t)lw * 64 + lane;
   const bool valid = ray < a.B;
   float ro[3] = {0.f, 0.f, 0.f}, rd[3] = {0.f, 0.f, 1.f}, dL[3] = {0.f, 0.f, 0.f};
   float R[3] = {0.f, 0.f, 0.f};
@@ -287,21 +233,7 @@ __global__ void __launch_bounds__(BLOCK) render_bwd_kernel(RenderArgs a) {
     }
   }
   // flush this wave's MLP gradients (any_batch is wave-uniform)
-  if (any_batch && a.g_mlp) {
-    const int i = lane & 15, g = lane >> 4;
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int row = 4 * g + rr;  // hidden unit for dW1, output for dW2
-      if (i < NIN) atomic_add_f32(a.g_mlp + row * NIN + i, acc_w1[rr]);
-      else if (i == NIN) atomic_add_f32(a.g_mlp + OFF_B1 + row, acc_w1[rr]);
-      if (row < 3) atomic_add_f32(a.g_mlp + OFF_W2 + row * HID + i, acc_w2[rr]);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float s = wave_sum(db2[c]);
-      if (lane == 0) atomic_add_f32(a.g_mlp + OFF_B2 + c, s);
-    }
-  }
+  if (any_batch && a.g_mlp) mlp_grad_flush(a.g_mlp, lane, acc_w1, acc_w2, db2);
 }
 
 hipError_t launch_render_backward(const RenderArgs& a, int sdf_dt, int feat_dt, int mlp_dt,

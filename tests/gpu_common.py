@@ -69,13 +69,18 @@ def gpu_forward(fld, o, d, N, tau=64.0, skip=0.0, flags=0):
                 dev=(do, dd, rgb, aux))
 
 
-def gpu_backward(fld, o_dev, d_dev, aux_dev, dL, N, tau=64.0, skip=0.0, flags=0):
+def gpu_backward(fld, o_dev, d_dev, aux_dev, dL, N, tau=64.0, skip=0.0, flags=0, workspace=None,
+                 groups=("sdf", "feat", "probes", "mlp")):
+    """workspace: None (fused schedule), an int (entry-parallel schedule with room for that
+    many shaded samples) or a device buffer."""
     import paper_2412_10084_amd as ps
     t = torch()
     g = dict(sdf=t.zeros(fld.sdf.shape, device="cuda"), feat=t.zeros(fld.feat.shape, device="cuda"),
              probes=t.zeros(fld.probes.shape, device="cuda"), mlp=t.zeros(227, device="cuda"))
+    if isinstance(workspace, int):
+        workspace = ps.backward_workspace(o_dev.shape[0], fld.probes.shape[0], workspace)
     ps.render_backward(fld, ps.RenderOpts(N, tau, skip, flags), o_dev, d_dev, aux_dev,
-                       dev(dL.astype(np.float32)), g)
+                       dev(dL.astype(np.float32)), {k: g[k] for k in groups}, workspace=workspace)
     t.cuda.synchronize()
     return {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
 

@@ -92,12 +92,35 @@ def test_backward_requires_grads_and_aux():
     L = ps.lib()
     g = ps._Grads(FAKE, FAKE, FAKE, FAKE)
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, FAKE, FAKE,
-                                  None, None) == ps.EINVAL
+                                  None, None, 0, None) == ps.EINVAL
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, None, FAKE,
-                                  C.byref(g), None) == ps.EINVAL
+                                  C.byref(g), None, 0, None) == ps.EINVAL
     g.probes = FAKE + 2
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, FAKE, FAKE,
-                                  C.byref(g), None) == ps.EALIGN
+                                  C.byref(g), None, 0, None) == ps.EALIGN
+
+
+def test_backward_workspace_validation():
+    L = ps.lib()
+    g = ps._Grads(FAKE, FAKE, FAKE, FAKE)
+    B = 1000
+    need = ps.backward_workspace_bytes(B, 16, 0)
+    assert need > 0
+    assert ps.backward_workspace_bytes(B, 16, 10) == need + 10 * 128
+    assert ps.backward_workspace_bytes(B, 32, 0) > need
+    # misaligned workspace
+    assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), B, FAKE, FAKE, FAKE, FAKE,
+                                  C.byref(g), FAKE + 64, need, None) == ps.EALIGN
+    # too small for the per-wave arrays
+    assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), B, FAKE, FAKE, FAKE, FAKE,
+                                  C.byref(g), FAKE, need - 1, None) == ps.EINVAL
+    assert "workspace" in ps.last_error()
+    assert L.psdf_backward_workspace_bytes(-1, 16, 0) == -1
+    assert L.psdf_backward_workspace_bytes(10, 16, -5) == -1
+    assert L.psdf_backward_workspace_bytes(10, 1, 0) == -1
+    # B = 0 with a workspace is a no-op
+    assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 0, FAKE, FAKE, FAKE, FAKE,
+                                  C.byref(g), FAKE, 0, None) == ps.OK
 
 
 def _step_args(**kw):
