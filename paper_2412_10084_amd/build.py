@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libprobesdf.so")
 
 SOURCES = ["abi.cpp", "render_fwd.hip", "render_bwd.hip", "trace.hip", "loss.hip", "step.hip",
-           "bounds.hip", "bwd_split.hip"]
+           "bounds.hip", "bwd_split.hip", "step_sdf.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -68,6 +68,16 @@ __device__ __forceinline__ float4 ld4(const _Float16* __restrict__ p, int i) {
 
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
 
+// bias-corrected Adam (Kingma & Ba, Algorithm 1) on one parameter; bc = 1 - beta^t
+__device__ __forceinline__ float adam_update_f(float p, float G, float& m, float& v, float lr,
+                                               float b1, float b2, float eps, float bc1, float bc2) {
+  m = b1 * m + (1.0f - b1) * G;
+  v = b2 * v + (1.0f - b2) * G * G;
+  const float mh = m / bc1;
+  const float vh = v / bc2;
+  return p - lr * mh / (sqrtf(vh) + eps);
+}
+
 // ---------------------------------------------------------------------------
 // align-corners cell of a point: per axis u = (x+1)/h, k0 = clamp(floor u, 0, R-2),
 // weights f = u - k0 (computed in FP64, see shade.h)

@@ -143,6 +143,7 @@ hipError_t launch_sphere_trace(const TraceArgs& a, int sdf_dt, int feat_dt, int 
 hipError_t launch_l1_loss(int64_t B, const float* rgb, const float* target, float* dL,
                           float* loss, hipStream_t s);
 hipError_t launch_grid_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_step_sdf(const StepArgs& a, hipStream_t s);
 hipError_t launch_sdf_bounds(const void* sdf, int R, int sdf_dt, float* bounds, hipStream_t s);
 
 }  // namespace psdf

@@ -39,8 +39,10 @@ hipError_t launch_l1_loss(int64_t B, const float* rgb, const float* target, floa
                           hipStream_t s) {
   const int64_t n = 3 * B;
   if (loss) hipLaunchKernelGGL(zero1_kernel, dim3(1), dim3(64), 0, s, loss);
-  int64_t blocks = (n + LBLOCK - 1) / LBLOCK;
-  if (blocks > 4096) blocks = 4096;
+  // every block adds its partial sum to the one loss value, and same-address
+  // atomics serialise: few blocks, each looping
+  int64_t blocks = (n + 8 * LBLOCK - 1) / (8 * LBLOCK);
+  if (blocks > 256) blocks = 256;
   hipLaunchKernelGGL(l1_loss_kernel, dim3((unsigned)blocks), dim3(LBLOCK), 0, s, n,
                      (float)(1.0 / (3.0 * (double)B)), rgb, target, dL, loss);
   return hipGetLastError();

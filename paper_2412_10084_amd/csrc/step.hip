@@ -4,27 +4,18 @@
 // smooth_probes) added to the accumulated render gradient, then Adam (Sec. 3.4;
 // moments as in the supplementary scheduling section).
 //
-// Each grid is one streaming pass launched as (row chunk, j, k): a thread owns
-// one parameter (four for probes), gathers the regulariser gradient of that
-// parameter from its stencil (no scatter, no atomics), applies Adam, writes the
-// new value to a separate output buffer (neighbours still read the old one),
-// writes the moments back, zeroes the gradient and optionally writes an FP16
-// copy.  Index arithmetic divides only by compile-time constants.
+// The feature and probe grids are streaming passes launched as (row chunk, j,
+// k): a thread owns four parameters, gathers the regulariser gradient of each
+// from its stencil (no scatter, no atomics), applies Adam, writes the new value
+// to a separate output buffer (neighbours still read the old one), writes the
+// moments back, zeroes the gradient and optionally writes an FP16 copy.  The
+// SDF pass (eikonal) is tiled through LDS (step_sdf.hip).
 #include "device.h"
 #include "kernels.h"
 
 namespace psdf {
 
 constexpr int SBLOCK = 256;
-
-__device__ __forceinline__ float adam_update(float p, float G, float& m, float& v, float lr, float b1,
-                                             float b2, float eps, float bc1, float bc2) {
-  m = b1 * m + (1.0f - b1) * G;
-  v = b2 * v + (1.0f - b2) * G * G;
-  const float mh = m / bc1;
-  const float vh = v / bc2;
-  return p - lr * mh / (sqrtf(vh) + eps);
-}
 
 __device__ __forceinline__ void block_add(float val, float* dst) {
   __shared__ float part[SBLOCK / 64];
@@ -36,62 +27,6 @@ __device__ __forceinline__ void block_add(float val, float* dst) {
     for (int w = 0; w < SBLOCK / 64; ++w) s += part[w];
     if (s != 0.f) atomic_add_f32(dst, s);
   }
-}
-
-// ---------------------------------------------------------------------------
-// SDF: eikonal gradient in gather form.  With g_n the central-difference
-// gradient of interior node n and q_n = 2 (|g_n| - 1) g_n / |g_n| (0 off the
-// interior or for g_n = 0), dL/ds_m = lambda/M * sum_a (q_{m-e_a,a} - q_{m+e_a,a}) / 2h.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float eik_q(const float* __restrict__ s, int R, int RR, int i, int j,
-                                       int k, float inv2h, int axis) {
-  if (i < 1 || j < 1 || k < 1 || i > R - 2 || j > R - 2 || k > R - 2) return 0.f;
-  const int n = (k * R + j) * R + i;
-  const float gx = (s[n + 1] - s[n - 1]) * inv2h;
-  const float gy = (s[n + R] - s[n - R]) * inv2h;
-  const float gz = (s[n + RR] - s[n - RR]) * inv2h;
-  const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
-  if (!(gn > 0.f)) return 0.f;
-  const float ga = axis == 0 ? gx : (axis == 1 ? gy : gz);
-  return 2.0f * (gn - 1.0f) / gn * ga;
-}
-
-__global__ void __launch_bounds__(SBLOCK) step_sdf_kernel(StepArgs a) {
-  const int R = a.R, RR = R * R;
-  unsigned bx, by, bz;
-  xcd_block3(bx, by, bz);
-  const int i = bx * SBLOCK + threadIdx.x, j = by, k = bz;
-  const bool valid = i < R;
-  const float inv2h = 0.5f / a.h;
-  const float M = (float)(R - 2) * (float)(R - 2) * (float)(R - 2);
-  const float coef = a.lambda_eik / M;
-  float loss = 0.f;
-  if (valid) {
-    const int n = (k * R + j) * R + i;
-    const float* __restrict__ s = a.sdf_in;
-    float G = a.g_sdf[n];
-    if (a.lambda_eik != 0.f && R >= 3) {
-      const float ge = eik_q(s, R, RR, i - 1, j, k, inv2h, 0) - eik_q(s, R, RR, i + 1, j, k, inv2h, 0) +
-                       eik_q(s, R, RR, i, j - 1, k, inv2h, 1) - eik_q(s, R, RR, i, j + 1, k, inv2h, 1) +
-                       eik_q(s, R, RR, i, j, k - 1, inv2h, 2) - eik_q(s, R, RR, i, j, k + 1, inv2h, 2);
-      G += coef * ge * inv2h;
-      if (a.losses && i >= 1 && j >= 1 && k >= 1 && i <= R - 2 && j <= R - 2 && k <= R - 2) {
-        const float gx = (s[n + 1] - s[n - 1]) * inv2h;
-        const float gy = (s[n + R] - s[n - R]) * inv2h;
-        const float gz = (s[n + RR] - s[n - RR]) * inv2h;
-        const float e = sqrtf(gx * gx + gy * gy + gz * gz) - 1.0f;
-        loss = e * e;
-      }
-    }
-    float m = a.m_sdf[n], v = a.v_sdf[n];
-    const float p = adam_update(s[n], G, m, v, a.lr_sdf, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
-    a.sdf_out[n] = p;
-    a.m_sdf[n] = m;
-    a.v_sdf[n] = v;
-    a.g_sdf[n] = 0.f;
-    if (a.sdf_half) static_cast<_Float16*>(a.sdf_half)[n] = (_Float16)p;
-  }
-  if (a.losses) block_add(loss * coef, a.losses + 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -135,7 +70,7 @@ __global__ void __launch_bounds__(SBLOCK) step_tv_kernel(TvArgs t, StepArgs a) {
     if (k < R - 1) { const float d = F[e + sz] - f; acc -= d; loss += d * d; }
     const float G = t.g[e] + 2.0f * scale * acc;
     float m = t.m[e], v = t.v[e];
-    const float p = adam_update(f, G, m, v, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    const float p = adam_update_f(f, G, m, v, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
     t.F_out[e] = p;
     t.m[e] = m;
     t.v[e] = v;
@@ -191,10 +126,10 @@ __global__ void __launch_bounds__(SBLOCK) step_tv4_kernel(TvArgs t, StepArgs a) 
     float4 m = ld4g(t.m, e), v = ld4g(t.v, e);
     const float s2 = 2.0f * scale;
     float4 p;
-    p.x = adam_update(f.x, g.x + s2 * acc.x, m.x, v.x, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
-    p.y = adam_update(f.y, g.y + s2 * acc.y, m.y, v.y, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
-    p.z = adam_update(f.z, g.z + s2 * acc.z, m.z, v.z, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
-    p.w = adam_update(f.w, g.w + s2 * acc.w, m.w, v.w, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.x = adam_update_f(f.x, g.x + s2 * acc.x, m.x, v.x, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.y = adam_update_f(f.y, g.y + s2 * acc.y, m.y, v.y, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.z = adam_update_f(f.z, g.z + s2 * acc.z, m.z, v.z, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.w = adam_update_f(f.w, g.w + s2 * acc.w, m.w, v.w, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
     st4g(t.F_out, e, p);
     st4g(t.m, e, m);
     st4g(t.v, e, v);
@@ -255,10 +190,10 @@ __global__ void __launch_bounds__(SBLOCK) step_tv3v_kernel(TvArgs t, StepArgs a)
     float4 m = ld4g(t.m, e), v = ld4g(t.v, e);
     const float s2 = 2.0f * scale;
     float4 p;
-    p.x = adam_update(f[0], g.x + s2 * acc[0], m.x, v.x, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
-    p.y = adam_update(f[1], g.y + s2 * acc[1], m.y, v.y, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
-    p.z = adam_update(f[2], g.z + s2 * acc[2], m.z, v.z, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
-    p.w = adam_update(f[3], g.w + s2 * acc[3], m.w, v.w, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.x = adam_update_f(f[0], g.x + s2 * acc[0], m.x, v.x, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.y = adam_update_f(f[1], g.y + s2 * acc[1], m.y, v.y, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.z = adam_update_f(f[2], g.z + s2 * acc[2], m.z, v.z, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    p.w = adam_update_f(f[3], g.w + s2 * acc[3], m.w, v.w, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
     st4g(t.F_out, e, p);
     st4g(t.m, e, m);
     st4g(t.v, e, v);
@@ -275,7 +210,7 @@ __global__ void __launch_bounds__(SBLOCK) step_mlp_kernel(StepArgs a) {
   const int e = blockIdx.x * SBLOCK + threadIdx.x;
   if (e < a.n_mlp) {
     float m = a.m_mlp[e], v = a.v_mlp[e];
-    a.mlp[e] = adam_update(a.mlp[e], a.g_mlp[e], m, v, a.lr_mlp, a.beta1, a.beta2, a.eps, a.bc1,
+    a.mlp[e] = adam_update_f(a.mlp[e], a.g_mlp[e], m, v, a.lr_mlp, a.beta1, a.beta2, a.eps, a.bc1,
                            a.bc2);
     a.m_mlp[e] = m;
     a.v_mlp[e] = v;
@@ -311,7 +246,7 @@ __global__ void __launch_bounds__(SBLOCK) step_tv_any_kernel(TvArgs t, int C, St
     if (k > 0) acc += f - F[e - sz];
     if (k < R - 1) { const float d = F[e + sz] - f; acc -= d; loss += d * d; }
     float m = t.m[e], v = t.v[e];
-    const float p = adam_update(f, t.g[e] + 2.0f * scale * acc, m, v, t.lr, a.beta1, a.beta2,
+    const float p = adam_update_f(f, t.g[e] + 2.0f * scale * acc, m, v, t.lr, a.beta1, a.beta2,
                                 a.eps, a.bc1, a.bc2);
     t.F_out[e] = p;
     t.m[e] = m;
@@ -347,8 +282,7 @@ static void launch_tv(const TvArgs& t, int C, const StepArgs& a, hipStream_t s) 
 
 hipError_t launch_grid_step(const StepArgs& a, hipStream_t s) {
   if (a.losses) hipLaunchKernelGGL(zero3_kernel, dim3(1), dim3(64), 0, s, a.losses);
-  const unsigned R = (unsigned)a.R;
-  hipLaunchKernelGGL(step_sdf_kernel, dim3((R + SBLOCK - 1) / SBLOCK, R, R), dim3(SBLOCK), 0, s, a);
+  launch_step_sdf(a, s);
   TvArgs tf{a.R, a.lambda_tv_feat, a.lr_feat, a.feat_in, a.feat_out, a.g_feat, a.m_feat, a.v_feat,
             static_cast<_Float16*>(a.feat_half), a.losses ? a.losses + 1 : nullptr};
   launch_tv(tf, a.n_feat, a, s);
@@ -358,12 +292,6 @@ hipError_t launch_grid_step(const StepArgs& a, hipStream_t s) {
   if (a.n_mlp > 0)
     hipLaunchKernelGGL(step_mlp_kernel, dim3((unsigned)((a.n_mlp + SBLOCK - 1) / SBLOCK)),
                        dim3(SBLOCK), 0, s, a);
-  if (a.sdf_bounds) {
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return a.sdf_half ? launch_sdf_bounds(a.sdf_half, a.R, 1, a.sdf_bounds, s)
-                      : launch_sdf_bounds(a.sdf_out, a.R, 0, a.sdf_bounds, s);
-  }
   return hipGetLastError();
 }
 

@@ -124,10 +124,11 @@ def test_backward_with_bounds():
 
 
 @pytest.mark.parametrize("with_half", [False, True])
-def test_grid_step_writes_bounds(with_half):
+@pytest.mark.parametrize("R", [24, 70, 129])
+def test_grid_step_writes_bounds(with_half, R):
     import paper_2412_10084_amd as ps
     t = torch()
-    R, P = 24, 8
+    P = 8
     rng = np.random.default_rng(3)
     keys = ("sdf", "feat", "probes", "mlp")
     shapes = dict(sdf=(R, R, R), feat=(R, R, R, 3), probes=(P, P, P, 9, 4), mlp=(227,))

@@ -108,11 +108,12 @@ def _step_inputs(R=24, P=8, seed=21):
     return p, g, m, v
 
 
-@pytest.mark.parametrize("step", [1, 7])
-def test_grid_step_matches_oracle(step):
+# R = 70: several x tiles and z chunks of the tiled SDF pass, ragged at the ends
+@pytest.mark.parametrize("step,R", [(1, 24), (7, 24), (3, 70)])
+def test_grid_step_matches_oracle(step, R):
     import paper_2412_10084_amd as ps
     t = torch()
-    p, g, m, v = _step_inputs()
+    p, g, m, v = _step_inputs(R=R)
     opts = ps.StepOpts()
     keys = ("sdf", "feat", "probes", "mlp")
     dp = {k: dev(p[k]) for k in keys}
