@@ -110,11 +110,11 @@ def train_step(ps, w, st, step, timer):
         fld = ps.Field(p["sdf"], p["feat"], p["probes"], p["mlp"], st["mlp_dtype"], st["bounds"])
     opts = ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels)
     timer.run("render_forward", lambda: ps.render_forward(fld, opts, st["o"], st["d"], st["rgb"],
-                                                           st["aux"]))
+                                                           st["aux"], tape=st["ws"]))
     timer.run("l1_loss", lambda: ps.l1_loss(st["rgb"], st["target"], st["dL"], st["loss"]))
     timer.run("render_backward", lambda: ps.render_backward(fld, opts, st["o"], st["d"], st["aux"],
                                                              st["dL"], st["grads"],
-                                                             workspace=st["ws"]))
+                                                             workspace=st["ws"], from_tape=True))
     out = dict(st["spare"], mlp=p["mlp"])
     timer.run("grid_step", lambda: ps.grid_step(p, out, st["grads"], st["m"], st["v"], step,
                                                 ps.StepOpts(), half_out=st["half"] or None,
@@ -219,9 +219,9 @@ def time_fwd_bwd_512(torch, ps, wl, steps, warmup):
         grads = {k: torch.zeros(v.shape, device="cuda", dtype=torch.float32) for k, v in
                  dict(sdf=fld.sdf, feat=fld.feat, probes=fld.probes, mlp=fld.mlp).items()}
         def step():
-            ps.render_forward(fld, opts, do, dd, rgb, aux)
+            ps.render_forward(fld, opts, do, dd, rgb, aux, tape=ws)
             ps.l1_loss(rgb, tgt, dL)
-            ps.render_backward(fld, opts, do, dd, aux, dL, grads, workspace=ws)
+            ps.render_backward(fld, opts, do, dd, aux, dL, grads, workspace=ws, from_tape=True)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -229,11 +229,11 @@ def time_fwd_bwd_512(torch, ps, wl, steps, warmup):
         tf_ms = tb_ms = 0.0
         for _ in range(steps):
             e[0].record()
-            ps.render_forward(fld, opts, do, dd, rgb, aux)
+            ps.render_forward(fld, opts, do, dd, rgb, aux, tape=ws)
             e[1].record()
             ps.l1_loss(rgb, tgt, dL)
             e[2].record()
-            ps.render_backward(fld, opts, do, dd, aux, dL, grads, workspace=ws)
+            ps.render_backward(fld, opts, do, dd, aux, dL, grads, workspace=ws, from_tape=True)
             e[3].record()
             torch.cuda.synchronize()
             tf_ms += e[0].elapsed_time(e[1])

@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define PSDF_ABI_VERSION 2
+#define PSDF_ABI_VERSION 3
 
 #define PSDF_OK 0
 #define PSDF_EINVAL (-1)       /* null pointer, bad size or shape, aliasing */
@@ -142,10 +142,16 @@ typedef struct psdf_grads {
  *   rgb         [B][3] out
  *   aux         [B][4] out, nullable: (rgb, log T_final); required by the backward
  *   depth_wsum  [B][2] out, nullable: (sum_i w_i (t_i + dt/2), sum_i w_i), w_i = T_i alpha_i
+ *   tape, tape_bytes: nullable device buffer laid out as a backward workspace
+ *     (see psdf_render_backward); when given, the forward also records every
+ *     shaded sample there (position, weights, s_i, s_{i+1}, colour, MLP inputs,
+ *     normal, about 160 bytes each) for a backward called with
+ *     PSDF_BWD_FROM_TAPE.  Waves of 64 rays whose samples do not fit are
+ *     flagged and re-marched by that backward.  The outputs do not depend on it.
  */
 int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
                         const float* rays_o, const float* rays_d, float* rgb, float* aux,
-                        float* depth_wsum, void* stream);
+                        float* depth_wsum, void* tape, int64_t tape_bytes, void* stream);
 
 /*
  * psdf_render_backward -- reverse mode of psdf_render_forward for the same
@@ -165,17 +171,27 @@ int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, i
  *     cell's 8 corner nodes, and a per-ray pass adds the opacity gradient.
  *     Waves of 64 rays whose samples do not fit are run by the fused schedule
  *     afterwards, so any size gives the same gradients.  NULL: the fused
- *     single-kernel schedule for every wave.  The workspace holds no state
- *     between calls; calls that share one must not overlap.
+ *     single-kernel schedule for every wave.  Calls that share a workspace
+ *     must not overlap.
+ *   flags: PSDF_BWD_FROM_TAPE -- the workspace holds the tape that
+ *     psdf_render_forward recorded for the same field, opts and rays (the
+ *     reserve-space contract: nothing may touch it in between).  The march and
+ *     the re-read of the shading inputs are skipped, the per-ray walk runs
+ *     first on the recorded colours, and the opacity gradient at s_i joins the
+ *     sample's SDF patch.  Waves the forward flagged as not fitting are
+ *     re-marched by the fused schedule.  0: the workspace is scratch.
  */
+#define PSDF_BWD_FROM_TAPE 1
+
 int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
                          const float* rays_o, const float* rays_d, const float* aux,
                          const float* dL_drgb, const psdf_grads* grads, void* workspace,
-                         int64_t workspace_bytes, void* stream);
+                         int64_t workspace_bytes, int32_t flags, void* stream);
 
-/* Bytes of a backward workspace for B rays and a P^3 probe grid with room for
- * `max_samples` shaded samples (128 bytes each, plus 12 bytes per 64 rays and
- * about 8 bytes per probe cell); -1 if an argument is out of range. */
+/* Bytes of a backward workspace (or forward tape) for B rays and a P^3 probe
+ * grid with room for `max_samples` shaded samples (208 bytes each, plus 12
+ * bytes per 64 rays and about 12 bytes per probe cell); -1 if an argument is
+ * out of range. */
 int64_t psdf_backward_workspace_bytes(int64_t B, int32_t P, int64_t max_samples);
 
 /*

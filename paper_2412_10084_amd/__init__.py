@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libprobesdf.so")
 F32, F16, BF16 = 0, 1, 2
 FLAG_NO_FS, FLAG_NO_FA, FLAG_NV_ONE = 1, 2, 4
 OK, EINVAL, EALIGN, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
-ABI_VERSION = 2
+ABI_VERSION = 3
+BWD_FROM_TAPE = 1
 BRICK = 8
 
 N_FEAT, N_ANG, HIDDEN, N_MLP = 3, 4, 16, 227
@@ -84,8 +85,8 @@ def lib():
                                " (the HIP library is required; there is no fallback)")
         L = C.CDLL(LIB_PATH)
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
-        L.psdf_render_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
-        L.psdf_render_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.psdf_render_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.psdf_render_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i64, i32, vp]
         L.psdf_backward_workspace_bytes.argtypes = [i64, i32, i64]
         L.psdf_l1_loss.argtypes = [i64, vp, vp, vp, vp, vp]
         L.psdf_grid_step.argtypes = [vp, vp]
@@ -188,12 +189,19 @@ class StepOpts:
 # ---------------------------------------------------------------------------
 # entry points (raw calls: every tensor argument is a device tensor or a pointer)
 # ---------------------------------------------------------------------------
+def _nbytes(t) -> int:
+    return 0 if t is None else t.numel() * t.element_size()
+
+
 def render_forward(field: Field, opts: RenderOpts, rays_o, rays_d, rgb, aux=None,
-                   depth_wsum=None, stream=None) -> None:
+                   depth_wsum=None, stream=None, tape=None) -> None:
+    """tape: optional workspace (backward_workspace) in which the forward records its
+    shaded samples for render_backward(..., from_tape=True)."""
     fs, op = field.cstruct(), opts.cstruct()
     B = rays_o.shape[0] if not isinstance(rays_o, int) else None
     _check(lib().psdf_render_forward(C.byref(fs), C.byref(op), B, _ptr(rays_o), _ptr(rays_d),
-                                     _ptr(rgb), _ptr(aux), _ptr(depth_wsum), _stream(stream)))
+                                     _ptr(rgb), _ptr(aux), _ptr(depth_wsum), _ptr(tape),
+                                     _nbytes(tape), _stream(stream)))
 
 
 def backward_workspace_bytes(B: int, P: int, max_samples: int) -> int:
@@ -214,14 +222,16 @@ def backward_workspace(B: int, P: int, max_samples: int, device="cuda"):
 
 
 def render_backward(field: Field, opts: RenderOpts, rays_o, rays_d, aux, dL_drgb, grads: dict,
-                    stream=None, workspace=None) -> None:
+                    stream=None, workspace=None, from_tape: bool = False) -> None:
+    """workspace: optional scratch for the entry-parallel schedule, or (from_tape) the
+    tape the forward recorded for the same field, opts and rays."""
     fs, op = field.cstruct(), opts.cstruct()
     g = _Grads(_ptr(grads.get("sdf")), _ptr(grads.get("feat")), _ptr(grads.get("probes")),
                _ptr(grads.get("mlp")))
-    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(lib().psdf_render_backward(C.byref(fs), C.byref(op), rays_o.shape[0], _ptr(rays_o),
                                       _ptr(rays_d), _ptr(aux), _ptr(dL_drgb), C.byref(g),
-                                      _ptr(workspace), ws_bytes, _stream(stream)))
+                                      _ptr(workspace), _nbytes(workspace),
+                                      BWD_FROM_TAPE if from_tape else 0, _stream(stream)))
 
 
 def l1_loss(rgb, target, dL_drgb, loss=None, stream=None) -> None:

@@ -121,9 +121,18 @@ int psdf_abi_version(void) { return PSDF_ABI_VERSION; }
 
 const char* psdf_last_error(void) { return g_err; }
 
+static int check_ws(void* ws, int64_t bytes, int64_t B, int P, const char* what) {
+  if (!aligned(ws, 256)) return fail(PSDF_EALIGN, "%s must be 256-byte aligned", what);
+  const int64_t need = psdf::bwd_ws_bytes(B, P, 0);
+  if (bytes < need || bytes > ((int64_t)1 << 40))
+    return fail(PSDF_EINVAL, "%s bytes=%lld outside [%lld, 2^40]", what, (long long)bytes,
+                (long long)need);
+  return PSDF_OK;
+}
+
 int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
                         const float* rays_o, const float* rays_d, float* rgb, float* aux,
-                        float* depth_wsum, void* stream) {
+                        float* depth_wsum, void* tape, int64_t tape_bytes, void* stream) {
   int rc;
   if ((rc = check_field(field)) || (rc = check_opts(opts))) return rc;
   if (B < 0 || B > kMaxRays) return fail(PSDF_EINVAL, "B=%lld out of range", (long long)B);
@@ -137,7 +146,13 @@ int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, i
   a.rgb = rgb;
   a.aux = aux;
   a.depth_wsum = depth_wsum;
-  return hip_status(psdf::launch_render_forward(a, field->sdf_dtype, field->feat_dtype,
+  psdf::BwdWs ws{};
+  if (tape) {
+    if ((rc = check_ws(tape, tape_bytes, B, field->P, "tape"))) return rc;
+    ws = psdf::bwd_ws_carve(tape, B, field->P, tape_bytes);
+  }
+  return hip_status(psdf::launch_render_forward(a, tape ? &ws : nullptr, field->sdf_dtype,
+                                                field->feat_dtype,
                                                 field->mlp_dtype, field->sh_coeffs,
                                                 static_cast<hipStream_t>(stream)),
                     "render_forward launch");
@@ -153,7 +168,7 @@ int64_t psdf_backward_workspace_bytes(int64_t B, int32_t P, int64_t max_samples)
 int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
                          const float* rays_o, const float* rays_d, const float* aux,
                          const float* dL_drgb, const psdf_grads* grads, void* workspace,
-                         int64_t workspace_bytes, void* stream) {
+                         int64_t workspace_bytes, int32_t flags, void* stream) {
   int rc;
   if ((rc = check_field(field)) || (rc = check_opts(opts))) return rc;
   if (B < 0 || B > kMaxRays) return fail(PSDF_EINVAL, "B=%lld out of range", (long long)B);
@@ -172,14 +187,14 @@ int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, 
   a.g_feat = grads->feat;
   a.g_probes = grads->probes;
   a.g_mlp = grads->mlp;
+  if (flags & ~PSDF_BWD_FROM_TAPE) return fail(PSDF_EINVAL, "unknown backward flags 0x%x", flags);
+  if ((flags & PSDF_BWD_FROM_TAPE) && !workspace)
+    return fail(PSDF_EINVAL, "PSDF_BWD_FROM_TAPE needs the workspace the forward recorded");
   if (workspace) {
-    if (!aligned(workspace, 256)) return fail(PSDF_EALIGN, "workspace must be 256-byte aligned");
-    const int64_t need = psdf::bwd_ws_bytes(B, field->P, 0);
-    if (workspace_bytes < need || workspace_bytes > ((int64_t)1 << 40))
-      return fail(PSDF_EINVAL, "workspace_bytes=%lld outside [%lld, 2^40]",
-                  (long long)workspace_bytes, (long long)need);
+    if ((rc = check_ws(workspace, workspace_bytes, B, field->P, "workspace"))) return rc;
     const psdf::BwdWs ws = psdf::bwd_ws_carve(workspace, B, field->P, workspace_bytes);
-    return hip_status(psdf::launch_render_backward_split(a, ws, field->sdf_dtype,
+    return hip_status(psdf::launch_render_backward_split(a, ws, (flags & PSDF_BWD_FROM_TAPE) != 0,
+                                                         field->sdf_dtype,
                                                          field->feat_dtype, field->mlp_dtype,
                                                          field->sh_coeffs,
                                                          static_cast<hipStream_t>(stream)),

@@ -75,17 +75,28 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   return w;
 }
 
-static_assert(sizeof(BwdEntry) == 80 && sizeof(ProbeRec) == 48, "record layouts");
+static_assert(sizeof(BwdEntry) == 160 && sizeof(ProbeRec) == 48, "record layouts");
 
-__global__ void __launch_bounds__(256) bwd_ws_clear_kernel(BwdWs ws) {
+// waves = 1: reset the slot counter and the overflow flags (before a march or a
+// taped forward); probe_bins: reset the probe-cell counts
+__global__ void __launch_bounds__(256) bwd_ws_clear_kernel(BwdWs ws, int waves) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i == 0) {
-    *ws.counter = 0;
+    if (waves) *ws.counter = 0;
     *ws.pocc = 0;
   }
-  if (i < ws.n_waves) ws.overflow[i] = 0;
+  if (waves && i < ws.n_waves) ws.overflow[i] = 0;
   if (ws.probe_bins && i < ws.P3) ws.pcount[i] = 0;
 }
+
+static hipError_t launch_clear(const BwdWs& ws, int waves, hipStream_t s) {
+  const int64_t n = max(waves ? ws.n_waves : (int64_t)1, ws.probe_bins ? ws.P3 : (int64_t)1);
+  hipLaunchKernelGGL(bwd_ws_clear_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ws,
+                     waves);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_ws_clear(const BwdWs& ws, hipStream_t s) { return launch_clear(ws, 1, s); }
 
 // Lanes with `on` set, grouped by equal `key`: returns the group's lane mask
 // to every member; the lowest member is the group's leader.  One iteration per
@@ -318,7 +329,7 @@ struct ShadeLds {
   int fb[64];
 };
 
-template <typename ST, typename FT, int NSH, int M>
+template <typename ST, typename FT, int NSH, int M, bool TAPE>
 __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs ws) {
   __shared__ ShadeLds<NSH> lds[WAVES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -365,16 +376,34 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
       v[1] = E.v[1];
       v[2] = E.v[2];
       sh_basis<NSH>(v[0], v[1], v[2], Y);
-      shade_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, Y, z, nm);
+      if constexpr (TAPE) {
+        // the forward's shading inputs
+#pragma unroll
+        for (int j = 0; j < NIN; ++j) z[j] = E.z[j];
+        nm.n[0] = E.nrm[0];
+        nm.n[1] = E.nrm[1];
+        nm.n[2] = E.nrm[2];
+        nm.gn = E.gn;
+        nm.c = E.z[7];
+      } else {
+        shade_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, Y, z, nm);
+      }
     }
     float pre[HID], hid[HID], out[3];
     mlp_lane<M>(W, z, pre, hid, out);
-    const float C0 = sigmoidf(out[0]), C1 = sigmoidf(out[1]), C2 = sigmoidf(out[2]);
+    float C0 = sigmoidf(out[0]), C1 = sigmoidf(out[1]), C2 = sigmoidf(out[2]);
+    if (TAPE && ve) {  // the colour the forward composited
+      C0 = E.C[0];
+      C1 = E.C[1];
+      C2 = E.C[2];
+    }
     float dout[3] = {0.f, 0.f, 0.f};
     if (ve) {
-      ws.entries[e].C[0] = C0;
-      ws.entries[e].C[1] = C1;
-      ws.entries[e].C[2] = C2;
+      if (!TAPE) {
+        ws.entries[e].C[0] = C0;
+        ws.entries[e].C[1] = C1;
+        ws.entries[e].C[2] = C2;
+      }
       const float* dLr = a.dL + 3 * (int64_t)E.ray;
       dout[0] = E.w * dLr[0] * C0 * (1.f - C0);
       dout[1] = E.w * dLr[1] * C1 * (1.f - C1);
@@ -382,8 +411,10 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
     }
     float dpre[HID], dz[NIN];
     mlp_backward_lane<M>(W, dout, pre, ve, dpre, dz);
-    // SDF through the normal (the opacity path is pass 3)
-    if (a.g_sdf && !(G.flags & FLAG_NV_ONE)) {
+    // SDF through the normal; with a tape also the opacity path at s_i (this
+    // sample's alpha and the previous sample's, which meet at x_i); the rest of
+    // the opacity path is scattered by the per-ray walk
+    if (a.g_sdf && (TAPE || !(G.flags & FLAG_NV_ONE))) {
       float* row = L.u.sc[lane];
 #pragma unroll
       for (int q = 0; q < 64; ++q) row[q] = 0.f;
@@ -393,7 +424,11 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
         L.k0[lane][0] = k0[0];
         L.k0[lane][1] = k0[1];
         L.k0[lane][2] = k0[2];
-        normal_backward_patch(row, k0, G, x, v, nm, dz);
+        if constexpr (TAPE) {
+          const float a0 = a.tau * sigmoidf(-a.tau * E.s0) * (E.gdl_prev - E.gdl);
+          if (a0 != 0.f) patch_add(row, k0, x, G.R, G.inv_h, a0);
+        }
+        if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch(row, k0, G, x, v, nm, dz);
       }
       wave_sync();
       sdf_patch_flush(L.u.sc, L.k0, n, lane, G.R, a.g_sdf);
@@ -514,6 +549,125 @@ __global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs
 }
 
 // ---------------------------------------------------------------------------
+// taped schedule: probe-cell counts of the recorded entries, and the per-ray
+// walk that runs before the shading pass (the colours come from the forward)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BLOCK) tape_count_kernel(RenderArgs a, BwdWs ws) {
+  const int lane = threadIdx.x & 63;
+  const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
+  const double inv_hp = 0.5 * (a.P - 1);
+  for (int64_t e0 = ((int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 64; e0 < total;
+       e0 += (int64_t)gridDim.x * WAVES * 64) {
+    const int64_t e = e0 + lane;
+    bool counted = false;
+    int pc = 0;
+    if (e < total) {
+      const BwdEntry& E = ws.entries[e];
+      counted = E.lw >= 0;
+      const double xs[3] = {E.x[0], E.x[1], E.x[2]};
+      if (counted) pc = cell_d(xs, a.P, inv_hp).base;
+    }
+    for_each_key_group(counted, pc, [&](int k, int leader, uint64_t grp) {
+      if (lane == leader) atomicAdd(ws.pcount + k, (int)__popcll(grp));
+    });
+  }
+}
+
+struct WalkLds {
+  RayD ray[64];
+  int own[64];
+  int si[64];
+  float w[64];
+  float T[64];
+  float C[64][3];
+  float gdl[64];
+  int nin[64];
+};
+
+__global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws) {
+  __shared__ WalkLds lds[WAVES];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  WalkLds& L = lds[wv];
+  const unsigned lw = xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;
+  if (lw >= ws.n_waves || ws.overflow[lw] != 0) return;
+  const int cnt = ws.count[lw];
+  if (cnt == 0) return;
+  const int64_t ray = (int64_t)lw * 64 + lane;
+  const bool valid = ray < a.B;
+  float ro[3] = {0.f, 0.f, 0.f}, rd[3] = {0.f, 0.f, 1.f}, dL[3] = {0.f, 0.f, 0.f};
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ro[k] = a.rays_o[3 * ray + k];
+      rd[k] = a.rays_d[3 * ray + k];
+      dL[k] = a.dL[3 * ray + k];
+    }
+  }
+  RayD r;
+  ray_setup_d(ro[0], ro[1], ro[2], rd[0], rd[1], rd[2], a.N, r);
+  L.ray[lane] = r;
+  const int R = a.R;
+  const double inv_h = 0.5 * (a.R - 1);
+  float Rc[3] = {0.f, 0.f, 0.f};  // remaining colour of this lane's ray
+  int nx_i = -2, nx_slot = -1;    // the ray's entry processed last (the next in sample order)
+  int base = ws.last[lw];
+  int n = cnt - 64 * ((cnt - 1) / 64);
+  while (base >= 0) {  // wave-uniform
+    wave_sync();
+    int key = 0, prev = -1;
+    float s1 = 0.f;
+    if (lane < n) {
+      const BwdEntry& E = ws.entries[base + lane];
+      key = E.key;
+      prev = E.prev;
+      s1 = E.s1;
+      L.own[lane] = key & 63;
+      L.si[lane] = key >> 6;
+      L.w[lane] = E.w;
+      L.T[lane] = E.T;
+      L.C[lane][0] = E.C[0];
+      L.C[lane][1] = E.C[1];
+      L.C[lane][2] = E.C[2];
+    }
+    wave_sync();
+    for (int k = n - 1; k >= 0; --k) {
+      if (lane == L.own[k]) {
+        const float w = L.w[k], T = L.T[k];
+        const float c0 = L.C[k][0], c1 = L.C[k][1], c2 = L.C[k][2];
+        Rc[0] = fmaf(w, c0, Rc[0]);
+        Rc[1] = fmaf(w, c1, Rc[1]);
+        Rc[2] = fmaf(w, c2, Rc[2]);
+        const float g = dL[0] * (Rc[0] - T * c0) + dL[1] * (Rc[1] - T * c1) + dL[2] * (Rc[2] - T * c2);
+        const int si = L.si[k];
+        const bool nin = nx_i == si + 1;
+        if (nin) ws.entries[nx_slot].gdl_prev = g;
+        L.gdl[k] = g;
+        L.nin[k] = nin ? 1 : 0;
+        nx_i = si;
+        nx_slot = base + k;
+      }
+    }
+    wave_sync();
+    if (lane < n) {
+      const float gdl = L.gdl[lane];
+      const int nin = L.nin[lane];
+      BwdEntry& E = ws.entries[base + lane];
+      E.gdl = gdl;
+      E.next_in = nin;
+      if (!nin) {
+        // s_{i+1} belongs to no entry: its share of the opacity gradient goes here
+        const RayD& rr = L.ray[key & 63];
+        double x1[3];
+        sample_pos(rr, sample_t(rr, (key >> 6) + 1), x1);
+        scatter8(a.g_sdf, R, cell_d(x1, R, inv_h), a.tau * sigmoidf(-a.tau * s1) * gdl);
+      }
+    }
+    base = __shfl(prev, 0, 64);
+    n = 64;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // pass 5: per-ray walk and the opacity gradient
 // ---------------------------------------------------------------------------
 struct AlphaLds {
@@ -592,30 +746,44 @@ __global__ void __launch_bounds__(BLOCK) bwd_alpha_kernel(RenderArgs a, BwdWs ws
   }
 }
 
-hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in, int sdf_dt,
-                                        int feat_dt, int mlp_dt, int n_sh, hipStream_t s) {
+hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in, bool from_tape,
+                                        int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
+                                        hipStream_t s) {
   BwdWs ws = ws_in;
   // probe gradients go through the cell bins (one lane per node coefficient:
   // n_sh * n_ang <= 64 for every compiled SH order)
   ws.probe_bins = (a.g_probes && !(a.flags & FLAG_NO_FA)) ? 1 : 0;
   const dim3 wgrid((unsigned)((a.B + BLOCK - 1) / BLOCK));
-  const int64_t nclear = max(ws.n_waves, ws.probe_bins ? ws.P3 : (int64_t)0);
-  hipLaunchKernelGGL(bwd_ws_clear_kernel, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, s,
-                     ws);
-  if (sdf_dt == 0)
-    hipLaunchKernelGGL(bwd_march_kernel<float>, wgrid, dim3(BLOCK), 0, s, a, ws);
-  else
-    hipLaunchKernelGGL(bwd_march_kernel<_Float16>, wgrid, dim3(BLOCK), 0, s, a, ws);
+  hipError_t e = launch_clear(ws, from_tape ? 0 : 1, s);
+  if (e != hipSuccess) return e;
+  if (!from_tape) {
+    if (sdf_dt == 0)
+      hipLaunchKernelGGL(bwd_march_kernel<float>, wgrid, dim3(BLOCK), 0, s, a, ws);
+    else
+      hipLaunchKernelGGL(bwd_march_kernel<_Float16>, wgrid, dim3(BLOCK), 0, s, a, ws);
+  } else if (ws.probe_bins) {
+    const int64_t cw = (ws.cap + 63) / 64;
+    const dim3 cgrid((unsigned)max((int64_t)1, min((cw + WAVES - 1) / WAVES, (int64_t)2048)));
+    hipLaunchKernelGGL(tape_count_kernel, cgrid, dim3(BLOCK), 0, s, a, ws);
+  }
   if (ws.probe_bins) {
     hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(scan_offsets_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);
   }
+  if (from_tape && a.g_sdf) hipLaunchKernelGGL(tape_walk_kernel, wgrid, dim3(BLOCK), 0, s, a, ws);
   // enough waves to fill the chip; each loops over batches of 64 entries
   const int64_t want = (ws.cap + 64 * WAVES - 1) / (64 * WAVES);
   const dim3 sgrid((unsigned)max((int64_t)1, min(want, (int64_t)1024)));
-  PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,
-      hipLaunchKernelGGL((bwd_shade_kernel<ST, FT, NSH, M>), sgrid, dim3(BLOCK), 0, s, a, ws))));
+  if (from_tape) {
+    PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,
+        hipLaunchKernelGGL((bwd_shade_kernel<ST, FT, NSH, M, true>), sgrid, dim3(BLOCK), 0, s, a,
+                           ws))));
+  } else {
+    PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,
+        hipLaunchKernelGGL((bwd_shade_kernel<ST, FT, NSH, M, false>), sgrid, dim3(BLOCK), 0, s, a,
+                           ws))));
+  }
   if (ws.probe_bins) {
     // one wave per occupied cell (the count is on the device: enough waves for
     // a dense band, each looping)
@@ -624,8 +792,8 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
     PSDF_SH_SWITCH(n_sh,
         hipLaunchKernelGGL((probe_reduce_kernel<NSH>), pgrid, dim3(BLOCK), 0, s, a, ws));
   }
-  if (a.g_sdf) hipLaunchKernelGGL(bwd_alpha_kernel, wgrid, dim3(BLOCK), 0, s, a, ws);
-  hipError_t e = hipGetLastError();
+  if (!from_tape && a.g_sdf) hipLaunchKernelGGL(bwd_alpha_kernel, wgrid, dim3(BLOCK), 0, s, a, ws);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   // waves that did not fit
   RenderArgs f = a;

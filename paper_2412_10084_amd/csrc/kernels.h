@@ -37,7 +37,7 @@ struct RenderArgs {
   const int* todo;  // backward: nonzero entries select the 64-ray waves to run; nullptr = all
 };
 
-// One shaded sample of the entry-parallel backward (80 bytes).
+// One shaded sample of the entry-parallel backward (160 bytes).
 struct BwdEntry {
   double x[3];    // sample position
   float v[3];     // view direction (-unit ray direction)
@@ -47,7 +47,16 @@ struct BwdEntry {
   int key;        // (sample index << 6) | lane of the ray in its wave
   int lw;         // the ray's 64-ray wave; -1: a slot that holds no sample
   int prev;       // first slot of the previous chunk of the same wave, -1 if none
-  float C[3];     // colour of the sample (written by the shading pass)
+  float C[3];     // colour of the sample
+  // recorded by a forward that writes a tape
+  float z[10];    // MLP inputs [F_s, F_a, c, c^2, c^4]
+  float nrm[3];   // unit FD normal
+  float gn;       // |FD gradient|
+  // written by the per-ray walk of a taped backward
+  float gdl;      // dL/d dl_i
+  float gdl_prev; // dL/d dl_{i-1} when sample i-1 of the ray is an entry, else 0
+  int next_in;    // 1: sample i+1 of the ray is an entry
+  float pad[3];
 };
 
 // Gradient record of one shaded sample for the probe grid, placed in probe-cell order.
@@ -132,12 +141,14 @@ struct StepArgs {
 };
 
 // dtype codes as in the public header
-hipError_t launch_render_forward(const RenderArgs& a, int sdf_dt, int feat_dt, int mlp_dt,
-                                 int n_sh, hipStream_t s);
+hipError_t launch_render_forward(const RenderArgs& a, const BwdWs* tape, int sdf_dt, int feat_dt,
+                                 int mlp_dt, int n_sh, hipStream_t s);
+hipError_t launch_bwd_ws_clear(const BwdWs& ws, hipStream_t s);
 hipError_t launch_render_backward(const RenderArgs& a, int sdf_dt, int feat_dt, int mlp_dt,
                                   int n_sh, hipStream_t s);
-hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws, int sdf_dt,
-                                        int feat_dt, int mlp_dt, int n_sh, hipStream_t s);
+hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws, bool from_tape,
+                                        int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
+                                        hipStream_t s);
 hipError_t launch_sphere_trace(const TraceArgs& a, int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
                                hipStream_t s);
 hipError_t launch_l1_loss(int64_t B, const float* rgb, const float* target, float* dL,

@@ -9,6 +9,11 @@
 // spatial features, probe coefficients contracted with the SH basis of the
 // ray's view direction, MLP).  The weighted colours are then summed per ray by
 // the ray's own lane, in sample order.
+//
+// Training forwards may record a tape: every batch of shaded samples is written
+// to the caller's workspace as one chunk of entries (position, weights, s_i,
+// s_{i+1}, colour, MLP inputs and normal), so that the backward neither
+// re-marches nor re-reads the shading inputs.
 #include "dispatch.h"
 #include "shade.h"
 
@@ -19,13 +24,23 @@ struct FwdLds {
   int next[RING];   // sequence number of the same ray's next entry
   int key[RING];    // (sample index << 6) | ray lane
   float w[RING];    // compositing weight T_i alpha_i
+  float T[RING];    // transmittance T_i
+  float s0[RING];   // s_i
+  float s1[RING];   // s_{i+1}
   float wc[RING][3];
+};
+
+// tape state of a wave (wave-uniform)
+struct TapeW {
+  int last = -1, total = 0;
+  bool ovf = false;
 };
 
 template <typename ST, typename FT, int NSH, int M>
 __device__ __forceinline__ void fwd_batch(const RenderArgs& a, const Geo& G, FwdLds& L,
                                           MlpLds<M>& ML, const MlpFrag<M>& frag, int lane, int head,
-                                          int n, float rgb[3], int& my_first, int& my_cnt) {
+                                          int n, float rgb[3], int& my_first, int& my_cnt,
+                                          const BwdWs& ws, bool tape, unsigned lw, TapeW& tw) {
   const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
   const FT* __restrict__ feat = static_cast<const FT*>(a.feat);
   const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
@@ -36,16 +51,20 @@ __device__ __forceinline__ void fwd_batch(const RenderArgs& a, const Geo& G, Fwd
 #pragma unroll
   for (int j = 0; j < NIN; ++j) z[j] = 0.f;
   float w = 0.f;
+  int key = 0;
+  double x[3] = {0.0, 0.0, 0.0};
+  float v[3] = {0.f, 0.f, 0.f};
+  Normal nm{};
   if (ve) {
-    const int key = L.key[slot];
+    key = L.key[slot];
     const RayD r = L.ray[key & 63];
     w = L.w[slot];
-    double x[3];
     sample_pos(r, sample_t(r, key >> 6), x);
-    const float v[3] = {(float)-r.d[0], (float)-r.d[1], (float)-r.d[2]};
+    v[0] = (float)-r.d[0];
+    v[1] = (float)-r.d[1];
+    v[2] = (float)-r.d[2];
     float Y[NSH];
     sh_basis<NSH>(v[0], v[1], v[2], Y);
-    Normal nm;
     shade_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, Y, z, nm);
   }
   float out[3];
@@ -55,10 +74,56 @@ __device__ __forceinline__ void fwd_batch(const RenderArgs& a, const Geo& G, Fwd
   } else {
     mlp_wave<M>(frag, ML, lane, z, out);
   }
+  const float C0 = sigmoidf(out[0]), C1 = sigmoidf(out[1]), C2 = sigmoidf(out[2]);
   if (ve) {
-    L.wc[slot][0] = w * sigmoidf(out[0]);
-    L.wc[slot][1] = w * sigmoidf(out[1]);
-    L.wc[slot][2] = w * sigmoidf(out[2]);
+    L.wc[slot][0] = w * C0;
+    L.wc[slot][1] = w * C1;
+    L.wc[slot][2] = w * C2;
+  }
+  if (tape && !tw.ovf) {
+    // one chunk of entries per batch, chunks of the wave linked backwards
+    unsigned long long got = 0;
+    if (lane == 0) got = atomicAdd(ws.counter, (unsigned long long)n);
+    const int64_t base = (int64_t)__shfl(got, 0, 64);
+    if (base + n > ws.cap) {
+      // no room: the backward runs this wave with the fused kernel
+      if (base + lane < ws.cap && lane < n) ws.entries[base + lane].lw = -1;
+      tw.ovf = true;
+    } else {
+      if (ve) {
+        BwdEntry e;
+        e.x[0] = x[0];
+        e.x[1] = x[1];
+        e.x[2] = x[2];
+        e.v[0] = v[0];
+        e.v[1] = v[1];
+        e.v[2] = v[2];
+        e.w = w;
+        e.T = L.T[slot];
+        e.s0 = L.s0[slot];
+        e.s1 = L.s1[slot];
+        e.ray = (int)(lw * 64u) + (key & 63);
+        e.key = key;
+        e.lw = (int)lw;
+        e.prev = tw.last;
+        e.C[0] = C0;
+        e.C[1] = C1;
+        e.C[2] = C2;
+#pragma unroll
+        for (int j = 0; j < NIN; ++j) e.z[j] = z[j];
+        e.nrm[0] = nm.n[0];
+        e.nrm[1] = nm.n[1];
+        e.nrm[2] = nm.n[2];
+        e.gn = nm.gn;
+        e.gdl = 0.f;
+        e.gdl_prev = 0.f;
+        e.next_in = 0;
+        e.pad[0] = e.pad[1] = e.pad[2] = 0.f;
+        ws.entries[base + lane] = e;
+      }
+      tw.last = (int)base;
+      tw.total += n;
+    }
   }
   wave_sync();
   // each ray's lane adds its own entries of this batch, in sample order
@@ -73,7 +138,7 @@ __device__ __forceinline__ void fwd_batch(const RenderArgs& a, const Geo& G, Fwd
 }
 
 template <typename ST, typename FT, int NSH, int M>
-__global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a) {
+__global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a, BwdWs ws, int tape) {
   __shared__ FwdLds lds[WAVES];
   __shared__ MlpLds<M> mlds[M == MLP_F32 ? 1 : WAVES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -84,8 +149,10 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a) {
   MlpFrag<M> frag;
   if constexpr (M != MLP_F32) mlp_frag_load<M>(a.mlp, lane, frag);
 
-  const int64_t ray = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  const unsigned lw = xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;  // this wave's 64 rays
+  const int64_t ray = (int64_t)lw * 64 + lane;
   const bool valid = ray < a.B;
+  TapeW tw;
   float ro[3] = {0.f, 0.f, 0.f}, rd[3] = {0.f, 0.f, 1.f};
   if (valid) {
 #pragma unroll
@@ -120,7 +187,8 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a) {
       }
       const uint64_t mask = __ballot(shaded);
       if (shaded) {
-        const float w = expf(logT) * -expm1f(dl);
+        const float T = expf(logT);
+        const float w = T * -expm1f(dl);
         wsum += w;
         depth = fmaf(w, (float)(sample_t(r, i) + 0.5 * r.dt), depth);
         logT += dl;
@@ -128,6 +196,9 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a) {
         const int slot = seq & (RING - 1);
         L.key[slot] = (i << 6) | lane;
         L.w[slot] = w;
+        L.T[slot] = T;
+        L.s0[slot] = s_i;
+        L.s1[slot] = s_n;
         if (my_cnt > 0) L.next[my_last & (RING - 1)] = seq;
         else my_first = seq;
         my_last = seq;
@@ -138,7 +209,8 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a) {
     const int pending = tail - head;
     if (pending >= 64 || (!stepping && pending > 0)) {
       const int n = min(64, pending);
-      fwd_batch<ST, FT, NSH, M>(a, G, L, ML, frag, lane, head, n, rgb, my_first, my_cnt);
+      fwd_batch<ST, FT, NSH, M>(a, G, L, ML, frag, lane, head, n, rgb, my_first, my_cnt, ws,
+                                tape != 0, lw, tw);
       head += n;
     } else if (!stepping) {
       break;
@@ -159,13 +231,26 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a) {
       a.depth_wsum[2 * ray + 1] = wsum;
     }
   }
+  if (tape && lane == 0 && lw < ws.n_waves) {
+    ws.count[lw] = tw.ovf ? 0 : tw.total;
+    ws.last[lw] = tw.ovf ? -1 : tw.last;
+    if (tw.ovf) ws.overflow[lw] = 1;
+  }
 }
 
-hipError_t launch_render_forward(const RenderArgs& a, int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
-                                 hipStream_t s) {
+hipError_t launch_render_forward(const RenderArgs& a, const BwdWs* tape, int sdf_dt, int feat_dt,
+                                 int mlp_dt, int n_sh, hipStream_t s) {
   const dim3 grid((unsigned)((a.B + BLOCK - 1) / BLOCK));
+  BwdWs ws{};
+  if (tape) {
+    ws = *tape;
+    ws.probe_bins = 0;
+    const hipError_t e = launch_bwd_ws_clear(ws, s);
+    if (e != hipSuccess) return e;
+  }
+  const int on = tape ? 1 : 0;
   PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,
-      hipLaunchKernelGGL((render_fwd_kernel<ST, FT, NSH, M>), grid, dim3(BLOCK), 0, s, a))));
+      hipLaunchKernelGGL((render_fwd_kernel<ST, FT, NSH, M>), grid, dim3(BLOCK), 0, s, a, ws, on))));
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ def rays(views: int, W: int, H: int, order: str = "image"):
     return wl.camera_rays(cams, W, H, order)
 
 
-def gpu_forward(fld, o, d, N, tau=64.0, skip=0.0, flags=0):
+def gpu_forward(fld, o, d, N, tau=64.0, skip=0.0, flags=0, tape=None):
     import paper_2412_10084_amd as ps
     t = torch()
     B = o.shape[0]
@@ -63,16 +63,16 @@ def gpu_forward(fld, o, d, N, tau=64.0, skip=0.0, flags=0):
     rgb = t.empty((B, 3), device="cuda")
     aux = t.empty((B, 4), device="cuda")
     dw = t.empty((B, 2), device="cuda")
-    ps.render_forward(fld, ps.RenderOpts(N, tau, skip, flags), do, dd, rgb, aux, dw)
+    ps.render_forward(fld, ps.RenderOpts(N, tau, skip, flags), do, dd, rgb, aux, dw, tape=tape)
     t.cuda.synchronize()
     return dict(rgb=rgb.cpu().numpy(), aux=aux.cpu().numpy(), depth_wsum=dw.cpu().numpy(),
                 dev=(do, dd, rgb, aux))
 
 
 def gpu_backward(fld, o_dev, d_dev, aux_dev, dL, N, tau=64.0, skip=0.0, flags=0, workspace=None,
-                 groups=("sdf", "feat", "probes", "mlp")):
+                 groups=("sdf", "feat", "probes", "mlp"), from_tape=False):
     """workspace: None (fused schedule), an int (entry-parallel schedule with room for that
-    many shaded samples) or a device buffer."""
+    many shaded samples) or a device buffer (with from_tape: the forward's tape)."""
     import paper_2412_10084_amd as ps
     t = torch()
     g = dict(sdf=t.zeros(fld.sdf.shape, device="cuda"), feat=t.zeros(fld.feat.shape, device="cuda"),
@@ -80,7 +80,8 @@ def gpu_backward(fld, o_dev, d_dev, aux_dev, dL, N, tau=64.0, skip=0.0, flags=0,
     if isinstance(workspace, int):
         workspace = ps.backward_workspace(o_dev.shape[0], fld.probes.shape[0], workspace)
     ps.render_backward(fld, ps.RenderOpts(N, tau, skip, flags), o_dev, d_dev, aux_dev,
-                       dev(dL.astype(np.float32)), {k: g[k] for k in groups}, workspace=workspace)
+                       dev(dL.astype(np.float32)), {k: g[k] for k in groups}, workspace=workspace,
+                       from_tape=from_tape)
     t.cuda.synchronize()
     return {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
 

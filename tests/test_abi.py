@@ -44,7 +44,7 @@ def _fwd(f, o, B=0):
     L = ps.lib()
     return L.psdf_render_forward(C.byref(f) if f is not None else None,
                                  C.byref(o) if o is not None else None, B, FAKE, FAKE, FAKE, None,
-                                 None, None)
+                                 None, None, 0, None)
 
 
 def test_empty_batch_ok():
@@ -83,21 +83,27 @@ def test_null_descriptors_and_negative_batch():
     assert _fwd(_field(), _opts(), -1) == ps.EINVAL
     L = ps.lib()
     assert L.psdf_render_forward(C.byref(_field()), C.byref(_opts()), 10, None, FAKE, FAKE, None,
-                                 None, None) == ps.EINVAL
+                                 None, None, 0, None) == ps.EINVAL
     assert L.psdf_render_forward(C.byref(_field()), C.byref(_opts()), 10, FAKE + 1, FAKE, FAKE,
-                                 None, None, None) == ps.EALIGN
+                                 None, None, None, 0, None) == ps.EALIGN
+    # a tape must be aligned and hold at least the per-wave arrays
+    need = ps.backward_workspace_bytes(10, 16, 0)
+    assert L.psdf_render_forward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, FAKE, None,
+                                 None, FAKE + 64, need, None) == ps.EALIGN
+    assert L.psdf_render_forward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, FAKE, None,
+                                 None, FAKE, need - 1, None) == ps.EINVAL
 
 
 def test_backward_requires_grads_and_aux():
     L = ps.lib()
     g = ps._Grads(FAKE, FAKE, FAKE, FAKE)
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, FAKE, FAKE,
-                                  None, None, 0, None) == ps.EINVAL
+                                  None, None, 0, 0, None) == ps.EINVAL
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, None, FAKE,
-                                  C.byref(g), None, 0, None) == ps.EINVAL
+                                  C.byref(g), None, 0, 0, None) == ps.EINVAL
     g.probes = FAKE + 2
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, FAKE, FAKE,
-                                  C.byref(g), None, 0, None) == ps.EALIGN
+                                  C.byref(g), None, 0, 0, None) == ps.EALIGN
 
 
 def test_backward_workspace_validation():
@@ -106,21 +112,26 @@ def test_backward_workspace_validation():
     B = 1000
     need = ps.backward_workspace_bytes(B, 16, 0)
     assert need > 0
-    assert ps.backward_workspace_bytes(B, 16, 10) == need + 10 * 128
+    assert ps.backward_workspace_bytes(B, 16, 10) == need + 10 * 208
     assert ps.backward_workspace_bytes(B, 32, 0) > need
     # misaligned workspace
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), B, FAKE, FAKE, FAKE, FAKE,
-                                  C.byref(g), FAKE + 64, need, None) == ps.EALIGN
+                                  C.byref(g), FAKE + 64, need, 0, None) == ps.EALIGN
     # too small for the per-wave arrays
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), B, FAKE, FAKE, FAKE, FAKE,
-                                  C.byref(g), FAKE, need - 1, None) == ps.EINVAL
+                                  C.byref(g), FAKE, need - 1, 0, None) == ps.EINVAL
     assert "workspace" in ps.last_error()
     assert L.psdf_backward_workspace_bytes(-1, 16, 0) == -1
     assert L.psdf_backward_workspace_bytes(10, 16, -5) == -1
     assert L.psdf_backward_workspace_bytes(10, 1, 0) == -1
+    # unknown flags; a tape backward without a workspace
+    assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), B, FAKE, FAKE, FAKE, FAKE,
+                                  C.byref(g), FAKE, need, 2, None) == ps.EINVAL
+    assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), B, FAKE, FAKE, FAKE, FAKE,
+                                  C.byref(g), None, 0, ps.BWD_FROM_TAPE, None) == ps.EINVAL
     # B = 0 with a workspace is a no-op
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), 0, FAKE, FAKE, FAKE, FAKE,
-                                  C.byref(g), FAKE, 0, None) == ps.OK
+                                  C.byref(g), FAKE, 0, 0, None) == ps.OK
 
 
 def _step_args(**kw):

@@ -135,3 +135,92 @@ def test_split_backward_train256_full_size_sampled():
     g_ref = oracle.render_backward(of, o[sel], d[sel], dL[sel], w.n_samples,
                                    skip_voxels=w.skip_voxels)
     _check(g, g_ref)
+
+
+# ---------------------------------------------------------------------------
+# taped schedule: the forward records its shaded samples, the backward reads them
+# ---------------------------------------------------------------------------
+def _tape_run(f, o, d, dL, N, skip, cap, flags=0, groups=("sdf", "feat", "probes", "mlp"),
+              feat_half=False, mlp_dtype=0, bounds=True):
+    import paper_2412_10084_amd as ps
+    fld = device_field(f, feat_half=feat_half, mlp_dtype=mlp_dtype)
+    if bounds:
+        fld.bounds = ps.sdf_bounds(fld.sdf)
+    tape = ps.backward_workspace(o.shape[0], fld.probes.shape[0], cap)
+    plain = gpu_forward(fld, o, d, N, skip=skip, flags=flags)
+    fw = gpu_forward(fld, o, d, N, skip=skip, flags=flags, tape=tape)
+    for k in ("rgb", "aux", "depth_wsum"):  # recording changes no output
+        np.testing.assert_array_equal(fw[k], plain[k], err_msg=k)
+    do, dd, _, aux = fw["dev"]
+    g = gpu_backward(fld, do, dd, aux, dL, N, skip=skip, flags=flags, workspace=tape,
+                     groups=groups, from_tape=True)
+    return fld, fw, g
+
+
+@pytest.mark.parametrize("cap", [1 << 20, 1000, 64, 0])
+def test_tape_backward_matches_oracle(cap):
+    N, skip = 96, 4.0
+    f, o, d, dL, g_ref = _case(N, skip)
+    fld, fw, g = _tape_run(f, o, d, dL, N, skip, cap)
+    _check(g, g_ref)
+    do, dd, _, aux = fw["dev"]
+    g_fused = gpu_backward(fld, do, dd, aux, dL, N, skip=skip)
+    for k, t in TOL:
+        assert norm_rel(g[k], g_fused[k]) <= t, k
+
+
+@pytest.mark.parametrize("flags", [1, 2, 4])
+def test_tape_backward_flags(flags):
+    N, skip = 64, 2.0
+    f, o, d, dL, g_ref = _case(N, skip, B=2048, flags=flags, shape="torus")
+    _, _, g = _tape_run(f, o, d, dL, N, skip, 1 << 16, flags=flags)
+    _check(g, g_ref)
+
+
+def test_tape_backward_no_skip_and_partial_groups():
+    N = 64
+    f, o, d, dL, g_ref = _case(N, 0.0, B=1500)
+    _, _, g = _tape_run(f, o, d, dL, N, 0.0, 1 << 18, groups=("sdf", "probes"), bounds=False)
+    _check(g, g_ref, (("sdf", FP32_GRAD_REL), ("probes", FP32_GRAD_REL)))
+    assert not g["feat"].any() and not g["mlp"].any()
+    _, _, g = _tape_run(f, o, d, dL, N, 0.0, 1 << 18, groups=("feat", "mlp"), bounds=False)
+    _check(g, g_ref, (("feat", FP32_GRAD_REL), ("mlp", FP32_MLP_GRAD_REL)))
+    assert not g["sdf"].any()
+
+
+@pytest.mark.parametrize("mlp_dt,gtol", [(1, F16_GRAD_REL), (2, BF16_GRAD_REL)])
+def test_tape_backward_mixed(mlp_dt, gtol):
+    f = scene(0, 64, 16)
+    ft = scene(1, 64, 16, shape="torus")
+    o, d = rays(8, 32, 16)
+    N = 64
+    of_h = oracle.field_from(f, half=True)
+    ref = oracle.render_forward(of_h, o, d, N)
+    tgt = oracle.render_forward(oracle.field_from(ft), o, d, N)["rgb"]
+    _, dL = oracle.l1_loss(ref["rgb"], tgt)
+    g_ref = oracle.render_backward(of_h, o, d, dL, N)
+    _, _, g = _tape_run(f, o, d, dL, N, 0.0, 1 << 18, feat_half=True, mlp_dtype=mlp_dt,
+                        bounds=False)
+    for k in ("sdf", "feat", "probes", "mlp"):
+        e = norm_rel(g[k], g_ref[k])
+        assert e <= gtol, f"{k}: {e:.3g} > {gtol}"
+
+
+def test_tape_backward_train256_full_size_sampled():
+    """The benchmark's launch: full train256 batch, brick bounds, forward tape with
+    room for 8 shaded samples per ray, backward from the tape."""
+    w = wl.WORKLOADS["train256"]
+    f = scene(0, w.R, w.P)
+    o, d = rays(w.views, w.W, w.H)
+    rng = np.random.default_rng(12)
+    idx = np.sort(rng.choice(o.shape[0], 3000, replace=False))
+    of = oracle.field_from(f)
+    ref = oracle.render_forward(of, o[idx], d[idx], w.n_samples, skip_voxels=w.skip_voxels)
+    keep = ref["margin"] > SKIP_MARGIN
+    sel = idx[keep][:1500]
+    dL = np.zeros((o.shape[0], 3))
+    dL[sel] = rng.choice([-1.0, 1.0], size=(sel.size, 3)) / (3.0 * o.shape[0])
+    _, _, g = _tape_run(f, o, d, dL, w.n_samples, w.skip_voxels, 8 * o.shape[0])
+    g_ref = oracle.render_backward(of, o[sel], d[sel], dL[sel], w.n_samples,
+                                   skip_voxels=w.skip_voxels)
+    _check(g, g_ref)
