@@ -70,6 +70,111 @@ __device__ __forceinline__ void feat_scatter_wave(float (*sc)[65], int* fb, bool
   wave_sync();
 }
 
+// ---------------------------------------------------------------------------
+// Box accumulation: when the wave's samples are spatially compact, their SDF
+// (or feature) gradients are added into one LDS box of nodes with LDS atomics,
+// and the box is flushed once, each row of nodes as a contiguous run of lanes.
+// Call with the whole wave; returns false (nothing done) when the box does not
+// fit, and the caller then takes the per-sample path.
+// ---------------------------------------------------------------------------
+constexpr int BOXCAP = 64 * 65;  // floats
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+// nrows rows of row_len floats; row r holds nodes (ox + x / C, oy + r % ey, oz + r / ey)
+__device__ __forceinline__ void box_flush(const float* box, int row_len, int nrows, int ey, int ox,
+                                          int oy, int oz, int R, int C, float* g, int lane) {
+  int lpr = 1;
+  while (lpr < row_len && lpr < 64) lpr <<= 1;  // lanes per row
+  const int sh = __builtin_ctz(lpr), rows_per = 64 >> sh;
+  for (int r0 = 0; r0 < nrows; r0 += rows_per) {
+    const int r = r0 + (lane >> sh);
+    if (r < nrows) {
+      const int iz = r / ey, iy = r - iz * ey;
+      const int gy = oy + iy, gz = oz + iz;
+      const bool row_in = gy >= 0 && gy < R && gz >= 0 && gz < R;
+      for (int xx = lane & (lpr - 1); xx < row_len; xx += lpr) {
+        const float v = box[r * row_len + xx];
+        const int gx = ox + xx / C;
+        if (v != 0.f && row_in && gx >= 0 && gx < R)
+          atomic_add_f32(g + ((int64_t)(gz * R + gy) * R + ox) * C + xx, v);
+      }
+    }
+  }
+}
+
+// SDF: the opacity gradient at s_i (coefficient a0) and the normal path
+__device__ __forceinline__ bool sdf_box_wave(float* box, int lane, bool ve, const double x[3],
+                                             const float v[3], const Normal& nm,
+                                             const float dz[NIN], float a0, const Geo& G,
+                                             float* g_sdf) {
+  if (!wave_any(ve)) return true;
+  int k0[3] = {0, 0, 0};
+  if (ve) cell_k(x, G.R, G.inv_h, k0);
+  int lo[3], ext[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_min_i(ve ? k0[a] : 0x7FFFFFFF);
+    ext[a] = wave_max_i(ve ? k0[a] : -0x7FFFFFFF) - lo[a] + 4;  // nodes lo-1 .. hi+2
+  }
+  if ((int64_t)ext[0] * ext[1] * ext[2] > BOXCAP) return false;
+  const int vol = ext[0] * ext[1] * ext[2];
+  for (int i = lane; i < vol; i += 64) box[i] = 0.f;
+  wave_sync();
+  const PatchDst D{box, lo[0] - 1, lo[1] - 1, lo[2] - 1, ext[0], ext[0] * ext[1]};
+  if (ve) {
+    if (a0 != 0.f) patch_add<true>(D, k0, x, G.R, G.inv_h, a0);
+    if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch<true>(D, k0, G, x, v, nm, dz);
+  }
+  wave_sync();
+  box_flush(box, ext[0], ext[1] * ext[2], ext[1], D.ox, D.oy, D.oz, G.R, 1, g_sdf, lane);
+  wave_sync();
+  return true;
+}
+
+// spatial features: 8 corners x 3 channels per sample
+__device__ __forceinline__ bool feat_box_wave(float* box, int lane, bool ve, const double x[3],
+                                              const Cell& cs, const float dz[NIN], const Geo& G,
+                                              float* g_feat) {
+  if (!wave_any(ve)) return true;
+  int k[3] = {0, 0, 0};
+  if (ve) cell_k(x, G.R, G.inv_h, k);
+  int lo[3], ext[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_min_i(ve ? k[a] : 0x7FFFFFFF);
+    ext[a] = wave_max_i(ve ? k[a] : -0x7FFFFFFF) - lo[a] + 2;  // nodes lo .. hi+1
+  }
+  if ((int64_t)ext[0] * ext[1] * ext[2] * NF > BOXCAP) return false;
+  const int vol = ext[0] * ext[1] * ext[2];
+  for (int i = lane; i < vol * NF; i += 64) box[i] = 0.f;
+  wave_sync();
+  if (ve) {
+    float wc[8];
+    corner_w(cs, wc);
+    const int b = ((k[2] - lo[2]) * ext[1] + (k[1] - lo[1])) * ext[0] + (k[0] - lo[0]);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int o = b + (c & 1) + ((c >> 1) & 1) * ext[0] + ((c >> 2) & 1) * ext[0] * ext[1];
+#pragma unroll
+      for (int ch = 0; ch < NF; ++ch) atomicAdd(&box[o * NF + ch], wc[c] * dz[ch]);
+    }
+  }
+  wave_sync();
+  box_flush(box, ext[0] * NF, ext[1] * ext[2], ext[1], lo[0], lo[1], lo[2], G.R, NF, g_feat, lane);
+  wave_sync();
+  return true;
+}
+
 // MLP weight gradients of the wave's entries, summed on MFMA (K = samples)
 template <int M>
 __device__ __forceinline__ void mlp_dw_wave(DwLds& D, int lane, bool ve, const float z[NIN],

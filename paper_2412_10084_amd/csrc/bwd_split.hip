@@ -41,7 +41,7 @@ int64_t nsum_of(int P) { return (p3_of(P) + kScan - 1) / kScan; }
 int64_t fixed_bytes(int64_t B, int P) {
   return kHead + 3 * al256(n_waves_of(B) * 4) + 3 * al256(p3_of(P) * 4) + al256(nsum_of(P) * 4);
 }
-constexpr int64_t kPerSample = (int64_t)sizeof(BwdEntry) + (int64_t)sizeof(ProbeRec);
+constexpr int64_t kPerSample = (int64_t)sizeof(BwdEntry) + (int64_t)sizeof(ProbeRec) + 4;
 }  // namespace
 
 int64_t bwd_ws_bytes(int64_t B, int P, int64_t cap) { return fixed_bytes(B, P) + cap * kPerSample; }
@@ -68,10 +68,14 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   w.cap = bwd_ws_capacity(B, P, bytes);
   w.entries = reinterpret_cast<BwdEntry*>(p + fixed_bytes(B, P));
   w.precs = reinterpret_cast<ProbeRec*>(p + fixed_bytes(B, P) + w.cap * (int64_t)sizeof(BwdEntry));
+  w.perm = reinterpret_cast<int*>(p + fixed_bytes(B, P) +
+                                  w.cap * (int64_t)(sizeof(BwdEntry) + sizeof(ProbeRec)));
+  w.nsorted = reinterpret_cast<int*>(p + 16);
   w.n_waves = nw;
   w.P3 = p3_of(P);
   w.nsum = nsum_of(P);
   w.probe_bins = 0;
+  w.bins = 0;
   return w;
 }
 
@@ -86,11 +90,11 @@ __global__ void __launch_bounds__(256) bwd_ws_clear_kernel(BwdWs ws, int waves) 
     *ws.pocc = 0;
   }
   if (waves && i < ws.n_waves) ws.overflow[i] = 0;
-  if (ws.probe_bins && i < ws.P3) ws.pcount[i] = 0;
+  if (ws.bins && i < ws.P3) ws.pcount[i] = 0;
 }
 
 static hipError_t launch_clear(const BwdWs& ws, int waves, hipStream_t s) {
-  const int64_t n = max(waves ? ws.n_waves : (int64_t)1, ws.probe_bins ? ws.P3 : (int64_t)1);
+  const int64_t n = max(waves ? ws.n_waves : (int64_t)1, ws.bins ? ws.P3 : (int64_t)1);
   hipLaunchKernelGGL(bwd_ws_clear_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ws,
                      waves);
   return hipGetLastError();
@@ -288,6 +292,7 @@ __global__ void __launch_bounds__(256) scan_partials_kernel(BwdWs ws) {
     if (b < ws.nsum) ws.psum[b] = carry + excl;
     carry += tot;
   }
+  if (threadIdx.x == 0) *ws.nsorted = carry;
 }
 
 // offsets of every cell, and the list of occupied cells
@@ -324,6 +329,7 @@ struct ShadeLds {
   union {
     DwLds dw;
     float sc[64][65];
+    float box[BOXCAP];
   } u;
   int k0[64][3];
   int fb[64];
@@ -339,7 +345,11 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
   const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
   const float* __restrict__ W = a.mlp;
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
-  const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
+  // taped: the samples in probe-cell order (slots of perm); else: in the order the
+  // march wrote them
+  const int64_t total =
+      TAPE ? (int64_t)*ws.nsorted
+           : min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
   const int64_t nbat = (total + 63) / 64;
 
   f4 acc_w1 = {0.f, 0.f, 0.f, 0.f}, acc_w2 = {0.f, 0.f, 0.f, 0.f};
@@ -348,11 +358,13 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
   for (int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WAVES + wv; b < nbat;
        b += (int64_t)gridDim.x * WAVES) {
     any = true;
-    const int64_t e = b * 64 + lane;
+    const int64_t slot = b * 64 + lane;
     const int n = (int)min((int64_t)64, total - b * 64);
+    int64_t e = slot;
     BwdEntry E;
     bool counted = false, ve = false;  // counted: holds a sample (has a probe bin slot)
     if (lane < n) {
+      if constexpr (TAPE) e = ws.perm[slot];
       E = ws.entries[e];
       counted = E.lw >= 0;
       ve = counted && ws.overflow[E.lw] == 0;
@@ -414,7 +426,17 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
     // SDF through the normal; with a tape also the opacity path at s_i (this
     // sample's alpha and the previous sample's, which meet at x_i); the rest of
     // the opacity path is scattered by the per-ray walk
-    if (a.g_sdf && (TAPE || !(G.flags & FLAG_NV_ONE))) {
+    bool box_done = false;
+    if constexpr (TAPE) {
+      // the batch is spatially compact (one or a few neighbouring probe cells):
+      // its SDF and feature gradients are summed in one LDS box and each touched
+      // node is flushed once, in row-contiguous runs
+      if (a.g_sdf) {
+        const float a0 = ve ? a.tau * sigmoidf(-a.tau * E.s0) * (E.gdl_prev - E.gdl) : 0.f;
+        box_done = sdf_box_wave(L.u.box, lane, ve, x, v, nm, dz, a0, G, a.g_sdf);
+      }
+    }
+    if (!box_done && a.g_sdf && (TAPE || !(G.flags & FLAG_NV_ONE))) {
       float* row = L.u.sc[lane];
 #pragma unroll
       for (int q = 0; q < 64; ++q) row[q] = 0.f;
@@ -426,17 +448,41 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
         L.k0[lane][2] = k0[2];
         if constexpr (TAPE) {
           const float a0 = a.tau * sigmoidf(-a.tau * E.s0) * (E.gdl_prev - E.gdl);
-          if (a0 != 0.f) patch_add(row, k0, x, G.R, G.inv_h, a0);
+          if (a0 != 0.f) patch_add(patch_of_row(row, k0), k0, x, G.R, G.inv_h, a0);
         }
-        if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch(row, k0, G, x, v, nm, dz);
+        if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch(patch_of_row(row, k0), k0, G, x, v, nm, dz);
       }
       wave_sync();
       sdf_patch_flush(L.u.sc, L.k0, n, lane, G.R, a.g_sdf);
       wave_sync();
     }
-    if (!(G.flags & FLAG_NO_FS) && a.g_feat)
-      feat_scatter_wave(L.u.sc, L.fb, ve, cell_d(x, G.R, G.inv_h), dz, n, lane, G.R, a.g_feat);
-    if (ws.probe_bins) {
+    if (!(G.flags & FLAG_NO_FS) && a.g_feat) {
+      const Cell cs = cell_d(x, G.R, G.inv_h);
+      bool fdone = false;
+      if constexpr (TAPE) fdone = feat_box_wave(L.u.box, lane, ve, x, cs, dz, G, a.g_feat);
+      if (!fdone) feat_scatter_wave(L.u.sc, L.fb, ve, cs, dz, n, lane, G.R, a.g_feat);
+    }
+    if (TAPE && ws.probe_bins) {
+      // the sample's probe record goes to its own sorted slot
+      if (lane < n) {
+        const double xs[3] = {E.x[0], E.x[1], E.x[2]};
+        const Cell cp = cell_d(xs, G.P, G.inv_hp);
+        ProbeRec pr;
+        pr.cell = cp.base;
+        pr.f[0] = cp.fx;
+        pr.f[1] = cp.fy;
+        pr.f[2] = cp.fz;
+        pr.v[0] = E.v[0];
+        pr.v[1] = E.v[1];
+        pr.v[2] = E.v[2];
+        pr.dfa[0] = ve ? dz[3] : 0.f;
+        pr.dfa[1] = ve ? dz[4] : 0.f;
+        pr.dfa[2] = ve ? dz[5] : 0.f;
+        pr.dfa[3] = ve ? dz[6] : 0.f;
+        pr.pad = 0.f;
+        ws.precs[slot] = pr;
+      }
+    } else if (ws.probe_bins) {
       // file dL/dF_a under the probe cell (the cell of the stored position, as
       // counted by the march pass)
       double xs[3] = {0.0, 0.0, 0.0};
@@ -570,6 +616,37 @@ __global__ void __launch_bounds__(BLOCK) tape_count_kernel(RenderArgs a, BwdWs w
     for_each_key_group(counted, pc, [&](int k, int leader, uint64_t grp) {
       if (lane == leader) atomicAdd(ws.pcount + k, (int)__popcll(grp));
     });
+  }
+}
+
+// sorted slot of every recorded sample: perm[slot] = entry, cells in index
+// order, the samples of a cell contiguous
+__global__ void __launch_bounds__(BLOCK) tape_place_kernel(RenderArgs a, BwdWs ws) {
+  const int lane = threadIdx.x & 63;
+  const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
+  const double inv_hp = 0.5 * (a.P - 1);
+  for (int64_t e0 = ((int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 64; e0 < total;
+       e0 += (int64_t)gridDim.x * WAVES * 64) {
+    const int64_t e = e0 + lane;
+    bool counted = false;
+    int pc = 0;
+    if (e < total) {
+      const BwdEntry& E = ws.entries[e];
+      counted = E.lw >= 0;
+      const double xs[3] = {E.x[0], E.x[1], E.x[2]};
+      if (counted) pc = cell_d(xs, a.P, inv_hp).base;
+    }
+    int first = 0, my_leader = 0;
+    uint64_t my_grp = 0;
+    for_each_key_group(counted, pc, [&](int k, int leader, uint64_t grp) {
+      if (lane == leader) first = atomicAdd(ws.pcursor + k, (int)__popcll(grp));
+      if ((grp >> lane) & 1ull) {
+        my_leader = leader;
+        my_grp = grp;
+      }
+    });
+    first = __shfl(first, my_leader, 64);
+    if (counted) ws.perm[first + lane_rank(my_grp)] = (int)e;
   }
 }
 
@@ -753,6 +830,9 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
   // probe gradients go through the cell bins (one lane per node coefficient:
   // n_sh * n_ang <= 64 for every compiled SH order)
   ws.probe_bins = (a.g_probes && !(a.flags & FLAG_NO_FA)) ? 1 : 0;
+  // a taped backward always files its samples in probe-cell order (locality of
+  // the shading pass's scatters)
+  ws.bins = (ws.probe_bins || from_tape) ? 1 : 0;
   const dim3 wgrid((unsigned)((a.B + BLOCK - 1) / BLOCK));
   hipError_t e = launch_clear(ws, from_tape ? 0 : 1, s);
   if (e != hipSuccess) return e;
@@ -761,15 +841,20 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
       hipLaunchKernelGGL(bwd_march_kernel<float>, wgrid, dim3(BLOCK), 0, s, a, ws);
     else
       hipLaunchKernelGGL(bwd_march_kernel<_Float16>, wgrid, dim3(BLOCK), 0, s, a, ws);
-  } else if (ws.probe_bins) {
+  } else {
     const int64_t cw = (ws.cap + 63) / 64;
     const dim3 cgrid((unsigned)max((int64_t)1, min((cw + WAVES - 1) / WAVES, (int64_t)2048)));
     hipLaunchKernelGGL(tape_count_kernel, cgrid, dim3(BLOCK), 0, s, a, ws);
   }
-  if (ws.probe_bins) {
+  if (ws.bins) {
     hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(scan_offsets_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);
+  }
+  if (from_tape) {
+    const int64_t cw = (ws.cap + 63) / 64;
+    const dim3 cgrid((unsigned)max((int64_t)1, min((cw + WAVES - 1) / WAVES, (int64_t)2048)));
+    hipLaunchKernelGGL(tape_place_kernel, cgrid, dim3(BLOCK), 0, s, a, ws);
   }
   if (from_tape && a.g_sdf) hipLaunchKernelGGL(tape_walk_kernel, wgrid, dim3(BLOCK), 0, s, a, ws);
   // enough waves to fill the chip; each loops over batches of 64 entries

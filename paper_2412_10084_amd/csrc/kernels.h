@@ -79,12 +79,15 @@ struct BwdWs {
   int* psum;           // [nsum] scan partials
   int* plist;          // [P^3] occupied probe cells (first *pocc entries)
   int* pocc;           // [1]
+  int* nsorted;        // [1] samples filed in probe-cell order (taped schedule)
+  int* perm;           // [cap] entry of each sorted slot (taped schedule)
   BwdEntry* entries;   // [cap]
   ProbeRec* precs;     // [cap] in probe-cell order
   int64_t cap;
   int64_t n_waves;
   int64_t P3, nsum;
   int probe_bins;      // 1: the probe gradient goes through the cell bins
+  int bins;            // 1: samples are counted per probe cell (probe bins or taped order)
 };
 
 // bytes of a workspace with room for `cap` samples; carve() lays it out

@@ -127,8 +127,8 @@ __device__ __forceinline__ void bwd_batch(const RenderArgs& a, const Geo& G, Bwd
       L.k0[lane][0] = k0[0];
       L.k0[lane][1] = k0[1];
       L.k0[lane][2] = k0[2];
-      if (gs0 != 0.f) patch_add(row, k0, x, G.R, G.inv_h, gs0);
-      if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch(row, k0, G, x, v, nm, dz);
+      if (gs0 != 0.f) patch_add(patch_of_row(row, k0), k0, x, G.R, G.inv_h, gs0);
+      if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch(patch_of_row(row, k0), k0, G, x, v, nm, dz);
     }
     wave_sync();
     sdf_patch_flush(L.u.sc, L.k0, n, lane, G.R, a.g_sdf);

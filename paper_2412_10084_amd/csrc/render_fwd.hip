@@ -245,6 +245,7 @@ hipError_t launch_render_forward(const RenderArgs& a, const BwdWs* tape, int sdf
   if (tape) {
     ws = *tape;
     ws.probe_bins = 0;
+    ws.bins = 0;
     const hipError_t e = launch_bwd_ws_clear(ws, s);
     if (e != hipSuccess) return e;
   }

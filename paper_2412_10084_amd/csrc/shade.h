@@ -414,9 +414,30 @@ __device__ __forceinline__ void cell_k(const double x[3], int R, double inv_h, i
   for (int a = 0; a < 3; ++a) k[a] = (int)fmin(fmax(floor((x[a] + 1.0) * inv_h), 0.0), kmax);
 }
 
-// add val * trilinear weights of the cell of point y into the patch of cell k0
-__device__ __forceinline__ void patch_add(float* row, const int k0[3], const double y[3], int R,
-                                          double inv_h, float val) {
+// Destination of SDF-gradient contributions: an LDS block of nodes with origin
+// (ox, oy, oz) and strides (1, sy, sz) -- an entry's private 4x4x4 patch, or a
+// box shared by the whole wave (then the adds are LDS atomics).
+struct PatchDst {
+  float* p;
+  int ox, oy, oz;
+  int sy, sz;
+};
+
+__device__ __forceinline__ PatchDst patch_of_row(float* row, const int k0[3]) {
+  return PatchDst{row, k0[0] - 1, k0[1] - 1, k0[2] - 1, 4, 16};
+}
+
+template <bool SHARED>
+__device__ __forceinline__ void dst_add(float* p, float v) {
+  if constexpr (SHARED) atomicAdd(p, v);
+  else *p += v;
+}
+
+// add val * trilinear weights of the cell of point y (kept within one cell of
+// k0) into the destination
+template <bool SHARED = false>
+__device__ __forceinline__ void patch_add(const PatchDst& D, const int k0[3], const double y[3],
+                                          int R, double inv_h, float val) {
   int k[3];
   float f[3];
   const double kmax = (double)(R - 2);
@@ -431,24 +452,26 @@ __device__ __forceinline__ void patch_add(float* row, const int k0[3], const dou
     k[a] = (int)fl;
     f[a] = (float)(u - fl);
   }
-  // k[a] - k0[a] + 1 is in [0, 2] per axis, so o + 21 <= 63
-  const int o = (k[2] - k0[2] + 1) * 16 + (k[1] - k0[1] + 1) * 4 + (k[0] - k0[0] + 1);
+  // k lies within one cell of k0, so the 8 corners are inside the destination
+  float* q = D.p + (k[2] - D.oz) * D.sz + (k[1] - D.oy) * D.sy + (k[0] - D.ox);
   const float gx = 1.0f - f[0], gy = 1.0f - f[1], gz = 1.0f - f[2];
-  row[o + 0] += val * gx * gy * gz;
-  row[o + 1] += val * f[0] * gy * gz;
-  row[o + 4] += val * gx * f[1] * gz;
-  row[o + 5] += val * f[0] * f[1] * gz;
-  row[o + 16] += val * gx * gy * f[2];
-  row[o + 17] += val * f[0] * gy * f[2];
-  row[o + 20] += val * gx * f[1] * f[2];
-  row[o + 21] += val * f[0] * f[1] * f[2];
+  const int sy = D.sy, sz = D.sz;
+  dst_add<SHARED>(q, val * gx * gy * gz);
+  dst_add<SHARED>(q + 1, val * f[0] * gy * gz);
+  dst_add<SHARED>(q + sy, val * gx * f[1] * gz);
+  dst_add<SHARED>(q + sy + 1, val * f[0] * f[1] * gz);
+  dst_add<SHARED>(q + sz, val * gx * gy * f[2]);
+  dst_add<SHARED>(q + sz + 1, val * f[0] * gy * f[2]);
+  dst_add<SHARED>(q + sz + sy, val * gx * f[1] * f[2]);
+  dst_add<SHARED>(q + sz + sy + 1, val * f[0] * f[1] * f[2]);
 }
 
-// SDF gradient of the normal path (c = n.v, n = g/|g|, g the FD gradient) into
-// the patch row
-__device__ __forceinline__ void normal_backward_patch(float* row, const int k0[3], const Geo& G,
-                                                      const double x[3], const float v[3],
-                                                      const Normal& nm, const float dz[NIN]) {
+// SDF gradient of the normal path (c = n.v, n = g/|g|, g the FD gradient)
+template <bool SHARED = false>
+__device__ __forceinline__ void normal_backward_patch(const PatchDst& D, const int k0[3],
+                                                      const Geo& G, const double x[3],
+                                                      const float v[3], const Normal& nm,
+                                                      const float dz[NIN]) {
   const float c = nm.c;
   const float dc = dz[7] + 2.0f * c * dz[8] + 4.0f * c * c * c * dz[9];
   float dg[3];
@@ -466,8 +489,8 @@ __device__ __forceinline__ void normal_backward_patch(float* row, const int k0[3
     xp[a] = fmin(x[a] + G.h, 1.0);
     xm[a] = fmax(x[a] - G.h, -1.0);
     const float coef = dg[a] / (float)(xp[a] - xm[a]);
-    patch_add(row, k0, xp, G.R, G.inv_h, coef);
-    patch_add(row, k0, xm, G.R, G.inv_h, -coef);
+    patch_add<SHARED>(D, k0, xp, G.R, G.inv_h, coef);
+    patch_add<SHARED>(D, k0, xm, G.R, G.inv_h, -coef);
   }
 }
 
