@@ -5,9 +5,11 @@
 One step = one training iteration of the render path on the train256 workload
 (256^3 SDF + 3 features, 64^3 probes x 9 SH x 4, MLP 10-16-3; 2^18 rays from 8
 cameras at 256x128, 128 samples, skip |s| > 4 voxels; L1 loss against a torus
-target): render_forward -> l1_loss -> render_backward -> grid_step (eikonal +
-smoothness + Adam over all 76.5 M parameters).  Inputs are resident in HBM
-before timing starts.  value = rays per second of that whole step.
+target): render_forward (recording its tape) -> l1_loss -> render_backward (from
+the tape) -> grid_step (eikonal + smoothness + Adam over all 76.5 M parameters,
+writing the SDF brick bounds the next forward skips empty space with).  Inputs
+are resident in HBM before timing starts.  value = rays per second of that whole
+step.
 
 The JSON line also carries the per-kernel times, the roofline of the dominant
 kernel (HIP events on the stream the kernels run on), the same step with FP16
@@ -293,14 +295,17 @@ def kernel_source_hash() -> str:
 
 
 TRAFFIC_KERNELS = {
-    "render_backward": ("void psdf::render_bwd_kernel<float, float, 9, 0>", "psdf::bwd_ws_clear_kernel",
-                        "void psdf::bwd_march_kernel<float>", "psdf::scan_sums_kernel",
-                        "psdf::scan_partials_kernel", "psdf::scan_offsets_kernel",
-                        "void psdf::bwd_shade_kernel<float, float, 9, 0>",
-                        "void psdf::probe_reduce_kernel<9>", "psdf::bwd_alpha_kernel"),
+    # the kernels each entry point launches on the benchmark's path (taped training step)
+    "render_backward": ("psdf::bwd_ws_clear_kernel", "psdf::tape_count_kernel",
+                        "psdf::scan_sums_kernel", "psdf::scan_partials_kernel",
+                        "psdf::scan_offsets_kernel", "psdf::tape_place_kernel",
+                        "psdf::tape_walk_kernel", "void psdf::bwd_shade_kernel<float, float, 9, 0, true>",
+                        "void psdf::probe_reduce_kernel<9>",
+                        "void psdf::render_bwd_kernel<float, float, 9, 0>"),
     "render_forward": ("void psdf::render_fwd_kernel<float, float, 9, 0>",),
-    "grid_step": ("psdf::step_sdf_kernel", "void psdf::step_tv_kernel<3>", "void psdf::step_tv4_kernel<36>",
-                  "psdf::step_mlp_kernel", "void psdf::sdf_bounds_kernel<float>"),
+    "grid_step": ("psdf::zero3_kernel", "psdf::bounds_init_kernel", "psdf::step_sdf_tiled_kernel",
+                  "psdf::bounds_decode_kernel", "psdf::step_tv3v_kernel",
+                  "void psdf::step_tv4_kernel<36>", "psdf::step_mlp_kernel"),
 }
 
 
