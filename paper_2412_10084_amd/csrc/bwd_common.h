@@ -198,6 +198,24 @@ __device__ __forceinline__ void mlp_dw_wave(DwLds& D, int lane, bool ve, const f
   db2[2] += dout[2];
 }
 
+// the wave's MLP gradient as one contiguous row of NMLP partials
+__device__ __forceinline__ void mlp_grad_store(float* row, int lane, const f4& acc_w1,
+                                               const f4& acc_w2, const float db2[3]) {
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int r = 4 * g + rr;
+    if (i < NIN) row[r * NIN + i] = acc_w1[rr];
+    else if (i == NIN) row[OFF_B1 + r] = acc_w1[rr];
+    if (r < 3) row[OFF_W2 + r * HID + i] = acc_w2[rr];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float s = wave_sum(db2[c]);
+    if (lane == 0) row[OFF_B2 + c] = s;
+  }
+}
+
 // one global atomic per MLP parameter per wave
 __device__ __forceinline__ void mlp_grad_flush(float* g_mlp, int lane, const f4& acc_w1,
                                                const f4& acc_w2, const float db2[3]) {

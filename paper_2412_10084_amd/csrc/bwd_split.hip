@@ -38,8 +38,10 @@ int64_t al256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 int64_t n_waves_of(int64_t B) { return (B + 63) / 64; }
 int64_t p3_of(int P) { return (int64_t)P * P * P; }
 int64_t nsum_of(int P) { return (p3_of(P) + kScan - 1) / kScan; }
+constexpr int64_t kMlpPart = (int64_t)NMLP * kMlpWaves * 4;
 int64_t fixed_bytes(int64_t B, int P) {
-  return kHead + 3 * al256(n_waves_of(B) * 4) + 3 * al256(p3_of(P) * 4) + al256(nsum_of(P) * 4);
+  return kHead + 3 * al256(n_waves_of(B) * 4) + 3 * al256(p3_of(P) * 4) + al256(nsum_of(P) * 4) +
+         kMlpPart;
 }
 constexpr int64_t kPerSample = (int64_t)sizeof(BwdEntry) + (int64_t)sizeof(ProbeRec) + 4;
 }  // namespace
@@ -64,6 +66,7 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   w.pcursor = reinterpret_cast<int*>(p + kHead + 3 * arr + parr);
   w.plist = reinterpret_cast<int*>(p + kHead + 3 * arr + 2 * parr);
   w.psum = reinterpret_cast<int*>(p + kHead + 3 * arr + 3 * parr);
+  w.mlp_part = reinterpret_cast<float*>(p + kHead + 3 * arr + 3 * parr + al256(nsum_of(P) * 4));
   w.pocc = reinterpret_cast<int*>(p + 8);
   w.cap = bwd_ws_capacity(B, P, bytes);
   w.entries = reinterpret_cast<BwdEntry*>(p + fixed_bytes(B, P));
@@ -354,10 +357,13 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
 
   f4 acc_w1 = {0.f, 0.f, 0.f, 0.f}, acc_w2 = {0.f, 0.f, 0.f, 0.f};
   float db2[3] = {0.f, 0.f, 0.f};
-  bool any = false;
-  for (int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WAVES + wv; b < nbat;
-       b += (int64_t)gridDim.x * WAVES) {
-    any = true;
+  const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;
+  for (int64_t b0 = gw; b0 < nbat; b0 += (int64_t)gridDim.x * WAVES) {
+    // taped: sorted batches are visited in a scrambled order (b0 * K mod nbat with K
+    // a prime above any batch count), so that waves running at the same time work
+    // on distant parts of the surface and their flushes do not meet on the same
+    // lines; the plain schedule keeps the march's order
+    const int64_t b = TAPE ? (int64_t)(((uint64_t)b0 * 2654435761ull) % (uint64_t)nbat) : b0;
     const int64_t slot = b * 64 + lane;
     const int n = (int)min((int64_t)64, total - b * 64);
     int64_t e = slot;
@@ -528,7 +534,20 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
     if (a.g_mlp) mlp_dw_wave<M>(L.u.dw, lane, ve, z, hid, dpre, dout, acc_w1, acc_w2, db2);
     wave_sync();
   }
-  if (any && a.g_mlp) mlp_grad_flush(a.g_mlp, lane, acc_w1, acc_w2, db2);
+  // MLP gradient: one row of partials per wave, summed by mlp_reduce_kernel
+  if (a.g_mlp) mlp_grad_store(ws.mlp_part + gw * NMLP, lane, acc_w1, acc_w2, db2);
+}
+
+// g_mlp[k] += sum over the shading waves of their partials (fixed order)
+__global__ void __launch_bounds__(256) mlp_reduce_kernel(BwdWs ws, int nwaves, float* g_mlp) {
+  __shared__ float part[4];
+  const int k = blockIdx.x;
+  float acc = 0.f;
+  for (int w = threadIdx.x; w < nwaves; w += 256) acc += ws.mlp_part[(int64_t)w * NMLP + k];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) g_mlp[k] += (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -869,6 +888,9 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
         hipLaunchKernelGGL((bwd_shade_kernel<ST, FT, NSH, M, false>), sgrid, dim3(BLOCK), 0, s, a,
                            ws))));
   }
+  if (a.g_mlp)
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(NMLP), dim3(256), 0, s, ws, (int)(sgrid.x * WAVES),
+                       a.g_mlp);
   if (ws.probe_bins) {
     // one wave per occupied cell (the count is on the device: enough waves for
     // a dense band, each looping)

@@ -68,6 +68,9 @@ struct ProbeRec {
   float pad;
 };
 
+// most waves a shading pass launches (1024 blocks of 4 waves)
+constexpr int kMlpWaves = 4096;
+
 // Device workspace of the entry-parallel backward, carved from one caller buffer.
 struct BwdWs {
   unsigned long long* counter;  // [1] slots handed out (may pass cap)
@@ -81,6 +84,7 @@ struct BwdWs {
   int* pocc;           // [1]
   int* nsorted;        // [1] samples filed in probe-cell order (taped schedule)
   int* perm;           // [cap] entry of each sorted slot (taped schedule)
+  float* mlp_part;     // [kMlpWaves][227] MLP gradient partials of the shading waves
   BwdEntry* entries;   // [cap]
   ProbeRec* precs;     // [cap] in probe-cell order
   int64_t cap;
