@@ -671,13 +671,13 @@ __global__ void __launch_bounds__(BLOCK) tape_place_kernel(RenderArgs a, BwdWs w
 
 struct WalkLds {
   RayD ray[64];
-  int own[64];
   int si[64];
   float w[64];
   float T[64];
   float C[64][3];
   float gdl[64];
   int nin[64];
+  unsigned long long mine[64];  // entries of the chunk owned by each lane's ray
 };
 
 __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws) {
@@ -710,6 +710,8 @@ __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws
   int n = cnt - 64 * ((cnt - 1) / 64);
   while (base >= 0) {  // wave-uniform
     wave_sync();
+    L.mine[lane] = 0ull;
+    wave_sync();
     int key = 0, prev = -1;
     float s1 = 0.f;
     if (lane < n) {
@@ -717,7 +719,7 @@ __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws
       key = E.key;
       prev = E.prev;
       s1 = E.s1;
-      L.own[lane] = key & 63;
+      atomicOr(&L.mine[key & 63], 1ull << lane);
       L.si[lane] = key >> 6;
       L.w[lane] = E.w;
       L.T[lane] = E.T;
@@ -726,8 +728,12 @@ __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws
       L.C[lane][2] = E.C[2];
     }
     wave_sync();
-    for (int k = n - 1; k >= 0; --k) {
-      if (lane == L.own[k]) {
+    // each lane walks its own ray's entries of the chunk, last sample first (a
+    // ray's entries are stored in sample order)
+    for (unsigned long long m = L.mine[lane]; m != 0ull;) {
+      const int k = 63 - __clzll(m);
+      m &= ~(1ull << k);
+      {
         const float w = L.w[k], T = L.T[k];
         const float c0 = L.C[k][0], c1 = L.C[k][1], c2 = L.C[k][2];
         Rc[0] = fmaf(w, c0, Rc[0]);
@@ -768,11 +774,11 @@ __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws
 // ---------------------------------------------------------------------------
 struct AlphaLds {
   RayD ray[64];
-  int own[64];
   float w[64];
   float T[64];
   float C[64][3];
   float gdl[64];
+  unsigned long long mine[64];  // entries of the chunk owned by each lane's ray
 };
 
 __global__ void __launch_bounds__(BLOCK) bwd_alpha_kernel(RenderArgs a, BwdWs ws) {
@@ -804,11 +810,13 @@ __global__ void __launch_bounds__(BLOCK) bwd_alpha_kernel(RenderArgs a, BwdWs ws
   int n = cnt - 64 * ((cnt - 1) / 64);  // the last chunk may be partial
   while (base >= 0) {  // wave-uniform
     wave_sync();
+    L.mine[lane] = 0ull;
+    wave_sync();
     BwdEntry E;
     E.prev = -1;
     if (lane < n) {
       E = ws.entries[base + lane];
-      L.own[lane] = E.key & 63;
+      atomicOr(&L.mine[E.key & 63], 1ull << lane);
       L.w[lane] = E.w;
       L.T[lane] = E.T;
       L.C[lane][0] = E.C[0];
@@ -816,8 +824,12 @@ __global__ void __launch_bounds__(BLOCK) bwd_alpha_kernel(RenderArgs a, BwdWs ws
       L.C[lane][2] = E.C[2];
     }
     wave_sync();
-    for (int k = n - 1; k >= 0; --k) {
-      if (lane == L.own[k]) {
+    // each lane walks its own ray's entries of the chunk, last sample first (a
+    // ray's entries are stored in sample order)
+    for (unsigned long long m = L.mine[lane]; m != 0ull;) {
+      const int k = 63 - __clzll(m);
+      m &= ~(1ull << k);
+      {
         const float w = L.w[k], T = L.T[k];
         const float c0 = L.C[k][0], c1 = L.C[k][1], c2 = L.C[k][2];
         Rc[0] = fmaf(w, c0, Rc[0]);
