@@ -68,13 +68,14 @@ __global__ void __launch_bounds__(SBLOCK) step_tv_kernel(TvArgs t, StepArgs a) {
     if (j < R - 1) { const float d = F[e + sy] - f; acc -= d; loss += d * d; }
     if (k > 0) acc += f - F[e - sz];
     if (k < R - 1) { const float d = F[e + sz] - f; acc -= d; loss += d * d; }
-    const float G = t.g[e] + 2.0f * scale * acc;
+    const float g = t.g[e];
+    const float G = g + 2.0f * scale * acc;
     float m = t.m[e], v = t.v[e];
     const float p = adam_update_f(f, G, m, v, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
     t.F_out[e] = p;
     t.m[e] = m;
     t.v[e] = v;
-    t.g[e] = 0.f;
+    if (g != 0.f) t.g[e] = 0.f;  // the render gradient is sparse
     if (t.half_out) t.half_out[e] = (_Float16)p;
   }
   if (t.loss_dst) block_add(loss * scale, t.loss_dst);
@@ -133,7 +134,9 @@ __global__ void __launch_bounds__(SBLOCK) step_tv4_kernel(TvArgs t, StepArgs a) 
     st4g(t.F_out, e, p);
     st4g(t.m, e, m);
     st4g(t.v, e, v);
-    st4g(t.g, e, make_float4(0.f, 0.f, 0.f, 0.f));
+    // the render gradient is sparse: only nonzero entries are cleared
+    if (g.x != 0.f || g.y != 0.f || g.z != 0.f || g.w != 0.f)
+      st4g(t.g, e, make_float4(0.f, 0.f, 0.f, 0.f));
     if (t.half_out) {
       h4 hv = {(_Float16)p.x, (_Float16)p.y, (_Float16)p.z, (_Float16)p.w};
       *reinterpret_cast<h4*>(t.half_out + e) = hv;
@@ -197,7 +200,9 @@ __global__ void __launch_bounds__(SBLOCK) step_tv3v_kernel(TvArgs t, StepArgs a)
     st4g(t.F_out, e, p);
     st4g(t.m, e, m);
     st4g(t.v, e, v);
-    st4g(t.g, e, make_float4(0.f, 0.f, 0.f, 0.f));
+    // the render gradient is sparse: only nonzero entries are cleared
+    if (g.x != 0.f || g.y != 0.f || g.z != 0.f || g.w != 0.f)
+      st4g(t.g, e, make_float4(0.f, 0.f, 0.f, 0.f));
     if (t.half_out) {
       h4 hv = {(_Float16)p.x, (_Float16)p.y, (_Float16)p.z, (_Float16)p.w};
       *reinterpret_cast<h4*>(t.half_out + e) = hv;
@@ -245,13 +250,14 @@ __global__ void __launch_bounds__(SBLOCK) step_tv_any_kernel(TvArgs t, int C, St
     if (j < R - 1) { const float d = F[e + sy] - f; acc -= d; loss += d * d; }
     if (k > 0) acc += f - F[e - sz];
     if (k < R - 1) { const float d = F[e + sz] - f; acc -= d; loss += d * d; }
+    const float g = t.g[e];
     float m = t.m[e], v = t.v[e];
-    const float p = adam_update_f(f, t.g[e] + 2.0f * scale * acc, m, v, t.lr, a.beta1, a.beta2,
+    const float p = adam_update_f(f, g + 2.0f * scale * acc, m, v, t.lr, a.beta1, a.beta2,
                                 a.eps, a.bc1, a.bc2);
     t.F_out[e] = p;
     t.m[e] = m;
     t.v[e] = v;
-    t.g[e] = 0.f;
+    if (g != 0.f) t.g[e] = 0.f;  // the render gradient is sparse
     if (t.half_out) t.half_out[e] = (_Float16)p;
   }
   if (t.loss_dst) block_add(loss * scale, t.loss_dst);

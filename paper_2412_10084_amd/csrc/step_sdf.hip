@@ -230,7 +230,8 @@ __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, in
       bstore(wo, off, p);
       bstore(wm, off, m);
       bstore(wv, off, vv);
-      bstore(wg, off, 0.f);
+      // the render gradient is sparse: only nonzero entries are cleared
+      bstore(wg, gc[c] != 0.f ? off : kOOB, 0.f);
       // FP16 copy (a resource without records when there is none)
       const _Float16 hp = (_Float16)p;
       __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hp), wh,
