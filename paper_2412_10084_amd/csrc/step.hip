@@ -88,6 +88,17 @@ __device__ __forceinline__ float4 ld4g(const float* p, int e) {
 __device__ __forceinline__ void st4g(float* p, int e, float4 v) {
   *reinterpret_cast<float4*>(p + e) = v;
 }
+// streaming (non-temporal) access for the optimiser state and the gradient: each
+// is touched once per step, so it should not displace cached grid data
+typedef float nf4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4s(const float* p, int e) {
+  const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(p + e));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4s(float* p, int e, float4 v) {
+  const nf4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<nf4*>(p + e));
+}
 
 template <int C>
 __global__ void __launch_bounds__(SBLOCK) step_tv4_kernel(TvArgs t, StepArgs a) {
@@ -123,8 +134,8 @@ __global__ void __launch_bounds__(SBLOCK) step_tv4_kernel(TvArgs t, StepArgs a) 
     if (j < R - 1) fwd(sy);
     if (k > 0) back(sz);
     if (k < R - 1) fwd(sz);
-    const float4 g = ld4g(t.g, e);
-    float4 m = ld4g(t.m, e), v = ld4g(t.v, e);
+    const float4 g = ld4s(t.g, e);
+    float4 m = ld4s(t.m, e), v = ld4s(t.v, e);
     const float s2 = 2.0f * scale;
     float4 p;
     p.x = adam_update_f(f.x, g.x + s2 * acc.x, m.x, v.x, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
@@ -132,8 +143,8 @@ __global__ void __launch_bounds__(SBLOCK) step_tv4_kernel(TvArgs t, StepArgs a) 
     p.z = adam_update_f(f.z, g.z + s2 * acc.z, m.z, v.z, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
     p.w = adam_update_f(f.w, g.w + s2 * acc.w, m.w, v.w, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
     st4g(t.F_out, e, p);
-    st4g(t.m, e, m);
-    st4g(t.v, e, v);
+    st4s(t.m, e, m);
+    st4s(t.v, e, v);
     // the render gradient is sparse: only nonzero entries are cleared
     if (g.x != 0.f || g.y != 0.f || g.z != 0.f || g.w != 0.f)
       st4g(t.g, e, make_float4(0.f, 0.f, 0.f, 0.f));
@@ -189,8 +200,8 @@ __global__ void __launch_bounds__(SBLOCK) step_tv3v_kernel(TvArgs t, StepArgs a)
     };
     yz(sy, j > 0, j < R - 1);
     yz(sz, k > 0, k < R - 1);
-    const float4 g = ld4g(t.g, e);
-    float4 m = ld4g(t.m, e), v = ld4g(t.v, e);
+    const float4 g = ld4s(t.g, e);
+    float4 m = ld4s(t.m, e), v = ld4s(t.v, e);
     const float s2 = 2.0f * scale;
     float4 p;
     p.x = adam_update_f(f[0], g.x + s2 * acc[0], m.x, v.x, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
@@ -198,8 +209,8 @@ __global__ void __launch_bounds__(SBLOCK) step_tv3v_kernel(TvArgs t, StepArgs a)
     p.z = adam_update_f(f[2], g.z + s2 * acc[2], m.z, v.z, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
     p.w = adam_update_f(f[3], g.w + s2 * acc[3], m.w, v.w, t.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
     st4g(t.F_out, e, p);
-    st4g(t.m, e, m);
-    st4g(t.v, e, v);
+    st4s(t.m, e, m);
+    st4s(t.v, e, v);
     // the render gradient is sparse: only nonzero entries are cleared
     if (g.x != 0.f || g.y != 0.f || g.z != 0.f || g.w != 0.f)
       st4g(t.g, e, make_float4(0.f, 0.f, 0.f, 0.f));

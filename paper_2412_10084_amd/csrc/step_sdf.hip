@@ -62,6 +62,14 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off) {
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
 }
+// streaming (non-temporal: cache policy bit 1) forms for the optimiser state and
+// the gradient, touched once per step
+__device__ __forceinline__ float bload_s(__amdgpu_buffer_rsrc_t r, int off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2));
+}
+__device__ __forceinline__ void bstore_s(__amdgpu_buffer_rsrc_t r, int off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 2);
+}
 
 // s plane z of the tile region into registers (0 outside the grid)
 __device__ __forceinline__ void s_plane_fetch(const float* __restrict__ s, int R, int x0, int y0,
@@ -176,9 +184,9 @@ __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, in
     for (int c = 0; c < 2; ++c) {
       const int gy = y0 + ty + 4 * c;
       const int off = gx < R && gy < R ? (gy * R + gx) * 4 : kOOB;
-      g[c] = bload(rg, off);
-      m[c] = bload(rm, off);
-      w[c] = bload(rv, off);
+      g[c] = bload_s(rg, off);
+      m[c] = bload_s(rm, off);
+      w[c] = bload_s(rv, off);
     }
   };
   // two planes of gradient / moments and two s planes in flight
@@ -228,8 +236,8 @@ __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, in
       const float p = adam_update_f(p0, G, m, vv, a.lr_sdf, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
       const int off = own ? (gy * R + gx) * 4 : kOOB;
       bstore(wo, off, p);
-      bstore(wm, off, m);
-      bstore(wv, off, vv);
+      bstore_s(wm, off, m);
+      bstore_s(wv, off, vv);
       // the render gradient is sparse: only nonzero entries are cleared
       bstore(wg, gc[c] != 0.f ? off : kOOB, 0.f);
       // FP16 copy (a resource without records when there is none)
