@@ -71,13 +71,11 @@ __device__ __forceinline__ void feat_scatter_wave(float (*sc)[65], int* fb, bool
 }
 
 // ---------------------------------------------------------------------------
-// Box accumulation: when the wave's samples are spatially compact, their SDF
-// (or feature) gradients are added into one LDS box of nodes with LDS atomics,
-// and the box is flushed once, each row of nodes as a contiguous run of lanes.
-// Call with the whole wave; returns false (nothing done) when the box does not
-// fit, and the caller then takes the per-sample path.
+// Box accumulation: the SDF (or feature) gradients of a spatially compact set of
+// samples are added into one LDS box of nodes with LDS atomics, and the box is
+// flushed once, each row of nodes as a contiguous run of lanes.  Called with the
+// whole wave.
 // ---------------------------------------------------------------------------
-constexpr int BOXCAP = 64 * 65;  // floats
 
 __device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
@@ -90,89 +88,183 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-// nrows rows of row_len floats; row r holds nodes (ox + x / C, oy + r % ey, oz + r / ey)
-__device__ __forceinline__ void box_flush(const float* box, int row_len, int nrows, int ey, int ox,
-                                          int oy, int oz, int R, int C, float* g, int lane) {
+// A box of ex x ey x ez nodes with C channels, origin (ox, oy, oz): rows of
+// ex * C floats, row r holding nodes (ox + x / C, oy + r % ey, oz + r / ey).  Each
+// nonzero value is added to the grid; a power-of-two group of lanes takes a row.
+template <int C>
+__device__ __forceinline__ void box_flush(const float* box, int ex, int ey, int ez, int ox, int oy,
+                                          int oz, int R, float* g, int lane) {
+  const int row_len = ex * C, nrows = ey * ez;
   int lpr = 1;
   while (lpr < row_len && lpr < 64) lpr <<= 1;  // lanes per row
   const int sh = __builtin_ctz(lpr), rows_per = 64 >> sh;
+  const int x0 = lane & (lpr - 1);
+  // this lane's row, advanced by rows_per rows (dz planes + dy rows) per step
+  int r = lane >> sh;
+  int iz = r / ey, iy = r - iz * ey;
+  const int dz = rows_per / ey, dy = rows_per - dz * ey;
   for (int r0 = 0; r0 < nrows; r0 += rows_per) {
-    const int r = r0 + (lane >> sh);
     if (r < nrows) {
-      const int iz = r / ey, iy = r - iz * ey;
       const int gy = oy + iy, gz = oz + iz;
       const bool row_in = gy >= 0 && gy < R && gz >= 0 && gz < R;
-      for (int xx = lane & (lpr - 1); xx < row_len; xx += lpr) {
-        const float v = box[r * row_len + xx];
+      const float* brow = box + r * row_len;
+      float* grow = g + ((int64_t)(gz * R + gy) * R + ox) * C;
+      for (int xx = x0; xx < row_len; xx += lpr) {
+        const float v = brow[xx];
         const int gx = ox + xx / C;
-        if (v != 0.f && row_in && gx >= 0 && gx < R)
-          atomic_add_f32(g + ((int64_t)(gz * R + gy) * R + ox) * C + xx, v);
+        if (v != 0.f && row_in && gx >= 0 && gx < R) atomic_add_f32(grow + xx, v);
       }
+    }
+    r += rows_per;
+    iy += dy;
+    iz += dz;
+    if (iy >= ey) {
+      iy -= ey;
+      ++iz;
     }
   }
 }
 
-// SDF: the opacity gradient at s_i (coefficient a0) and the normal path
-__device__ __forceinline__ bool sdf_box_wave(float* box, int lane, bool ve, const double x[3],
-                                             const float v[3], const Normal& nm,
-                                             const float dz[NIN], float a0, const Geo& G,
-                                             float* g_sdf) {
-  if (!wave_any(ve)) return true;
+// SDF box pass over the lanes with `part` set: the opacity gradient at s_i
+// (coefficient a0, trilinear at x) and the central-difference path (cotangent
+// dg of the FD gradient at x).  Returns false, having done nothing, when their
+// nodes do not fit in `cap` floats (wave-uniform).
+__device__ __forceinline__ bool sdf_box_pass(float* box, int cap, int lane, bool part,
+                                             const double x[3], const float dg[3], float a0,
+                                             const Geo& G, float* g_sdf) {
   int k0[3] = {0, 0, 0};
-  if (ve) cell_k(x, G.R, G.inv_h, k0);
+  if (part) cell_k(x, G.R, G.inv_h, k0);
   int lo[3], ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = wave_min_i(ve ? k0[a] : 0x7FFFFFFF);
-    ext[a] = wave_max_i(ve ? k0[a] : -0x7FFFFFFF) - lo[a] + 4;  // nodes lo-1 .. hi+2
+    lo[a] = wave_min_i(part ? k0[a] - 1 : 0x7FFFFFFF);  // nodes k0-1 .. k0+2
+    ext[a] = wave_max_i(part ? k0[a] + 2 : -0x7FFFFFFF) - lo[a] + 1;
   }
-  if ((int64_t)ext[0] * ext[1] * ext[2] > BOXCAP) return false;
+  if ((int64_t)ext[0] * ext[1] * ext[2] > cap) return false;
   const int vol = ext[0] * ext[1] * ext[2];
   for (int i = lane; i < vol; i += 64) box[i] = 0.f;
   wave_sync();
-  const PatchDst D{box, lo[0] - 1, lo[1] - 1, lo[2] - 1, ext[0], ext[0] * ext[1]};
-  if (ve) {
-    if (a0 != 0.f) patch_add<true>(D, k0, x, G.R, G.inv_h, a0);
-    if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch<true>(D, k0, G, x, v, nm, dz);
+  const int sy = ext[0], sz = ext[0] * ext[1];
+  if (part) {
+    // Away from the boundary the stencil points x -/+ h e_a lie one cell below /
+    // above x's cell with x's fractions, so the opacity term and the six FD terms
+    // touch 32 nodes of the 4x4x4 patch around the cell: its central 2x2x2 and
+    // two 2x2 end caps per axis.
+    float f[3];
+    bool inner = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double u = (x[a] + 1.0) * G.inv_h;
+      f[a] = (float)(u - (double)k0[a]);
+      inner = inner && k0[a] >= 1 && k0[a] <= G.R - 3 && x[a] + G.h <= 1.0 && x[a] - G.h >= -1.0;
+    }
+    if (inner) {
+      const float wx[2] = {1.f - f[0], f[0]}, wy[2] = {1.f - f[1], f[1]}, wz[2] = {1.f - f[2], f[2]};
+      float c[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) c[a] = dg[a] / (float)((x[a] + G.h) - (x[a] - G.h));
+      float* q = box + (k0[2] - 1 - lo[2]) * sz + (k0[1] - 1 - lo[1]) * sy + (k0[0] - 1 - lo[0]);
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const float yz = wy[jj] * wz[kk];
+          float* row = q + (kk + 1) * sz + (jj + 1) * sy;
+          atomicAdd(row, -c[0] * wx[0] * yz);
+          atomicAdd(row + 3, c[0] * wx[1] * yz);
+          const float yv = jj == 0 ? -c[1] * wy[1] : c[1] * wy[0];
+          const float zv = kk == 0 ? -c[2] * wz[1] : c[2] * wz[0];
+#pragma unroll
+          for (int ii = 0; ii < 2; ++ii) {
+            const float xv = ii == 0 ? -c[0] * wx[1] : c[0] * wx[0];
+            atomicAdd(row + ii + 1, (a0 * wx[ii] + xv) * yz + yv * wx[ii] * wz[kk] +
+                                        zv * wx[ii] * wy[jj]);
+          }
+        }
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+          const float xz = wx[ii] * wz[kk];
+          float* col = q + (kk + 1) * sz + ii + 1;
+          atomicAdd(col, -c[1] * wy[0] * xz);
+          atomicAdd(col + 3 * sy, c[1] * wy[1] * xz);
+        }
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+          const float xy = wx[ii] * wy[jj];
+          float* col = q + (jj + 1) * sy + ii + 1;
+          atomicAdd(col, -c[2] * wz[0] * xy);
+          atomicAdd(col + 3 * sz, c[2] * wz[1] * xy);
+        }
+    } else {
+      const PatchDst D{box, lo[0], lo[1], lo[2], sy, sz};
+      if (a0 != 0.f) patch_add<true>(D, k0, x, G.R, G.inv_h, a0);
+      if (dg[0] != 0.f || dg[1] != 0.f || dg[2] != 0.f) fd_patch<true>(D, k0, G, x, dg);
+    }
   }
   wave_sync();
-  box_flush(box, ext[0], ext[1] * ext[2], ext[1], D.ox, D.oy, D.oz, G.R, 1, g_sdf, lane);
+  box_flush<1>(box, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_sdf, lane);
   wave_sync();
   return true;
 }
 
-// spatial features: 8 corners x 3 channels per sample
-__device__ __forceinline__ bool feat_box_wave(float* box, int lane, bool ve, const double x[3],
-                                              const Cell& cs, const float dz[NIN], const Geo& G,
+// spatial-feature box pass: 8 corners x NF channels per lane with `part` set
+__device__ __forceinline__ bool feat_box_pass(float* box, int cap, int lane, bool part,
+                                              const double x[3], const float df[NF], const Geo& G,
                                               float* g_feat) {
-  if (!wave_any(ve)) return true;
   int k[3] = {0, 0, 0};
-  if (ve) cell_k(x, G.R, G.inv_h, k);
+  float f[3] = {0.f, 0.f, 0.f};
+  if (part) {
+    const double kmax = (double)(G.R - 2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) axis_cell_d(x[a], G.inv_h, kmax, k[a], f[a]);
+  }
   int lo[3], ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = wave_min_i(ve ? k[a] : 0x7FFFFFFF);
-    ext[a] = wave_max_i(ve ? k[a] : -0x7FFFFFFF) - lo[a] + 2;  // nodes lo .. hi+1
+    lo[a] = wave_min_i(part ? k[a] : 0x7FFFFFFF);  // nodes k .. k+1
+    ext[a] = wave_max_i(part ? k[a] : -0x7FFFFFFF) - lo[a] + 2;
   }
-  if ((int64_t)ext[0] * ext[1] * ext[2] * NF > BOXCAP) return false;
+  if ((int64_t)ext[0] * ext[1] * ext[2] * NF > cap) return false;
   const int vol = ext[0] * ext[1] * ext[2];
   for (int i = lane; i < vol * NF; i += 64) box[i] = 0.f;
   wave_sync();
-  if (ve) {
+  if (part) {
     float wc[8];
-    corner_w(cs, wc);
+    corner_w(Cell{0, f[0], f[1], f[2]}, wc);
     const int b = ((k[2] - lo[2]) * ext[1] + (k[1] - lo[1])) * ext[0] + (k[0] - lo[0]);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int o = b + (c & 1) + ((c >> 1) & 1) * ext[0] + ((c >> 2) & 1) * ext[0] * ext[1];
 #pragma unroll
-      for (int ch = 0; ch < NF; ++ch) atomicAdd(&box[o * NF + ch], wc[c] * dz[ch]);
+      for (int ch = 0; ch < NF; ++ch) atomicAdd(&box[o * NF + ch], wc[c] * df[ch]);
     }
   }
   wave_sync();
-  box_flush(box, ext[0] * NF, ext[1] * ext[2], ext[1], lo[0], lo[1], lo[2], G.R, NF, g_feat, lane);
+  box_flush<NF>(box, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_feat, lane);
   wave_sync();
   return true;
+}
+
+// Runs a box pass over the lanes with `ve` set: all of them at once when their
+// nodes fit, else in groups of 16 lanes, then 4, then one (a single lane's nodes
+// always fit a box of at least 64 floats).
+template <typename Pass>
+__device__ __forceinline__ void box_in_groups(bool ve, int lane, Pass pass) {
+  if (!wave_any(ve)) return;
+  if (pass(ve)) return;
+  bool pending = ve;
+  for (int gs = 16; gs >= 1; gs >>= 2) {
+    for (int g0 = 0; g0 < 64; g0 += gs) {
+      const bool part = pending && (unsigned)(lane - g0) < (unsigned)gs;
+      if (!wave_any(part)) continue;
+      if (pass(part)) pending = pending && !part;
+    }
+    if (!wave_any(pending)) return;
+  }
 }
 
 // MLP weight gradients of the wave's entries, summed on MFMA (K = samples)

@@ -36,27 +36,42 @@ constexpr int64_t kHead = 256;
 constexpr int kScan = 1024;  // items per scan block
 int64_t al256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 int64_t n_waves_of(int64_t B) { return (B + 63) / 64; }
-int64_t p3_of(int P) { return (int64_t)P * P * P; }
-int64_t nsum_of(int P) { return (p3_of(P) + kScan - 1) / kScan; }
+// Probe cells are binned under a key that keeps space together: blocks of 2x2x2
+// cells in row-major order, the 8 cells of a block consecutive.  Cells span
+// 0..P-2 per axis, so P/2 blocks per axis.
+int64_t nblk_of(int P) {
+  const int64_t nb = P / 2;
+  return nb * nb * nb;
+}
+int64_t nkeys_of(int P) { return 8 * nblk_of(P); }
+int64_t nsum_of(int P) { return (nkeys_of(P) + kScan - 1) / kScan; }
 constexpr int64_t kMlpPart = (int64_t)NMLP * kMlpWaves * 4;
 int64_t fixed_bytes(int64_t B, int P) {
-  return kHead + 3 * al256(n_waves_of(B) * 4) + 3 * al256(p3_of(P) * 4) + al256(nsum_of(P) * 4) +
+  return kHead + 3 * al256(n_waves_of(B) * 4) + 3 * al256(nkeys_of(P) * 4) + al256(nsum_of(P) * 4) +
          kMlpPart;
 }
-constexpr int64_t kPerSample = (int64_t)sizeof(BwdEntry) + (int64_t)sizeof(ProbeRec) + 4;
+constexpr int64_t kPerSample =
+    (int64_t)sizeof(BwdEntry) + (int64_t)sizeof(ProbeRec) + (int64_t)sizeof(ScatRec) + 4;
+// box-pass batches: each occupied block of cells ends at most one partial batch
+int64_t ndesc_of(int P, int64_t cap) { return nblk_of(P) + 1 + cap / 64; }
 }  // namespace
 
-int64_t bwd_ws_bytes(int64_t B, int P, int64_t cap) { return fixed_bytes(B, P) + cap * kPerSample; }
+int64_t bwd_ws_bytes(int64_t B, int P, int64_t cap) {
+  return fixed_bytes(B, P) + cap * kPerSample + al256(ndesc_of(P, cap) * 8);
+}
 
 int64_t bwd_ws_capacity(int64_t B, int P, int64_t bytes) {
-  // slot indices are 32-bit
-  const int64_t r = bytes - fixed_bytes(B, P);
-  return r > 0 ? min(r / kPerSample, (int64_t)INT32_MAX) : 0;
+  // the largest cap whose layout fits (slot indices are 32-bit)
+  const int64_t r = bytes - fixed_bytes(B, P) - al256((nblk_of(P) + 1) * 8) - 256;
+  if (r <= 0) return 0;
+  int64_t cap = min(r * 64 / (64 * kPerSample + 8), (int64_t)INT32_MAX);
+  while (cap > 0 && bwd_ws_bytes(B, P, cap) > bytes) --cap;
+  return cap;
 }
 
 BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   char* p = static_cast<char*>(base);
-  const int64_t nw = n_waves_of(B), arr = al256(nw * 4), parr = al256(p3_of(P) * 4);
+  const int64_t nw = n_waves_of(B), arr = al256(nw * 4), parr = al256(nkeys_of(P) * 4);
   BwdWs w;
   w.counter = reinterpret_cast<unsigned long long*>(p);
   w.overflow = reinterpret_cast<int*>(p + kHead);
@@ -67,22 +82,45 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   w.plist = reinterpret_cast<int*>(p + kHead + 3 * arr + 2 * parr);
   w.psum = reinterpret_cast<int*>(p + kHead + 3 * arr + 3 * parr);
   w.mlp_part = reinterpret_cast<float*>(p + kHead + 3 * arr + 3 * parr + al256(nsum_of(P) * 4));
+  w.nbatch = reinterpret_cast<int*>(p + 24);
   w.pocc = reinterpret_cast<int*>(p + 8);
   w.cap = bwd_ws_capacity(B, P, bytes);
   w.entries = reinterpret_cast<BwdEntry*>(p + fixed_bytes(B, P));
   w.precs = reinterpret_cast<ProbeRec*>(p + fixed_bytes(B, P) + w.cap * (int64_t)sizeof(BwdEntry));
-  w.perm = reinterpret_cast<int*>(p + fixed_bytes(B, P) +
-                                  w.cap * (int64_t)(sizeof(BwdEntry) + sizeof(ProbeRec)));
+  w.srecs = reinterpret_cast<ScatRec*>(p + fixed_bytes(B, P) +
+                                       w.cap * (int64_t)(sizeof(BwdEntry) + sizeof(ProbeRec)));
+  w.perm = reinterpret_cast<int*>(
+      p + fixed_bytes(B, P) + w.cap * (int64_t)(sizeof(BwdEntry) + sizeof(ProbeRec) + sizeof(ScatRec)));
   w.nsorted = reinterpret_cast<int*>(p + 16);
+  w.ndesc = ndesc_of(P, w.cap);
+  w.bdesc = reinterpret_cast<int2*>(p + fixed_bytes(B, P) + w.cap * kPerSample);
   w.n_waves = nw;
-  w.P3 = p3_of(P);
+  w.nkeys = nkeys_of(P);
   w.nsum = nsum_of(P);
   w.probe_bins = 0;
   w.bins = 0;
   return w;
 }
 
-static_assert(sizeof(BwdEntry) == 160 && sizeof(ProbeRec) == 48, "record layouts");
+static_assert(sizeof(BwdEntry) == 160 && sizeof(ProbeRec) == 48 && sizeof(ScatRec) == 64,
+              "record layouts");
+
+// key of the probe cell with flat corner index `base`
+__device__ __forceinline__ int probe_key(int base, int P) {
+  const int x = base % P, yz = base / P, y = yz % P, z = yz / P;
+  const int nb = P / 2;
+  const int blk = ((z >> 1) * nb + (y >> 1)) * nb + (x >> 1);
+  return blk * 8 + ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+}
+
+// flat corner index of the probe cell with key `key`
+__device__ __forceinline__ int probe_cell_of_key(int key, int P) {
+  const int nb = P / 2;
+  const int blk = key >> 3;
+  const int bx = blk % nb, byz = blk / nb, by = byz % nb, bz = byz / nb;
+  const int x = 2 * bx + (key & 1), y = 2 * by + ((key >> 1) & 1), z = 2 * bz + ((key >> 2) & 1);
+  return (z * P + y) * P + x;
+}
 
 // waves = 1: reset the slot counter and the overflow flags (before a march or a
 // taped forward); probe_bins: reset the probe-cell counts
@@ -91,13 +129,14 @@ __global__ void __launch_bounds__(256) bwd_ws_clear_kernel(BwdWs ws, int waves) 
   if (i == 0) {
     if (waves) *ws.counter = 0;
     *ws.pocc = 0;
+    *ws.nbatch = 0;
   }
   if (waves && i < ws.n_waves) ws.overflow[i] = 0;
-  if (ws.bins && i < ws.P3) ws.pcount[i] = 0;
+  if (ws.bins && i < ws.nkeys) ws.pcount[i] = 0;
 }
 
 static hipError_t launch_clear(const BwdWs& ws, int waves, hipStream_t s) {
-  const int64_t n = max(waves ? ws.n_waves : (int64_t)1, ws.bins ? ws.P3 : (int64_t)1);
+  const int64_t n = max(waves ? ws.n_waves : (int64_t)1, ws.bins ? ws.nkeys : (int64_t)1);
   hipLaunchKernelGGL(bwd_ws_clear_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ws,
                      waves);
   return hipGetLastError();
@@ -209,7 +248,7 @@ __global__ void __launch_bounds__(BLOCK) bwd_march_kernel(RenderArgs a, BwdWs ws
         const RayD& rr = L.ray[key & 63];
         BwdEntry e;
         sample_pos(rr, sample_t(rr, key >> 6), e.x);
-        pc = cell_d(e.x, a.P, inv_hp).base;
+        pc = probe_key(cell_d(e.x, a.P, inv_hp).base, a.P);
         e.v[0] = (float)-rr.d[0];
         e.v[1] = (float)-rr.d[1];
         e.v[2] = (float)-rr.d[2];
@@ -277,7 +316,7 @@ __global__ void __launch_bounds__(256) scan_sums_kernel(BwdWs ws) {
   const int64_t i0 = (int64_t)blockIdx.x * kScan + threadIdx.x * 4;
   int v = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) v += i0 + k < ws.P3 ? ws.pcount[i0 + k] : 0;
+  for (int k = 0; k < 4; ++k) v += i0 + k < ws.nkeys ? ws.pcount[i0 + k] : 0;
   int excl;
   const int tot = block_excl_scan(v, part, excl);
   if (threadIdx.x == 0) ws.psum[blockIdx.x] = tot;
@@ -298,27 +337,39 @@ __global__ void __launch_bounds__(256) scan_partials_kernel(BwdWs ws) {
   if (threadIdx.x == 0) *ws.nsorted = carry;
 }
 
-// offsets of every cell, and the list of occupied cells
+// offsets of every cell, the list of occupied cells, and the box-pass batches
+// (each block of 2x2x2 cells in runs of up to 64 samples)
 __global__ void __launch_bounds__(256) scan_offsets_kernel(BwdWs ws) {
+  static_assert(kScan % 8 == 0, "a block of 8 keys is two threads of one scan block");
   __shared__ int part[4];
-  __shared__ int lbase;
+  __shared__ int lbase, bbase;
   const int64_t i0 = (int64_t)blockIdx.x * kScan + threadIdx.x * 4;
   int c[4], v = 0, occ = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    c[k] = i0 + k < ws.P3 ? ws.pcount[i0 + k] : 0;
+    c[k] = i0 + k < ws.nkeys ? ws.pcount[i0 + k] : 0;
     v += c[k];
     occ += c[k] > 0;
   }
-  int excl, oexcl;
+  // keys 8j .. 8j+7 (one block of cells) are threads 2j and 2j+1
+  const int bv = v + __shfl_xor(v, 1, 64);
+  const int nb = (threadIdx.x & 1) == 0 ? (bv + 63) / 64 : 0;
+  int excl, oexcl, bexcl;
   block_excl_scan(v, part, excl);
   const int otot = block_excl_scan(occ, part, oexcl);
-  if (threadIdx.x == 0) lbase = otot > 0 ? atomicAdd(ws.pocc, otot) : 0;
+  const int btot = block_excl_scan(nb, part, bexcl);
+  if (threadIdx.x == 0) {
+    lbase = otot > 0 ? atomicAdd(ws.pocc, otot) : 0;
+    bbase = btot > 0 ? atomicAdd(ws.nbatch, btot) : 0;
+  }
   __syncthreads();
   int o = ws.psum[blockIdx.x] + excl, li = lbase + oexcl;
+  for (int q = 0; q < nb; ++q)
+    if (bbase + bexcl + q < ws.ndesc)
+      ws.bdesc[bbase + bexcl + q] = make_int2(o + 64 * q, min(64, bv - 64 * q));
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (i0 + k < ws.P3) ws.pcursor[i0 + k] = o;
+    if (i0 + k < ws.nkeys) ws.pcursor[i0 + k] = o;
     if (c[k] > 0) ws.plist[li++] = (int)(i0 + k);
     o += c[k];
   }
@@ -332,7 +383,6 @@ struct ShadeLds {
   union {
     DwLds dw;
     float sc[64][65];
-    float box[BOXCAP];
   } u;
   int k0[64][3];
   int fb[64];
@@ -429,44 +479,49 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
     }
     float dpre[HID], dz[NIN];
     mlp_backward_lane<M>(W, dout, pre, ve, dpre, dz);
-    // SDF through the normal; with a tape also the opacity path at s_i (this
-    // sample's alpha and the previous sample's, which meet at x_i); the rest of
-    // the opacity path is scattered by the per-ray walk
-    bool box_done = false;
     if constexpr (TAPE) {
-      // the batch is spatially compact (one or a few neighbouring probe cells):
-      // its SDF and feature gradients are summed in one LDS box and each touched
-      // node is flushed once, in row-contiguous runs
-      if (a.g_sdf) {
-        const float a0 = ve ? a.tau * sigmoidf(-a.tau * E.s0) * (E.gdl_prev - E.gdl) : 0.f;
-        box_done = sdf_box_wave(L.u.box, lane, ve, x, v, nm, dz, a0, G, a.g_sdf);
+      // the SDF and feature cotangents go to the sample's sorted slot; the box
+      // pass scatters them (SDF: the normal path and the opacity path at s_i,
+      // where this sample's alpha and the previous sample's meet; the rest of the
+      // opacity path is scattered by the per-ray walk)
+      if (lane < n) {
+        ScatRec r;
+        r.x[0] = x[0];
+        r.x[1] = x[1];
+        r.x[2] = x[2];
+        r.dg[0] = r.dg[1] = r.dg[2] = 0.f;
+        if (ve && !(G.flags & FLAG_NV_ONE)) normal_dg(v, nm, dz, r.dg);
+        r.a0 = ve ? a.tau * sigmoidf(-a.tau * E.s0) * (E.gdl_prev - E.gdl) : 0.f;
+        const bool fs = ve && !(G.flags & FLAG_NO_FS);
+        r.df[0] = fs ? dz[0] : 0.f;
+        r.df[1] = fs ? dz[1] : 0.f;
+        r.df[2] = fs ? dz[2] : 0.f;
+        r.valid = ve ? 1 : 0;
+        r.pad[0] = r.pad[1] = 0.f;
+        ws.srecs[slot] = r;
       }
-    }
-    if (!box_done && a.g_sdf && (TAPE || !(G.flags & FLAG_NV_ONE))) {
-      float* row = L.u.sc[lane];
+    } else {
+      // SDF through the normal (the opacity path is scattered by the per-ray pass)
+      if (a.g_sdf && !(G.flags & FLAG_NV_ONE)) {
+        float* row = L.u.sc[lane];
 #pragma unroll
-      for (int q = 0; q < 64; ++q) row[q] = 0.f;
-      if (ve) {
-        int k0[3];
-        cell_k(x, G.R, G.inv_h, k0);
-        L.k0[lane][0] = k0[0];
-        L.k0[lane][1] = k0[1];
-        L.k0[lane][2] = k0[2];
-        if constexpr (TAPE) {
-          const float a0 = a.tau * sigmoidf(-a.tau * E.s0) * (E.gdl_prev - E.gdl);
-          if (a0 != 0.f) patch_add(patch_of_row(row, k0), k0, x, G.R, G.inv_h, a0);
+        for (int q = 0; q < 64; ++q) row[q] = 0.f;
+        if (ve) {
+          int k0[3];
+          cell_k(x, G.R, G.inv_h, k0);
+          L.k0[lane][0] = k0[0];
+          L.k0[lane][1] = k0[1];
+          L.k0[lane][2] = k0[2];
+          normal_backward_patch(patch_of_row(row, k0), k0, G, x, v, nm, dz);
         }
-        if (!(G.flags & FLAG_NV_ONE)) normal_backward_patch(patch_of_row(row, k0), k0, G, x, v, nm, dz);
+        wave_sync();
+        sdf_patch_flush(L.u.sc, L.k0, n, lane, G.R, a.g_sdf);
+        wave_sync();
       }
-      wave_sync();
-      sdf_patch_flush(L.u.sc, L.k0, n, lane, G.R, a.g_sdf);
-      wave_sync();
-    }
-    if (!(G.flags & FLAG_NO_FS) && a.g_feat) {
-      const Cell cs = cell_d(x, G.R, G.inv_h);
-      bool fdone = false;
-      if constexpr (TAPE) fdone = feat_box_wave(L.u.box, lane, ve, x, cs, dz, G, a.g_feat);
-      if (!fdone) feat_scatter_wave(L.u.sc, L.fb, ve, cs, dz, n, lane, G.R, a.g_feat);
+      if (!(G.flags & FLAG_NO_FS) && a.g_feat) {
+        const Cell cs = cell_d(x, G.R, G.inv_h);
+        feat_scatter_wave(L.u.sc, L.fb, ve, cs, dz, n, lane, G.R, a.g_feat);
+      }
     }
     if (TAPE && ws.probe_bins) {
       // the sample's probe record goes to its own sorted slot
@@ -502,7 +557,7 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
       // its leader's base
       int first = 0, my_leader = 0;
       uint64_t my_grp = 0;
-      for_each_key_group(counted, cp.base, [&](int k, int leader, uint64_t grp) {
+      for_each_key_group(counted, probe_key(cp.base, G.P), [&](int k, int leader, uint64_t grp) {
         if (lane == leader) first = atomicAdd(ws.pcursor + k, (int)__popcll(grp));
         if ((grp >> lane) & 1ull) {
           my_leader = leader;
@@ -551,6 +606,52 @@ __global__ void __launch_bounds__(256) mlp_reduce_kernel(BwdWs ws, int nwaves, f
 }
 
 // ---------------------------------------------------------------------------
+// taped schedule, box pass: a wave takes one occupied block of 2x2x2 probe cells
+// (its samples are contiguous in the sorted slots) and scatters their records 64
+// at a time; the SDF and feature gradients of a batch are summed in an LDS box and
+// each touched node is flushed once, in row-contiguous runs.  A block spans about
+// 2 (R-1)/(P-1) grid cells per axis, so a batch's box normally fits; if not, the
+// batch is split into groups of lanes.  Few registers and a modest box keep
+// several waves resident to cover the latency of the flush atomics.
+// ---------------------------------------------------------------------------
+constexpr int kBoxCap = 3072;  // floats of a wave's box
+static_assert(kBoxCap >= 64 && kBoxCap >= 8 * NF, "one sample's nodes fit a box");
+
+__global__ void __launch_bounds__(BLOCK) bwd_box_kernel(RenderArgs a, BwdWs ws) {
+  __shared__ float boxes[WAVES][kBoxCap];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float* box = boxes[wv];
+  const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
+  const int nbat = (int)min((int64_t)*ws.nbatch, ws.ndesc);
+  const bool do_f = a.g_feat && !(G.flags & FLAG_NO_FS);
+  for (int j0 = xcd_block(blockIdx.x, gridDim.x) * WAVES + wv; j0 < nbat;
+       j0 += gridDim.x * WAVES) {
+    // batches in a scrambled order (j0 * K mod nbat, K a prime above any batch
+    // count): waves running at the same time flush distant parts of the surface
+    const int2 bd = ws.bdesc[(int)(((uint64_t)j0 * 2654435761ull) % (uint64_t)nbat)];
+    // every load comes before the flush atomics, and one wait here covers them
+    // (a first use inside a pass would also wait for the atomics issued so far)
+    ScatRec r = ws.srecs[bd.x + min(lane, bd.y - 1)];
+    __builtin_amdgcn_s_waitcnt(0);
+    const bool ve = lane < bd.y && r.valid != 0;
+    if (!ve) {
+      r.x[0] = r.x[1] = r.x[2] = 0.0;
+      r.dg[0] = r.dg[1] = r.dg[2] = 0.f;
+      r.a0 = 0.f;
+      r.df[0] = r.df[1] = r.df[2] = 0.f;
+    }
+    if (a.g_sdf)
+      box_in_groups(ve, lane, [&](bool part) {
+        return sdf_box_pass(box, kBoxCap, lane, part, r.x, r.dg, r.a0, G, a.g_sdf);
+      });
+    if (do_f)
+      box_in_groups(ve, lane, [&](bool part) {
+        return feat_box_pass(box, kBoxCap, lane, part, r.x, r.df, G, a.g_feat);
+      });
+  }
+}
+
+// ---------------------------------------------------------------------------
 // pass 4: probe gradient per occupied probe cell
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float rdlane(float v, int l) {
@@ -566,9 +667,10 @@ __global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs
   const int j = min(lane >> 2, NSH - 1), k = lane & 3;
   const int nocc = *ws.pocc;
   for (int oi = gw; oi < nocc; oi += nw) {
-    const int cell = ws.plist[oi];
-    const int cnt = ws.pcount[cell];
-    const int end = ws.pcursor[cell];  // advanced by the placement to offset + count
+    const int key = ws.plist[oi];
+    const int cell = probe_cell_of_key(key, a.P);
+    const int cnt = ws.pcount[key];
+    const int end = ws.pcursor[key];  // advanced by the placement to offset + count
     float acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.f;
@@ -630,7 +732,7 @@ __global__ void __launch_bounds__(BLOCK) tape_count_kernel(RenderArgs a, BwdWs w
       const BwdEntry& E = ws.entries[e];
       counted = E.lw >= 0;
       const double xs[3] = {E.x[0], E.x[1], E.x[2]};
-      if (counted) pc = cell_d(xs, a.P, inv_hp).base;
+      if (counted) pc = probe_key(cell_d(xs, a.P, inv_hp).base, a.P);
     }
     for_each_key_group(counted, pc, [&](int k, int leader, uint64_t grp) {
       if (lane == leader) atomicAdd(ws.pcount + k, (int)__popcll(grp));
@@ -653,7 +755,7 @@ __global__ void __launch_bounds__(BLOCK) tape_place_kernel(RenderArgs a, BwdWs w
       const BwdEntry& E = ws.entries[e];
       counted = E.lw >= 0;
       const double xs[3] = {E.x[0], E.x[1], E.x[2]};
-      if (counted) pc = cell_d(xs, a.P, inv_hp).base;
+      if (counted) pc = probe_key(cell_d(xs, a.P, inv_hp).base, a.P);
     }
     int first = 0, my_leader = 0;
     uint64_t my_grp = 0;
@@ -903,10 +1005,14 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
   if (a.g_mlp)
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3(NMLP), dim3(256), 0, s, ws, (int)(sgrid.x * WAVES),
                        a.g_mlp);
+  if (from_tape && (a.g_sdf || a.g_feat)) {
+    const dim3 bgrid((unsigned)max((int64_t)1, min(want, (int64_t)2048)));
+    hipLaunchKernelGGL(bwd_box_kernel, bgrid, dim3(BLOCK), 0, s, a, ws);
+  }
   if (ws.probe_bins) {
     // one wave per occupied cell (the count is on the device: enough waves for
     // a dense band, each looping)
-    const int64_t pw = min(ws.P3, (int64_t)16384);
+    const int64_t pw = min(ws.nkeys, (int64_t)16384);
     const dim3 pgrid((unsigned)max((int64_t)1, (pw + WAVES - 1) / WAVES));
     PSDF_SH_SWITCH(n_sh,
         hipLaunchKernelGGL((probe_reduce_kernel<NSH>), pgrid, dim3(BLOCK), 0, s, a, ws));

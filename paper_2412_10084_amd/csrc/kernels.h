@@ -68,6 +68,17 @@ struct ProbeRec {
   float pad;
 };
 
+// SDF and feature cotangents of one shaded sample, in probe-cell order (taped
+// schedule): written by the shading pass, scattered by the box pass.
+struct ScatRec {
+  double x[3];    // sample position
+  float dg[3];    // dL/d(FD gradient of the SDF at x) through the normal
+  float a0;       // dL/ds_i through the opacities of samples i and i-1
+  float df[3];    // dL/d(spatial features at x)
+  int valid;      // 0: the slot holds no sample to scatter
+  float pad[2];
+};
+
 // most waves a shading pass launches (1024 blocks of 4 waves)
 constexpr int kMlpWaves = 4096;
 
@@ -82,14 +93,18 @@ struct BwdWs {
   int* psum;           // [nsum] scan partials
   int* plist;          // [P^3] occupied probe cells (first *pocc entries)
   int* pocc;           // [1]
+  int* nbatch;         // [1] batches of the box pass
+  int2* bdesc;         // [ndesc] (first sorted slot, samples): up to 64 samples of one
+                       // block of 2x2x2 probe cells
   int* nsorted;        // [1] samples filed in probe-cell order (taped schedule)
   int* perm;           // [cap] entry of each sorted slot (taped schedule)
   float* mlp_part;     // [kMlpWaves][227] MLP gradient partials of the shading waves
   BwdEntry* entries;   // [cap]
   ProbeRec* precs;     // [cap] in probe-cell order
-  int64_t cap;
+  ScatRec* srecs;      // [cap] in probe-cell order (taped schedule)
+  int64_t cap, ndesc;
   int64_t n_waves;
-  int64_t P3, nsum;
+  int64_t nkeys, nsum;  // probe-cell keys (bins) and scan blocks
   int probe_bins;      // 1: the probe gradient goes through the cell bins
   int bins;            // 1: samples are counted per probe cell (probe bins or taped order)
 };

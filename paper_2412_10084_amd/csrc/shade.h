@@ -466,15 +466,11 @@ __device__ __forceinline__ void patch_add(const PatchDst& D, const int k0[3], co
   dst_add<SHARED>(q + sz + sy + 1, val * f[0] * f[1] * f[2]);
 }
 
-// SDF gradient of the normal path (c = n.v, n = g/|g|, g the FD gradient)
-template <bool SHARED = false>
-__device__ __forceinline__ void normal_backward_patch(const PatchDst& D, const int k0[3],
-                                                      const Geo& G, const double x[3],
-                                                      const float v[3], const Normal& nm,
-                                                      const float dz[NIN]) {
+// cotangent of the FD gradient g through the normal path (c = n.v, n = g/|g|)
+__device__ __forceinline__ void normal_dg(const float v[3], const Normal& nm, const float dz[NIN],
+                                          float dg[3]) {
   const float c = nm.c;
   const float dc = dz[7] + 2.0f * c * dz[8] + 4.0f * c * c * c * dz[9];
-  float dg[3];
   if (nm.gn >= 1e-30f) {
     const float sc = dc / nm.gn;
 #pragma unroll
@@ -483,6 +479,12 @@ __device__ __forceinline__ void normal_backward_patch(const PatchDst& D, const i
 #pragma unroll
     for (int a = 0; a < 3; ++a) dg[a] = dc * v[a] / 1e-30f;
   }
+}
+
+// SDF gradient from the cotangent dg of the central-difference gradient at x
+template <bool SHARED = false>
+__device__ __forceinline__ void fd_patch(const PatchDst& D, const int k0[3], const Geo& G,
+                                         const double x[3], const float dg[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
@@ -492,6 +494,17 @@ __device__ __forceinline__ void normal_backward_patch(const PatchDst& D, const i
     patch_add<SHARED>(D, k0, xp, G.R, G.inv_h, coef);
     patch_add<SHARED>(D, k0, xm, G.R, G.inv_h, -coef);
   }
+}
+
+// SDF gradient of the normal path
+template <bool SHARED = false>
+__device__ __forceinline__ void normal_backward_patch(const PatchDst& D, const int k0[3],
+                                                      const Geo& G, const double x[3],
+                                                      const float v[3], const Normal& nm,
+                                                      const float dz[NIN]) {
+  float dg[3];
+  normal_dg(v, nm, dz, dg);
+  fd_patch<SHARED>(D, k0, G, x, dg);
 }
 
 // ---------------------------------------------------------------------------
