@@ -77,15 +77,35 @@ __device__ __forceinline__ void feat_scatter_wave(float (*sc)[65], int* fb, bool
 // whole wave.
 // ---------------------------------------------------------------------------
 
+// Wave-wide min / max (call with every lane active), on DPP lane moves: a scan
+// within each row of 16 lanes (shifts 1, 2, 4, 8), then rows combined by the row
+// broadcasts of lanes 15 and 31, so lane 63 holds the result.
 __device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
-  return v;
+  constexpr int kId = 0x7FFFFFFF;
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
 }
 __device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
-  return v;
+  constexpr int kId = -0x7FFFFFFF - 1;
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x111, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x112, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x114, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x118, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x142, 0xa, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// zero the first n floats of a 16-byte aligned box whose capacity is a multiple
+// of 4 floats (n <= capacity)
+__device__ __forceinline__ void box_clear(float* box, int n, int lane) {
+  float4* b4 = reinterpret_cast<float4*>(box);
+  for (int i = lane; i < (n + 3) / 4; i += 64) b4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // A box of ex x ey x ez nodes with C channels, origin (ox, oy, oz): rows of
@@ -103,6 +123,40 @@ __device__ __forceinline__ void box_flush(const float* box, int ex, int ey, int 
   int r = lane >> sh;
   int iz = r / ey, iy = r - iz * ey;
   const int dz = rows_per / ey, dy = rows_per - dz * ey;
+  if (row_len <= 64) {
+    // one element per lane and step; four steps at a time, their LDS reads first
+    const int nstep = (nrows + rows_per - 1) / rows_per;
+    const int gx = ox + x0 / C;
+    const bool x_in = x0 < row_len && gx >= 0 && gx < R;
+    for (int s0 = 0; s0 < nstep; s0 += 4) {
+      float v[4];
+      float* dst[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ru = r + u * rows_per;
+        int uy = iy + u * dy, uz = iz + u * dz;
+        while (uy >= ey) {
+          uy -= ey;
+          ++uz;
+        }
+        const int gy = oy + uy, gz = oz + uz;
+        const bool in = x_in && ru < nrows && gy >= 0 && gy < R && gz >= 0 && gz < R;
+        v[u] = in ? box[ru * row_len + x0] : 0.f;
+        dst[u] = g + ((int64_t)(gz * R + gy) * R + ox) * C + x0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (v[u] != 0.f) atomic_add_f32(dst[u], v[u]);
+      r += 4 * rows_per;
+      iy += 4 * dy;
+      iz += 4 * dz;
+      while (iy >= ey) {
+        iy -= ey;
+        ++iz;
+      }
+    }
+    return;
+  }
   for (int r0 = 0; r0 < nrows; r0 += rows_per) {
     if (r < nrows) {
       const int gy = oy + iy, gz = oz + iz;
@@ -142,7 +196,7 @@ __device__ __forceinline__ bool sdf_box_pass(float* box, int cap, int lane, bool
   }
   if ((int64_t)ext[0] * ext[1] * ext[2] > cap) return false;
   const int vol = ext[0] * ext[1] * ext[2];
-  for (int i = lane; i < vol; i += 64) box[i] = 0.f;
+  box_clear(box, vol, lane);
   wave_sync();
   const int sy = ext[0], sz = ext[0] * ext[1];
   if (part) {
@@ -230,7 +284,7 @@ __device__ __forceinline__ bool feat_box_pass(float* box, int cap, int lane, boo
   }
   if ((int64_t)ext[0] * ext[1] * ext[2] * NF > cap) return false;
   const int vol = ext[0] * ext[1] * ext[2];
-  for (int i = lane; i < vol * NF; i += 64) box[i] = 0.f;
+  box_clear(box, vol * NF, lane);
   wave_sync();
   if (part) {
     float wc[8];

@@ -616,9 +616,10 @@ __global__ void __launch_bounds__(256) mlp_reduce_kernel(BwdWs ws, int nwaves, f
 // ---------------------------------------------------------------------------
 constexpr int kBoxCap = 3072;  // floats of a wave's box
 static_assert(kBoxCap >= 64 && kBoxCap >= 8 * NF, "one sample's nodes fit a box");
+static_assert(kBoxCap % 4 == 0, "boxes are cleared in float4s");
 
 __global__ void __launch_bounds__(BLOCK) bwd_box_kernel(RenderArgs a, BwdWs ws) {
-  __shared__ float boxes[WAVES][kBoxCap];
+  __shared__ __align__(16) float boxes[WAVES][kBoxCap];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* box = boxes[wv];
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
