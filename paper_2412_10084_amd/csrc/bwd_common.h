@@ -108,17 +108,46 @@ __device__ __forceinline__ void box_clear(float* box, int n, int lane) {
   for (int i = lane; i < (n + 3) / 4; i += 64) b4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// LDS box accumulation.  The LDS executes FP32 atomic adds at a fraction of the
+// rate of integer ones, so a box normally holds 32-bit fixed point: each value is
+// scaled by sc = 2^30 / (64 B), B a bound on any one lane's contribution to a
+// node, and rounded; a node sums at most 64 lanes, so |sum| < 2^30, and the
+// rounding error is below B / 2^25 per contribution.  Integer sums are also
+// independent of the order of the adds.  Boxes with a non-finite or huge bound
+// (or boundary samples, SDF) take FP32 atomics.
+template <bool FIXED>
+__device__ __forceinline__ void box_add(float* p, float v, float sc) {
+  if constexpr (FIXED) atomicAdd(reinterpret_cast<int*>(p), __float2int_rn(v * sc));
+  else atomicAdd(p, v);
+}
+
+// wave-wide max of a non-negative float (NaN compares above +inf)
+__device__ __forceinline__ float wave_max_nonneg(float v) {
+  return __int_as_float(wave_max_i(__float_as_int(v)));
+}
+
+constexpr float kFixedMaxBound = 1e36f;  // larger bounds use FP32 atomics
+
+__device__ __forceinline__ float fixed_scale(float B) {
+  return B > 0.f ? 0x1p30f / (64.f * B) : 1.f;
+}
+
 // A box of ex x ey x ez nodes with C channels, origin (ox, oy, oz): rows of
-// ex * C floats, row r holding nodes (ox + x / C, oy + r % ey, oz + r / ey).  Each
-// nonzero value is added to the grid; a power-of-two group of lanes takes a row.
-template <int C>
-__device__ __forceinline__ void box_flush(const float* box, int ex, int ey, int ez, int ox, int oy,
-                                          int oz, int R, float* g, int lane) {
+// ex * C values, row r holding nodes (ox + x / C, oy + r % ey, oz + r / ey).  Each
+// nonzero value (fixed point: times inv) is added to the grid; a power-of-two
+// group of lanes takes a row.
+template <int C, bool FIXED>
+__device__ __forceinline__ void box_flush(const float* box, float inv, int ex, int ey, int ez,
+                                          int ox, int oy, int oz, int R, float* g, int lane) {
   const int row_len = ex * C, nrows = ey * ez;
   int lpr = 1;
   while (lpr < row_len && lpr < 64) lpr <<= 1;  // lanes per row
   const int sh = __builtin_ctz(lpr), rows_per = 64 >> sh;
   const int x0 = lane & (lpr - 1);
+  auto value = [&](int i) {
+    if constexpr (FIXED) return (float)reinterpret_cast<const int*>(box)[i] * inv;
+    else return box[i];
+  };
   // this lane's row, advanced by rows_per rows (dz planes + dy rows) per step
   int r = lane >> sh;
   int iz = r / ey, iy = r - iz * ey;
@@ -141,7 +170,7 @@ __device__ __forceinline__ void box_flush(const float* box, int ex, int ey, int 
         }
         const int gy = oy + uy, gz = oz + uz;
         const bool in = x_in && ru < nrows && gy >= 0 && gy < R && gz >= 0 && gz < R;
-        v[u] = in ? box[ru * row_len + x0] : 0.f;
+        v[u] = in ? value(ru * row_len + x0) : 0.f;
         dst[u] = g + ((int64_t)(gz * R + gy) * R + ox) * C + x0;
       }
 #pragma unroll
@@ -161,10 +190,9 @@ __device__ __forceinline__ void box_flush(const float* box, int ex, int ey, int 
     if (r < nrows) {
       const int gy = oy + iy, gz = oz + iz;
       const bool row_in = gy >= 0 && gy < R && gz >= 0 && gz < R;
-      const float* brow = box + r * row_len;
       float* grow = g + ((int64_t)(gz * R + gy) * R + ox) * C;
       for (int xx = x0; xx < row_len; xx += lpr) {
-        const float v = brow[xx];
+        const float v = value(r * row_len + xx);
         const int gx = ox + xx / C;
         if (v != 0.f && row_in && gx >= 0 && gx < R) atomic_add_f32(grow + xx, v);
       }
@@ -177,6 +205,51 @@ __device__ __forceinline__ void box_flush(const float* box, int ex, int ey, int 
       ++iz;
     }
   }
+}
+
+// The opacity term and the six FD terms of an interior sample, whose stencil
+// points x -/+ h e_a lie one cell below / above x's cell with x's fractions: 32
+// nodes of the 4x4x4 patch around the cell (its central 2x2x2 and two 2x2 end caps
+// per axis).  q points at the patch's lowest node.
+template <bool FIXED>
+__device__ __forceinline__ void sdf_cross_add(float* q, int sy, int sz, const float f[3],
+                                              const float c[3], float a0, float sc) {
+  const float wx[2] = {1.f - f[0], f[0]}, wy[2] = {1.f - f[1], f[1]}, wz[2] = {1.f - f[2], f[2]};
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const float yz = wy[jj] * wz[kk];
+      float* row = q + (kk + 1) * sz + (jj + 1) * sy;
+      box_add<FIXED>(row, -c[0] * wx[0] * yz, sc);
+      box_add<FIXED>(row + 3, c[0] * wx[1] * yz, sc);
+      const float yv = jj == 0 ? -c[1] * wy[1] : c[1] * wy[0];
+      const float zv = kk == 0 ? -c[2] * wz[1] : c[2] * wz[0];
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii) {
+        const float xv = ii == 0 ? -c[0] * wx[1] : c[0] * wx[0];
+        box_add<FIXED>(row + ii + 1,
+                       (a0 * wx[ii] + xv) * yz + yv * wx[ii] * wz[kk] + zv * wx[ii] * wy[jj], sc);
+      }
+    }
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii) {
+      const float xz = wx[ii] * wz[kk];
+      float* col = q + (kk + 1) * sz + ii + 1;
+      box_add<FIXED>(col, -c[1] * wy[0] * xz, sc);
+      box_add<FIXED>(col + 3 * sy, c[1] * wy[1] * xz, sc);
+    }
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii) {
+      const float xy = wx[ii] * wy[jj];
+      float* col = q + (jj + 1) * sy + ii + 1;
+      box_add<FIXED>(col, -c[2] * wz[0] * xy, sc);
+      box_add<FIXED>(col + 3 * sz, c[2] * wz[1] * xy, sc);
+    }
 }
 
 // SDF box pass over the lanes with `part` set: the opacity gradient at s_i
@@ -196,73 +269,58 @@ __device__ __forceinline__ bool sdf_box_pass(float* box, int cap, int lane, bool
   }
   if ((int64_t)ext[0] * ext[1] * ext[2] > cap) return false;
   const int vol = ext[0] * ext[1] * ext[2];
-  box_clear(box, vol, lane);
-  wave_sync();
   const int sy = ext[0], sz = ext[0] * ext[1];
+  float f[3] = {0.f, 0.f, 0.f}, c[3] = {0.f, 0.f, 0.f}, bnd = 0.f;
+  bool inner = true;
   if (part) {
-    // Away from the boundary the stencil points x -/+ h e_a lie one cell below /
-    // above x's cell with x's fractions, so the opacity term and the six FD terms
-    // touch 32 nodes of the 4x4x4 patch around the cell: its central 2x2x2 and
-    // two 2x2 end caps per axis.
-    float f[3];
-    bool inner = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double u = (x[a] + 1.0) * G.inv_h;
       f[a] = (float)(u - (double)k0[a]);
       inner = inner && k0[a] >= 1 && k0[a] <= G.R - 3 && x[a] + G.h <= 1.0 && x[a] - G.h >= -1.0;
+      c[a] = dg[a] / (float)((x[a] + G.h) - (x[a] - G.h));
     }
-    if (inner) {
-      const float wx[2] = {1.f - f[0], f[0]}, wy[2] = {1.f - f[1], f[1]}, wz[2] = {1.f - f[2], f[2]};
-      float c[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) c[a] = dg[a] / (float)((x[a] + G.h) - (x[a] - G.h));
-      float* q = box + (k0[2] - 1 - lo[2]) * sz + (k0[1] - 1 - lo[1]) * sy + (k0[0] - 1 - lo[0]);
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          const float yz = wy[jj] * wz[kk];
-          float* row = q + (kk + 1) * sz + (jj + 1) * sy;
-          atomicAdd(row, -c[0] * wx[0] * yz);
-          atomicAdd(row + 3, c[0] * wx[1] * yz);
-          const float yv = jj == 0 ? -c[1] * wy[1] : c[1] * wy[0];
-          const float zv = kk == 0 ? -c[2] * wz[1] : c[2] * wz[0];
-#pragma unroll
-          for (int ii = 0; ii < 2; ++ii) {
-            const float xv = ii == 0 ? -c[0] * wx[1] : c[0] * wx[0];
-            atomicAdd(row + ii + 1, (a0 * wx[ii] + xv) * yz + yv * wx[ii] * wz[kk] +
-                                        zv * wx[ii] * wy[jj]);
-          }
-        }
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-        for (int ii = 0; ii < 2; ++ii) {
-          const float xz = wx[ii] * wz[kk];
-          float* col = q + (kk + 1) * sz + ii + 1;
-          atomicAdd(col, -c[1] * wy[0] * xz);
-          atomicAdd(col + 3 * sy, c[1] * wy[1] * xz);
-        }
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-        for (int ii = 0; ii < 2; ++ii) {
-          const float xy = wx[ii] * wy[jj];
-          float* col = q + (jj + 1) * sy + ii + 1;
-          atomicAdd(col, -c[2] * wz[0] * xy);
-          atomicAdd(col + 3 * sz, c[2] * wz[1] * xy);
-        }
-    } else {
-      const PatchDst D{box, lo[0], lo[1], lo[2], sy, sz};
-      if (a0 != 0.f) patch_add<true>(D, k0, x, G.R, G.inv_h, a0);
-      if (dg[0] != 0.f || dg[1] != 0.f || dg[2] != 0.f) fd_patch<true>(D, k0, G, x, dg);
+    // every node of the patch gets at most |a0| + sum |c_a| (weights <= 1)
+    bnd = fabsf(a0) + fabsf(c[0]) + fabsf(c[1]) + fabsf(c[2]);
+  }
+  const float B = wave_max_nonneg(bnd);
+  const bool fixed = !wave_any(part && !inner) && B < kFixedMaxBound;
+  const float sc = fixed_scale(B);
+  box_clear(box, vol, lane);
+  wave_sync();
+  float* q = box + (k0[2] - 1 - lo[2]) * sz + (k0[1] - 1 - lo[1]) * sy + (k0[0] - 1 - lo[0]);
+  if (fixed) {
+    if (part) sdf_cross_add<true>(q, sy, sz, f, c, a0, sc);
+    wave_sync();
+    box_flush<1, true>(box, 1.f / sc, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_sdf, lane);
+  } else {
+    if (part) {
+      if (inner) {
+        sdf_cross_add<false>(q, sy, sz, f, c, a0, 1.f);
+      } else {
+        const PatchDst D{box, lo[0], lo[1], lo[2], sy, sz};
+        if (a0 != 0.f) patch_add<true>(D, k0, x, G.R, G.inv_h, a0);
+        if (dg[0] != 0.f || dg[1] != 0.f || dg[2] != 0.f) fd_patch<true>(D, k0, G, x, dg);
+      }
     }
+    wave_sync();
+    box_flush<1, false>(box, 1.f, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_sdf, lane);
   }
   wave_sync();
-  box_flush<1>(box, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_sdf, lane);
-  wave_sync();
   return true;
+}
+
+template <bool FIXED>
+__device__ __forceinline__ void feat_corner_add(float* box, int b, int ex, int exy, const float f[3],
+                                                const float df[NF], float sc) {
+  float wc[8];
+  corner_w(Cell{0, f[0], f[1], f[2]}, wc);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int o = b + (c & 1) + ((c >> 1) & 1) * ex + ((c >> 2) & 1) * exy;
+#pragma unroll
+    for (int ch = 0; ch < NF; ++ch) box_add<FIXED>(&box[o * NF + ch], wc[c] * df[ch], sc);
+  }
 }
 
 // spatial-feature box pass: 8 corners x NF channels per lane with `part` set
@@ -284,21 +342,26 @@ __device__ __forceinline__ bool feat_box_pass(float* box, int cap, int lane, boo
   }
   if ((int64_t)ext[0] * ext[1] * ext[2] * NF > cap) return false;
   const int vol = ext[0] * ext[1] * ext[2];
+  // a corner weight is at most 1
+  float bnd = 0.f;
+#pragma unroll
+  for (int ch = 0; ch < NF; ++ch) bnd = fmaxf(bnd, part ? fabsf(df[ch]) : 0.f);
+  const float B = wave_max_nonneg(bnd);
+  const bool fixed = B < kFixedMaxBound;
+  const float sc = fixed_scale(B);
   box_clear(box, vol * NF, lane);
   wave_sync();
-  if (part) {
-    float wc[8];
-    corner_w(Cell{0, f[0], f[1], f[2]}, wc);
-    const int b = ((k[2] - lo[2]) * ext[1] + (k[1] - lo[1])) * ext[0] + (k[0] - lo[0]);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int o = b + (c & 1) + ((c >> 1) & 1) * ext[0] + ((c >> 2) & 1) * ext[0] * ext[1];
-#pragma unroll
-      for (int ch = 0; ch < NF; ++ch) atomicAdd(&box[o * NF + ch], wc[c] * df[ch]);
-    }
+  const int b = ((k[2] - lo[2]) * ext[1] + (k[1] - lo[1])) * ext[0] + (k[0] - lo[0]);
+  if (fixed) {
+    if (part) feat_corner_add<true>(box, b, ext[0], ext[0] * ext[1], f, df, sc);
+    wave_sync();
+    box_flush<NF, true>(box, 1.f / sc, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_feat,
+                        lane);
+  } else {
+    if (part) feat_corner_add<false>(box, b, ext[0], ext[0] * ext[1], f, df, 1.f);
+    wave_sync();
+    box_flush<NF, false>(box, 1.f, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_feat, lane);
   }
-  wave_sync();
-  box_flush<NF>(box, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_feat, lane);
   wave_sync();
   return true;
 }
