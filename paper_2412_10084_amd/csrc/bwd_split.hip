@@ -89,7 +89,7 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   w.precs = reinterpret_cast<ProbeRec*>(p + fixed_bytes(B, P) + w.cap * (int64_t)sizeof(BwdEntry));
   w.srecs = reinterpret_cast<ScatRec*>(p + fixed_bytes(B, P) +
                                        w.cap * (int64_t)(sizeof(BwdEntry) + sizeof(ProbeRec)));
-  w.perm = reinterpret_cast<int*>(
+  w.islot = reinterpret_cast<int*>(
       p + fixed_bytes(B, P) + w.cap * (int64_t)(sizeof(BwdEntry) + sizeof(ProbeRec) + sizeof(ScatRec)));
   w.nsorted = reinterpret_cast<int*>(p + 16);
   w.ndesc = ndesc_of(P, w.cap);
@@ -398,29 +398,23 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
   const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
   const float* __restrict__ W = a.mlp;
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
-  // taped: the samples in probe-cell order (slots of perm); else: in the order the
-  // march wrote them
-  const int64_t total =
-      TAPE ? (int64_t)*ws.nsorted
-           : min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
+  // the entries in the order they were written (loads coalesce, and an entry's
+  // 64 neighbours come from one or two waves of rays); taped: the records go to
+  // the entry's slot in probe-cell order
+  const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
   const int64_t nbat = (total + 63) / 64;
 
   f4 acc_w1 = {0.f, 0.f, 0.f, 0.f}, acc_w2 = {0.f, 0.f, 0.f, 0.f};
   float db2[3] = {0.f, 0.f, 0.f};
   const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;
-  for (int64_t b0 = gw; b0 < nbat; b0 += (int64_t)gridDim.x * WAVES) {
-    // taped: sorted batches are visited in a scrambled order (b0 * K mod nbat with K
-    // a prime above any batch count), so that waves running at the same time work
-    // on distant parts of the surface and their flushes do not meet on the same
-    // lines; the plain schedule keeps the march's order
-    const int64_t b = TAPE ? (int64_t)(((uint64_t)b0 * 2654435761ull) % (uint64_t)nbat) : b0;
-    const int64_t slot = b * 64 + lane;
+  for (int64_t b = gw; b < nbat; b += (int64_t)gridDim.x * WAVES) {
+    const int64_t e = b * 64 + lane;
     const int n = (int)min((int64_t)64, total - b * 64);
-    int64_t e = slot;
     BwdEntry E;
+    int slot = -1;  // taped: the entry's sorted slot
     bool counted = false, ve = false;  // counted: holds a sample (has a probe bin slot)
     if (lane < n) {
-      if constexpr (TAPE) e = ws.perm[slot];
+      if constexpr (TAPE) slot = ws.islot[e];
       E = ws.entries[e];
       counted = E.lw >= 0;
       ve = counted && ws.overflow[E.lw] == 0;
@@ -484,7 +478,7 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
       // pass scatters them (SDF: the normal path and the opacity path at s_i,
       // where this sample's alpha and the previous sample's meet; the rest of the
       // opacity path is scattered by the per-ray walk)
-      if (lane < n) {
+      if (slot >= 0) {
         ScatRec r;
         r.x[0] = x[0];
         r.x[1] = x[1];
@@ -525,7 +519,7 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
     }
     if (TAPE && ws.probe_bins) {
       // the sample's probe record goes to its own sorted slot
-      if (lane < n) {
+      if (slot >= 0) {
         const double xs[3] = {E.x[0], E.x[1], E.x[2]};
         const Cell cp = cell_d(xs, G.P, G.inv_hp);
         ProbeRec pr;
@@ -741,8 +735,8 @@ __global__ void __launch_bounds__(BLOCK) tape_count_kernel(RenderArgs a, BwdWs w
   }
 }
 
-// sorted slot of every recorded sample: perm[slot] = entry, cells in index
-// order, the samples of a cell contiguous
+// sorted slot of every recorded sample (cells in key order, the samples of a
+// cell contiguous): islot[entry] = slot, -1 for a slot that holds no sample
 __global__ void __launch_bounds__(BLOCK) tape_place_kernel(RenderArgs a, BwdWs ws) {
   const int lane = threadIdx.x & 63;
   const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
@@ -768,7 +762,7 @@ __global__ void __launch_bounds__(BLOCK) tape_place_kernel(RenderArgs a, BwdWs w
       }
     });
     first = __shfl(first, my_leader, 64);
-    if (counted) ws.perm[first + lane_rank(my_grp)] = (int)e;
+    if (e < total) ws.islot[e] = counted ? first + lane_rank(my_grp) : -1;
   }
 }
 
