@@ -300,6 +300,7 @@ TRAFFIC_KERNELS = {
                         "psdf::scan_sums_kernel", "psdf::scan_partials_kernel",
                         "psdf::scan_offsets_kernel", "psdf::tape_place_kernel",
                         "psdf::tape_walk_kernel", "void psdf::bwd_shade_kernel<float, float, 9, 0, true>",
+                        "psdf::mlp_reduce_kernel", "psdf::bwd_box_kernel",
                         "void psdf::probe_reduce_kernel<9>",
                         "void psdf::render_bwd_kernel<float, float, 9, 0>"),
     "render_forward": ("void psdf::render_fwd_kernel<float, float, 9, 0>",),
