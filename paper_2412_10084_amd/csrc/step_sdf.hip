@@ -6,7 +6,7 @@
 // q_n = 2 (|g_n| - 1) g_n / |g_n| (0 off the interior or for g_n = 0):
 //   dL/ds_m = lambda / M * sum_a (q_{m-e_a,a} - q_{m+e_a,a}) / 2h,  M = (R-2)^3.
 // A workgroup owns a 64 x 8 column tile and marches it along z through a chunk
-// of 64 planes.  Three s planes (tile + 2 halo) and three q planes (tile + 1
+// of 16 planes.  Three s planes (tile + 2 halo) and three q planes (tile + 1
 // halo: 3 components and the node's loss term) rotate through LDS, so every s
 // value is read from memory about 1.6 times (halos) instead of 25 times and
 // every q is evaluated once per tile.  The next two s planes and the next two
@@ -17,7 +17,7 @@
 namespace psdf {
 
 namespace {
-constexpr int ETX = 64, ETY = 8, ETZ = 64;  // tile and z chunk
+constexpr int ETX = 64, ETY = 8, ETZ = 16;  // tile and z chunk
 constexpr int ETHREADS = 256;
 constexpr int SXW = ETX + 4, SYW = ETY + 4, SN = SXW * SYW;  // s plane region (halo 2)
 constexpr int SPER = (SN + ETHREADS - 1) / ETHREADS;         // s loads per thread per plane
