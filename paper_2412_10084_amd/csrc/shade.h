@@ -280,16 +280,83 @@ __device__ __forceinline__ void sdf_normal(const ST* __restrict__ sdf, const Geo
   for (int a = 0; a < 3; ++a) nm.n[a] = g[a] * inv;
 }
 
+// The same gradient for a sample whose stencil points x -/+ h e_a all lie one
+// cell below / above x's cell (k0) with x's fractions (no clamping at the grid
+// boundary): the six trilinear values share 32 nodes of the 4x4x4 patch around
+// k0 (rows of 4 along x through the central 2x2 in y, z; end pairs along y and z)
+// and the bilinear blends of those rows.  Returns false (nothing done) for any
+// other sample.
+template <typename ST>
+__device__ __forceinline__ bool sdf_normal_cross(const ST* __restrict__ sdf, const Geo& G,
+                                                 const double x[3], const Cell& c, Normal& nm) {
+  const int R = G.R, RR = R * R;
+  const int kx = c.base % R, kyz = c.base / R, ky = kyz % R, kz = kyz / R;
+  const int kk[3] = {kx, ky, kz};
+  bool inner = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    inner = inner && kk[a] >= 1 && kk[a] <= R - 3 && x[a] + G.h <= 1.0 && x[a] - G.h >= -1.0;
+  if (!inner) return false;
+  const int b = c.base;
+  // rows along x at (y, z) = (k0 + jj, k0 + kk): nodes k0-1 .. k0+2
+  float2 lo[2][2], hi[2][2], yc[2][2], zc[2][2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int rb = b - 1 + p * R + q * RR;
+      lo[p][q] = ld2(sdf, rb);
+      hi[p][q] = ld2(sdf, rb + 2);
+      // end pairs (x = k0, k0+1) at y = k0-1 / k0+2 (z = k0+q) and z = k0-1 / k0+2 (y = k0+q)
+      yc[p][q] = ld2(sdf, b + (p ? 2 : -1) * R + q * RR);
+      zc[p][q] = ld2(sdf, b + q * R + (p ? 2 : -1) * RR);
+    }
+  const float fx = c.fx, fy = c.fy, fz = c.fz;
+  auto yzb = [&](float v00, float v10, float v01, float v11) {
+    return lerpf(lerpf(v00, v10, fy), lerpf(v01, v11, fy), fz);
+  };
+  // x: blends of the four rows' nodes x = k0-1 .. k0+2
+  const float bx0 = yzb(lo[0][0].x, lo[1][0].x, lo[0][1].x, lo[1][1].x);
+  const float bx1 = yzb(lo[0][0].y, lo[1][0].y, lo[0][1].y, lo[1][1].y);
+  const float bx2 = yzb(hi[0][0].x, hi[1][0].x, hi[0][1].x, hi[1][1].x);
+  const float bx3 = yzb(hi[0][0].y, hi[1][0].y, hi[0][1].y, hi[1][1].y);
+  // y: planes y = k0-1 .. k0+2 blended over (x, z) in the central 2x2
+  auto xzb = [&](float v00, float v10, float v01, float v11) {
+    return lerpf(lerpf(v00, v10, fx), lerpf(v01, v11, fx), fz);
+  };
+  const float by0 = xzb(yc[0][0].x, yc[0][0].y, yc[0][1].x, yc[0][1].y);
+  const float by1 = xzb(lo[0][0].y, hi[0][0].x, lo[0][1].y, hi[0][1].x);
+  const float by2 = xzb(lo[1][0].y, hi[1][0].x, lo[1][1].y, hi[1][1].x);
+  const float by3 = xzb(yc[1][0].x, yc[1][0].y, yc[1][1].x, yc[1][1].y);
+  // z: planes z = k0-1 .. k0+2 blended over (x, y)
+  auto xyb = [&](float v00, float v10, float v01, float v11) {
+    return lerpf(lerpf(v00, v10, fx), lerpf(v01, v11, fx), fy);
+  };
+  const float bz0 = xyb(zc[0][0].x, zc[0][0].y, zc[0][1].x, zc[0][1].y);
+  const float bz1 = xyb(lo[0][0].y, hi[0][0].x, lo[1][0].y, hi[1][0].x);
+  const float bz2 = xyb(lo[0][1].y, hi[0][1].x, lo[1][1].y, hi[1][1].x);
+  const float bz3 = xyb(zc[1][0].x, zc[1][0].y, zc[1][1].x, zc[1][1].y);
+  float g[3];
+  g[0] = (lerpf(bx2, bx3, fx) - lerpf(bx0, bx1, fx)) / (float)((x[0] + G.h) - (x[0] - G.h));
+  g[1] = (lerpf(by2, by3, fy) - lerpf(by0, by1, fy)) / (float)((x[1] + G.h) - (x[1] - G.h));
+  g[2] = (lerpf(bz2, bz3, fz) - lerpf(bz0, bz1, fz)) / (float)((x[2] + G.h) - (x[2] - G.h));
+  nm.gn = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  const float inv = 1.0f / fmaxf(nm.gn, 1e-30f);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) nm.n[a] = g[a] * inv;
+  return true;
+}
+
 template <typename ST, typename FT, int NSH>
 __device__ __forceinline__ void shade_inputs(const ST* __restrict__ sdf, const FT* __restrict__ feat,
                                              const FT* __restrict__ probes, const Geo& G,
                                              const double x[3], const float v[3], const float* Y,
                                              float z[NIN], Normal& nm) {
-  sdf_normal(sdf, G, x, nm);
+  const Cell cs = cell_d(x, G.R, G.inv_h);
+  if (!sdf_normal_cross(sdf, G, x, cs, nm)) sdf_normal(sdf, G, x, nm);
   nm.c = (G.flags & FLAG_NV_ONE) ? 1.0f : nm.n[0] * v[0] + nm.n[1] * v[1] + nm.n[2] * v[2];
   z[0] = z[1] = z[2] = 0.0f;
   if (!(G.flags & FLAG_NO_FS)) {
-    const Cell cs = cell_d(x, G.R, G.inv_h);
     float w[8];
     corner_w(cs, w);
 #pragma unroll
