@@ -296,7 +296,7 @@ def kernel_source_hash() -> str:
 
 TRAFFIC_KERNELS = {
     # the kernels each entry point launches on the benchmark's path (taped training step)
-    "render_backward": ("psdf::bwd_ws_clear_kernel", "psdf::tape_count_kernel",
+    "render_backward": ("psdf::bwd_ws_clear_kernel",
                         "psdf::scan_sums_kernel", "psdf::scan_partials_kernel",
                         "psdf::scan_offsets_kernel", "psdf::tape_place_kernel",
                         "psdf::tape_walk_kernel", "void psdf::bwd_shade_kernel<float, float, 9, 0, true>",

@@ -105,23 +105,6 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
 static_assert(sizeof(BwdEntry) == 160 && sizeof(ProbeRec) == 48 && sizeof(ScatRec) == 64,
               "record layouts");
 
-// key of the probe cell with flat corner index `base`
-__device__ __forceinline__ int probe_key(int base, int P) {
-  const int x = base % P, yz = base / P, y = yz % P, z = yz / P;
-  const int nb = P / 2;
-  const int blk = ((z >> 1) * nb + (y >> 1)) * nb + (x >> 1);
-  return blk * 8 + ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
-}
-
-// flat corner index of the probe cell with key `key`
-__device__ __forceinline__ int probe_cell_of_key(int key, int P) {
-  const int nb = P / 2;
-  const int blk = key >> 3;
-  const int bx = blk % nb, byz = blk / nb, by = byz % nb, bz = byz / nb;
-  const int x = 2 * bx + (key & 1), y = 2 * by + ((key >> 1) & 1), z = 2 * bz + ((key >> 2) & 1);
-  return (z * P + y) * P + x;
-}
-
 // waves = 1: reset the slot counter and the overflow flags (before a march or a
 // taped forward); probe_bins: reset the probe-cell counts
 __global__ void __launch_bounds__(256) bwd_ws_clear_kernel(BwdWs ws, int waves) {
@@ -143,21 +126,6 @@ static hipError_t launch_clear(const BwdWs& ws, int waves, hipStream_t s) {
 }
 
 hipError_t launch_bwd_ws_clear(const BwdWs& ws, hipStream_t s) { return launch_clear(ws, 1, s); }
-
-// Lanes with `on` set, grouped by equal `key`: returns the group's lane mask
-// to every member; the lowest member is the group's leader.  One iteration per
-// distinct key of the wave.
-template <typename F>
-__device__ __forceinline__ void for_each_key_group(bool on, int key, F&& f) {
-  uint64_t todo = __ballot(on);
-  while (todo) {
-    const int leader = __builtin_ctzll(todo);
-    const int k = __builtin_amdgcn_readlane(key, leader);
-    const uint64_t grp = __ballot(on && key == k);
-    f(k, leader, grp);
-    todo &= ~grp;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // pass 1: march and emit
@@ -711,46 +679,25 @@ __global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs
 }
 
 // ---------------------------------------------------------------------------
-// taped schedule: probe-cell counts of the recorded entries, and the per-ray
-// walk that runs before the shading pass (the colours come from the forward)
+// taped schedule: placement of the recorded entries (the forward counted them
+// per probe-cell key), and the per-ray walk that runs before the shading pass
+// (the colours come from the forward)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(BLOCK) tape_count_kernel(RenderArgs a, BwdWs ws) {
-  const int lane = threadIdx.x & 63;
-  const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
-  const double inv_hp = 0.5 * (a.P - 1);
-  for (int64_t e0 = ((int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 64; e0 < total;
-       e0 += (int64_t)gridDim.x * WAVES * 64) {
-    const int64_t e = e0 + lane;
-    bool counted = false;
-    int pc = 0;
-    if (e < total) {
-      const BwdEntry& E = ws.entries[e];
-      counted = E.lw >= 0;
-      const double xs[3] = {E.x[0], E.x[1], E.x[2]};
-      if (counted) pc = probe_key(cell_d(xs, a.P, inv_hp).base, a.P);
-    }
-    for_each_key_group(counted, pc, [&](int k, int leader, uint64_t grp) {
-      if (lane == leader) atomicAdd(ws.pcount + k, (int)__popcll(grp));
-    });
-  }
-}
-
 // sorted slot of every recorded sample (cells in key order, the samples of a
 // cell contiguous): islot[entry] = slot, -1 for a slot that holds no sample
 __global__ void __launch_bounds__(BLOCK) tape_place_kernel(RenderArgs a, BwdWs ws) {
   const int lane = threadIdx.x & 63;
   const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
-  const double inv_hp = 0.5 * (a.P - 1);
   for (int64_t e0 = ((int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 64; e0 < total;
        e0 += (int64_t)gridDim.x * WAVES * 64) {
     const int64_t e = e0 + lane;
     bool counted = false;
     int pc = 0;
     if (e < total) {
+      // the key the forward computed and counted
       const BwdEntry& E = ws.entries[e];
       counted = E.lw >= 0;
-      const double xs[3] = {E.x[0], E.x[1], E.x[2]};
-      if (counted) pc = probe_key(cell_d(xs, a.P, inv_hp).base, a.P);
+      pc = E.pkey;
     }
     int first = 0, my_leader = 0;
     uint64_t my_grp = 0;
@@ -962,17 +909,17 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
   // the shading pass's scatters)
   ws.bins = (ws.probe_bins || from_tape) ? 1 : 0;
   const dim3 wgrid((unsigned)((a.B + BLOCK - 1) / BLOCK));
-  hipError_t e = launch_clear(ws, from_tape ? 0 : 1, s);
+  // taped: the forward reset the slot counter and counted its samples per
+  // probe-cell key; only the per-call counters are reset here
+  BwdWs wc = ws;
+  if (from_tape) wc.bins = 0;
+  hipError_t e = launch_clear(wc, from_tape ? 0 : 1, s);
   if (e != hipSuccess) return e;
   if (!from_tape) {
     if (sdf_dt == 0)
       hipLaunchKernelGGL(bwd_march_kernel<float>, wgrid, dim3(BLOCK), 0, s, a, ws);
     else
       hipLaunchKernelGGL(bwd_march_kernel<_Float16>, wgrid, dim3(BLOCK), 0, s, a, ws);
-  } else {
-    const int64_t cw = (ws.cap + 63) / 64;
-    const dim3 cgrid((unsigned)max((int64_t)1, min((cw + WAVES - 1) / WAVES, (int64_t)2048)));
-    hipLaunchKernelGGL(tape_count_kernel, cgrid, dim3(BLOCK), 0, s, a, ws);
   }
   if (ws.bins) {
     hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);

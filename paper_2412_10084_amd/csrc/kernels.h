@@ -56,7 +56,8 @@ struct BwdEntry {
   float gdl;      // dL/d dl_i
   float gdl_prev; // dL/d dl_{i-1} when sample i-1 of the ray is an entry, else 0
   int next_in;    // 1: sample i+1 of the ray is an entry
-  float pad[3];
+  int pkey;       // key of the probe cell of x (the binning order of the backward)
+  float pad[2];
 };
 
 // Gradient record of one shaded sample for the probe grid, placed in probe-cell order.

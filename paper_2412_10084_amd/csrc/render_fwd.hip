@@ -81,6 +81,7 @@ __device__ __forceinline__ void fwd_batch(const RenderArgs& a, const Geo& G, Fwd
     L.wc[slot][2] = w * C2;
   }
   if (tape && !tw.ovf) {
+    const int pkey = ve ? probe_key(cell_d(x, G.P, G.inv_hp).base, G.P) : 0;
     // one chunk of entries per batch, chunks of the wave linked backwards
     unsigned long long got = 0;
     if (lane == 0) got = atomicAdd(ws.counter, (unsigned long long)n);
@@ -118,9 +119,14 @@ __device__ __forceinline__ void fwd_batch(const RenderArgs& a, const Geo& G, Fwd
         e.gdl = 0.f;
         e.gdl_prev = 0.f;
         e.next_in = 0;
-        e.pad[0] = e.pad[1] = e.pad[2] = 0.f;
+        e.pkey = pkey;
+        e.pad[0] = e.pad[1] = 0.f;
         ws.entries[base + lane] = e;
       }
+      // the backward's probe-cell histogram
+      for_each_key_group(ve, pkey, [&](int k, int leader, uint64_t grp) {
+        if (lane == leader) atomicAdd(ws.pcount + k, (int)__popcll(grp));
+      });
       tw.last = (int)base;
       tw.total += n;
     }
@@ -245,7 +251,7 @@ hipError_t launch_render_forward(const RenderArgs& a, const BwdWs* tape, int sdf
   if (tape) {
     ws = *tape;
     ws.probe_bins = 0;
-    ws.bins = 0;
+    ws.bins = 1;  // the forward counts its samples per probe-cell key
     const hipError_t e = launch_bwd_ws_clear(ws, s);
     if (e != hipSuccess) return e;
   }

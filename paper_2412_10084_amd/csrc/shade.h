@@ -245,6 +245,41 @@ __device__ __forceinline__ Cell cell_d(const double x[3], int R, double inv_h) {
   return c;
 }
 
+// Probe cells are binned (backward, taped forward) under a key that keeps space
+// together: blocks of 2x2x2 cells in row-major order, the 8 cells of a block
+// consecutive.  Cells span 0..P-2 per axis, so P/2 blocks per axis.
+// key of the probe cell with flat corner index `base`
+__device__ __forceinline__ int probe_key(int base, int P) {
+  const int x = base % P, yz = base / P, y = yz % P, z = yz / P;
+  const int nb = P / 2;
+  const int blk = ((z >> 1) * nb + (y >> 1)) * nb + (x >> 1);
+  return blk * 8 + ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+}
+
+// flat corner index of the probe cell with key `key`
+__device__ __forceinline__ int probe_cell_of_key(int key, int P) {
+  const int nb = P / 2;
+  const int blk = key >> 3;
+  const int bx = blk % nb, byz = blk / nb, by = byz % nb, bz = byz / nb;
+  const int x = 2 * bx + (key & 1), y = 2 * by + ((key >> 1) & 1), z = 2 * bz + ((key >> 2) & 1);
+  return (z * P + y) * P + x;
+}
+
+// Lanes with `on` set, grouped by equal `key`: returns the group's lane mask
+// to every member; the lowest member is the group's leader.  One iteration per
+// distinct key of the wave.
+template <typename F>
+__device__ __forceinline__ void for_each_key_group(bool on, int key, F&& f) {
+  uint64_t todo = __ballot(on);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int k = __builtin_amdgcn_readlane(key, leader);
+    const uint64_t grp = __ballot(on && key == k);
+    f(k, leader, grp);
+    todo &= ~grp;
+  }
+}
+
 // grid geometry handed to the shading code
 struct Geo {
   int R, P;
