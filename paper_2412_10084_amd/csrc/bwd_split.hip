@@ -623,11 +623,14 @@ __device__ __forceinline__ float rdlane(float v, int l) {
 
 template <int NSH>
 __global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs ws) {
-  const int lane = threadIdx.x & 63;
-  const int gw = (int)(blockIdx.x * WAVES + (threadIdx.x >> 6));
-  const int nw = (int)(gridDim.x * WAVES);
   constexpr int NQ = NSH * NA;  // coefficients per node, one per lane
-  const int j = min(lane >> 2, NSH - 1), k = lane & 3;
+  constexpr int PS = NQ + 1;    // odd row stride: the record lanes' stores hit distinct banks
+  __shared__ float prod[WAVES][64 * PS];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float* P = prod[wv];
+  const int gw = (int)(blockIdx.x * WAVES + wv);
+  const int nw = (int)(gridDim.x * WAVES);
+  const int q = lane < NQ ? lane : 0;
   const int nocc = *ws.pocc;
   for (int oi = gw; oi < nocc; oi += nw) {
     const int key = ws.plist[oi];
@@ -638,36 +641,32 @@ __global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.f;
     for (int r0 = end - cnt; r0 < end; r0 += 64) {
-      // one record per lane, then broadcast record by record
+      // one record per lane: its SH x dL/dF_a products go to LDS (row of the
+      // record), its 8 corner weights stay in registers
       const int m = min(64, end - r0);
-      float f0 = 0.f, f1 = 0.f, f2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
-      float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+      float wl[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) wl[c] = 0.f;
       if (lane < m) {
         const ProbeRec& pr = ws.precs[r0 + lane];
-        f0 = pr.f[0];
-        f1 = pr.f[1];
-        f2 = pr.f[2];
-        v0 = pr.v[0];
-        v1 = pr.v[1];
-        v2 = pr.v[2];
-        d0 = pr.dfa[0];
-        d1 = pr.dfa[1];
-        d2 = pr.dfa[2];
-        d3 = pr.dfa[3];
-      }
-      for (int t = 0; t < m; ++t) {
         float Y[NSH];
-        sh_basis<NSH>(rdlane(v0, t), rdlane(v1, t), rdlane(v2, t), Y);
-        float yj = Y[0];
+        sh_basis<NSH>(pr.v[0], pr.v[1], pr.v[2], Y);
+        const float d[NA] = {pr.dfa[0], pr.dfa[1], pr.dfa[2], pr.dfa[3]};
 #pragma unroll
-        for (int q = 1; q < NSH; ++q) yj = q == j ? Y[q] : yj;
-        const float e0 = rdlane(d0, t), e1 = rdlane(d1, t), e2 = rdlane(d2, t), e3 = rdlane(d3, t);
-        const float g = yj * (k == 0 ? e0 : k == 1 ? e1 : k == 2 ? e2 : e3);
-        float w[8];
-        corner_w(Cell{0, rdlane(f0, t), rdlane(f1, t), rdlane(f2, t)}, w);
+        for (int jj = 0; jj < NSH; ++jj)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = fmaf(w[c], g, acc[c]);
+          for (int kk = 0; kk < NA; ++kk) P[lane * PS + jj * NA + kk] = Y[jj] * d[kk];
+        corner_w(Cell{0, pr.f[0], pr.f[1], pr.f[2]}, wl);
       }
+      wave_sync();
+      // coefficient lanes sum the records: one LDS read and the record's weights
+      // (broadcast from its lane) per record
+      for (int t = 0; t < m; ++t) {
+        const float g = P[t * PS + q];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = fmaf(rdlane(wl[c], t), g, acc[c]);
+      }
+      wave_sync();
     }
     if (lane < NQ) {
 #pragma unroll
