@@ -13,22 +13,22 @@
 namespace psdf {
 
 // dpre (hidden pre-activation) and dz (MLP inputs) of one lane; dz = 0 unless ve
-template <int M>
-__device__ __forceinline__ void mlp_backward_lane(const float* __restrict__ W, const float dout[3],
+template <int M, bool WR = false, typename WT>
+__device__ __forceinline__ void mlp_backward_lane(WT* __restrict__ W, const float dout[3],
                                                   const float pre[HID], bool ve, float dpre[HID],
                                                   float dz[NIN]) {
 #pragma unroll
   for (int k = 0; k < HID; ++k) {
     float acc = 0.f;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc = fmaf(mrnd<M>(W[OFF_W2 + c * HID + k]), dout[c], acc);
+    for (int c = 0; c < 3; ++c) acc = fmaf(wrnd<M, WR>(W[OFF_W2 + c * HID + k]), dout[c], acc);
     dpre[k] = pre[k] > 0.f ? acc : 0.f;
   }
 #pragma unroll
   for (int j = 0; j < NIN; ++j) {
     float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < HID; ++k) acc = fmaf(mrnd<M>(W[k * NIN + j]), dpre[k], acc);
+    for (int k = 0; k < HID; ++k) acc = fmaf(wrnd<M, WR>(W[k * NIN + j]), dpre[k], acc);
     dz[j] = ve ? acc : 0.f;
   }
 }

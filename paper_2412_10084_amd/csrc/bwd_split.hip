@@ -48,7 +48,7 @@ int64_t nsum_of(int P) { return (nkeys_of(P) + kScan - 1) / kScan; }
 constexpr int64_t kMlpPart = (int64_t)NMLP * kMlpWaves * 4;
 int64_t fixed_bytes(int64_t B, int P) {
   return kHead + 3 * al256(n_waves_of(B) * 4) + 3 * al256(nkeys_of(P) * 4) + al256(nsum_of(P) * 4) +
-         kMlpPart;
+         kMlpPart + al256(NMLP * 4);
 }
 constexpr int64_t kPerSample =
     (int64_t)sizeof(BwdEntry) + (int64_t)sizeof(ProbeRec) + (int64_t)sizeof(ScatRec) + 4;
@@ -82,6 +82,8 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   w.plist = reinterpret_cast<int*>(p + kHead + 3 * arr + 2 * parr);
   w.psum = reinterpret_cast<int*>(p + kHead + 3 * arr + 3 * parr);
   w.mlp_part = reinterpret_cast<float*>(p + kHead + 3 * arr + 3 * parr + al256(nsum_of(P) * 4));
+  w.mlp_r = reinterpret_cast<float*>(p + kHead + 3 * arr + 3 * parr + al256(nsum_of(P) * 4) +
+                                      kMlpPart);
   w.nbatch = reinterpret_cast<int*>(p + 24);
   w.pocc = reinterpret_cast<int*>(p + 8);
   w.cap = bwd_ws_capacity(B, P, bytes);
@@ -364,7 +366,7 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
   const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
   const FT* __restrict__ feat = static_cast<const FT*>(a.feat);
   const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
-  const float* __restrict__ W = a.mlp;
+  cfloat* __restrict__ W = const_mlp(a.mlp);  // scalar loads
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
   // the entries in the order they were written (loads coalesce, and an entry's
   // 64 neighbours come from one or two waves of rays); taped: the records go to
@@ -553,6 +555,116 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
   }
   // MLP gradient: one row of partials per wave, summed by mlp_reduce_kernel
   if (a.g_mlp) mlp_grad_store(ws.mlp_part + gw * NMLP, lane, acc_w1, acc_w2, db2);
+}
+
+// Taped shading pass: everything it needs was recorded by the forward, so it
+// depends on the MLP type only.  The weight gradients are summed first, so that
+// the MLP's activations are dead before the records are built (the record fields
+// are read from the entry there), which keeps the pass free of register spills.
+template <int M>
+__global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdWs ws) {
+  __shared__ DwLds dlds[WAVES];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  DwLds& D = dlds[wv];
+  // the MLP read through scalar loads; reduced modes use the copy whose weights
+  // are already rounded (no per-use conversions to keep in registers)
+  cfloat* __restrict__ W = const_mlp(M == MLP_F32 ? a.mlp : ws.mlp_r);
+  const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
+  const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
+  const int64_t nbat = (total + 63) / 64;
+  f4 acc_w1 = {0.f, 0.f, 0.f, 0.f}, acc_w2 = {0.f, 0.f, 0.f, 0.f};
+  float db2[3] = {0.f, 0.f, 0.f};
+  const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;
+  for (int64_t b = gw; b < nbat; b += (int64_t)gridDim.x * WAVES) {
+    // entries in write order (coalesced); records go to the entry's sorted slot
+    const int64_t e = b * 64 + lane;
+    const BwdEntry& E = ws.entries[min(e, total - 1)];
+    int slot = -1;
+    bool ve = false;
+    if (e < total) {
+      const int lw = E.lw;
+      if (lw >= 0) {
+        slot = ws.islot[e];
+        ve = ws.overflow[lw] == 0;
+      }
+    }
+    float z[NIN];
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) z[j] = ve ? E.z[j] : 0.f;
+    float pre[HID], hid[HID], out[3];
+    mlp_lane<M, true>(W, z, pre, hid, out);
+    float dout[3] = {0.f, 0.f, 0.f};
+    if (ve) {
+      // the colour the forward composited
+      const float C0 = E.C[0], C1 = E.C[1], C2 = E.C[2], w = E.w;
+      const float* dLr = a.dL + 3 * (int64_t)E.ray;
+      dout[0] = w * dLr[0] * C0 * (1.f - C0);
+      dout[1] = w * dLr[1] * C1 * (1.f - C1);
+      dout[2] = w * dLr[2] * C2 * (1.f - C2);
+    }
+    float dpre[HID], dz[NIN];
+    mlp_backward_lane<M, true>(W, dout, pre, ve, dpre, dz);
+    if (a.g_mlp) mlp_dw_wave<M>(D, lane, ve, z, hid, dpre, dout, acc_w1, acc_w2, db2);
+    wave_sync();
+    if (slot >= 0) {
+      const double x[3] = {E.x[0], E.x[1], E.x[2]};
+      // SDF and feature cotangents for the box pass: the normal path and the
+      // opacity path at s_i, where this sample's alpha and the previous sample's
+      // meet (the rest of the opacity path is scattered by the per-ray walk)
+      ScatRec r;
+      r.x[0] = x[0];
+      r.x[1] = x[1];
+      r.x[2] = x[2];
+      r.dg[0] = r.dg[1] = r.dg[2] = 0.f;
+      if (ve && !(G.flags & FLAG_NV_ONE)) {
+        const float v[3] = {E.v[0], E.v[1], E.v[2]};
+        Normal nm;
+        nm.n[0] = E.nrm[0];
+        nm.n[1] = E.nrm[1];
+        nm.n[2] = E.nrm[2];
+        nm.gn = E.gn;
+        nm.c = z[7];
+        normal_dg(v, nm, dz, r.dg);
+      }
+      r.a0 = ve ? a.tau * sigmoidf(-a.tau * E.s0) * (E.gdl_prev - E.gdl) : 0.f;
+      const bool fs = ve && !(G.flags & FLAG_NO_FS);
+      r.df[0] = fs ? dz[0] : 0.f;
+      r.df[1] = fs ? dz[1] : 0.f;
+      r.df[2] = fs ? dz[2] : 0.f;
+      r.valid = ve ? 1 : 0;
+      r.pad[0] = r.pad[1] = 0.f;
+      ws.srecs[slot] = r;
+      if (ws.probe_bins) {
+        const Cell cp = cell_d(x, G.P, G.inv_hp);
+        ProbeRec pr;
+        pr.cell = cp.base;
+        pr.f[0] = cp.fx;
+        pr.f[1] = cp.fy;
+        pr.f[2] = cp.fz;
+        pr.v[0] = E.v[0];
+        pr.v[1] = E.v[1];
+        pr.v[2] = E.v[2];
+        pr.dfa[0] = ve ? dz[3] : 0.f;
+        pr.dfa[1] = ve ? dz[4] : 0.f;
+        pr.dfa[2] = ve ? dz[5] : 0.f;
+        pr.dfa[3] = ve ? dz[6] : 0.f;
+        pr.pad = 0.f;
+        ws.precs[slot] = pr;
+      }
+    }
+  }
+  // MLP gradient: one row of partials per wave, summed by mlp_reduce_kernel
+  if (a.g_mlp) mlp_grad_store(ws.mlp_part + gw * NMLP, lane, acc_w1, acc_w2, db2);
+}
+
+// the MLP with its weights (not its biases) rounded for MLP type M
+template <int M>
+__global__ void __launch_bounds__(256) mlp_round_kernel(const float* W, float* Wr) {
+  const int i = threadIdx.x;
+  if (i < NMLP) {
+    const bool weight = i < OFF_B1 || (i >= OFF_W2 && i < OFF_B2);
+    Wr[i] = weight ? mrnd<M>(W[i]) : W[i];
+  }
 }
 
 // g_mlp[k] += sum over the shading waves of their partials (fixed order)
@@ -935,9 +1047,11 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
   const int64_t want = (ws.cap + 64 * WAVES - 1) / (64 * WAVES);
   const dim3 sgrid((unsigned)max((int64_t)1, min(want, (int64_t)1024)));
   if (from_tape) {
-    PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,
-        hipLaunchKernelGGL((bwd_shade_kernel<ST, FT, NSH, M, true>), sgrid, dim3(BLOCK), 0, s, a,
-                           ws))));
+    if (mlp_dt != 0)
+      PSDF_MLP_SWITCH(mlp_dt, hipLaunchKernelGGL((mlp_round_kernel<M>), dim3(1), dim3(256), 0, s,
+                                                 a.mlp, ws.mlp_r));
+    PSDF_MLP_SWITCH(mlp_dt, hipLaunchKernelGGL((tape_shade_kernel<M>), sgrid, dim3(BLOCK), 0, s, a,
+                                               ws));
   } else {
     PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,
         hipLaunchKernelGGL((bwd_shade_kernel<ST, FT, NSH, M, false>), sgrid, dim3(BLOCK), 0, s, a,

@@ -200,14 +200,28 @@ __device__ __forceinline__ float mrnd(float x) {
 // Per-lane colour MLP.  In the reduced modes the operands are rounded exactly as
 // the MFMA path rounds them, products are exact in FP32 and sums are FP32, so the
 // two differ only in summation order.
-template <int M>
-__device__ __forceinline__ void mlp_lane(const float* __restrict__ W, const float z[NIN],
-                                         float pre[HID], float hid[HID], float out[3]) {
+
+// W: the packed MLP, in global memory or (const_mlp) in the constant address
+// space, which the compiler reads with scalar loads
+typedef const float __attribute__((address_space(4))) cfloat;
+__device__ __forceinline__ cfloat* const_mlp(const float* W) {
+  return (cfloat*)(W);
+}
+// WR: the weights (not the biases) are already rounded as mrnd<M> rounds them
+template <int M, bool WR>
+__device__ __forceinline__ float wrnd(float w) {
+  if constexpr (WR) return w;
+  else return mrnd<M>(w);
+}
+
+template <int M, bool WR = false, typename WT>
+__device__ __forceinline__ void mlp_lane(WT* __restrict__ W, const float z[NIN], float pre[HID],
+                                         float hid[HID], float out[3]) {
 #pragma unroll
   for (int k = 0; k < HID; ++k) {
     float acc = 0.0f;
 #pragma unroll
-    for (int j = 0; j < NIN; ++j) acc = fmaf(mrnd<M>(W[k * NIN + j]), mrnd<M>(z[j]), acc);
+    for (int j = 0; j < NIN; ++j) acc = fmaf(wrnd<M, WR>(W[k * NIN + j]), mrnd<M>(z[j]), acc);
     acc += W[OFF_B1 + k];
     pre[k] = acc;
     hid[k] = fmaxf(acc, 0.0f);
@@ -216,7 +230,8 @@ __device__ __forceinline__ void mlp_lane(const float* __restrict__ W, const floa
   for (int c = 0; c < 3; ++c) {
     float acc = 0.0f;
 #pragma unroll
-    for (int k = 0; k < HID; ++k) acc = fmaf(mrnd<M>(W[OFF_W2 + c * HID + k]), mrnd<M>(hid[k]), acc);
+    for (int k = 0; k < HID; ++k)
+      acc = fmaf(wrnd<M, WR>(W[OFF_W2 + c * HID + k]), mrnd<M>(hid[k]), acc);
     out[c] = acc + W[OFF_B2 + c];
   }
 }

@@ -100,6 +100,7 @@ struct BwdWs {
   int* nsorted;        // [1] samples filed in probe-cell order (taped schedule)
   int* islot;          // [cap] sorted slot of each entry, -1: none (taped schedule)
   float* mlp_part;     // [kMlpWaves][227] MLP gradient partials of the shading waves
+  float* mlp_r;        // [227] the MLP with its weights rounded as the shading pass rounds them
   BwdEntry* entries;   // [cap]
   ProbeRec* precs;     // [cap] in probe-cell order
   ScatRec* srecs;      // [cap] in probe-cell order (taped schedule)

@@ -48,7 +48,7 @@ __device__ __forceinline__ void bwd_batch(const RenderArgs& a, const Geo& G, Bwd
   const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
   const FT* __restrict__ feat = static_cast<const FT*>(a.feat);
   const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
-  const float* __restrict__ W = a.mlp;
+  cfloat* __restrict__ W = const_mlp(a.mlp);  // scalar loads
   wave_sync();
   const bool ve = lane < n;
   const int slot = (head + lane) & (RING - 1);

@@ -70,7 +70,7 @@ __device__ __forceinline__ void fwd_batch(const RenderArgs& a, const Geo& G, Fwd
   float out[3];
   if constexpr (M == MLP_F32) {
     float pre[HID], hid[HID];
-    mlp_lane<M>(a.mlp, z, pre, hid, out);
+    mlp_lane<M>(const_mlp(a.mlp), z, pre, hid, out);
   } else {
     mlp_wave<M>(frag, ML, lane, z, out);
   }

@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(BLOCK) sphere_trace_kernel(TraceArgs a) {
     }
     if constexpr (M == MLP_F32) {
       float pre[HID], hid[HID];
-      mlp_lane<M>(a.mlp, z, pre, hid, out);
+      mlp_lane<M>(const_mlp(a.mlp), z, pre, hid, out);
     } else {
       mlp_wave<M>(frag, ML, lane, z, out);
     }
