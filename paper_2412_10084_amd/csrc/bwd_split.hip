@@ -358,7 +358,7 @@ struct ShadeLds {
   int fb[64];
 };
 
-template <typename ST, typename FT, int NSH, int M, bool TAPE>
+template <typename ST, typename FT, int NSH, int M>
 __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs ws) {
   __shared__ ShadeLds<NSH> lds[WAVES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -368,9 +368,7 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
   const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
   cfloat* __restrict__ W = const_mlp(a.mlp);  // scalar loads
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
-  // the entries in the order they were written (loads coalesce, and an entry's
-  // 64 neighbours come from one or two waves of rays); taped: the records go to
-  // the entry's slot in probe-cell order
+  // the entries in the order the march wrote them
   const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
   const int64_t nbat = (total + 63) / 64;
 
@@ -381,10 +379,8 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
     const int64_t e = b * 64 + lane;
     const int n = (int)min((int64_t)64, total - b * 64);
     BwdEntry E;
-    int slot = -1;  // taped: the entry's sorted slot
     bool counted = false, ve = false;  // counted: holds a sample (has a probe bin slot)
     if (lane < n) {
-      if constexpr (TAPE) slot = ws.islot[e];
       E = ws.entries[e];
       counted = E.lw >= 0;
       ve = counted && ws.overflow[E.lw] == 0;
@@ -408,34 +404,17 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
       v[1] = E.v[1];
       v[2] = E.v[2];
       sh_basis<NSH>(v[0], v[1], v[2], Y);
-      if constexpr (TAPE) {
-        // the forward's shading inputs
-#pragma unroll
-        for (int j = 0; j < NIN; ++j) z[j] = E.z[j];
-        nm.n[0] = E.nrm[0];
-        nm.n[1] = E.nrm[1];
-        nm.n[2] = E.nrm[2];
-        nm.gn = E.gn;
-        nm.c = E.z[7];
-      } else {
-        shade_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, Y, z, nm);
-      }
+      shade_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, Y, z, nm);
     }
     float pre[HID], hid[HID], out[3];
     mlp_lane<M>(W, z, pre, hid, out);
-    float C0 = sigmoidf(out[0]), C1 = sigmoidf(out[1]), C2 = sigmoidf(out[2]);
-    if (TAPE && ve) {  // the colour the forward composited
-      C0 = E.C[0];
-      C1 = E.C[1];
-      C2 = E.C[2];
-    }
+    const float C0 = sigmoidf(out[0]), C1 = sigmoidf(out[1]), C2 = sigmoidf(out[2]);
     float dout[3] = {0.f, 0.f, 0.f};
     if (ve) {
-      if (!TAPE) {
-        ws.entries[e].C[0] = C0;
-        ws.entries[e].C[1] = C1;
-        ws.entries[e].C[2] = C2;
-      }
+      // the colour, for the per-ray opacity pass
+      ws.entries[e].C[0] = C0;
+      ws.entries[e].C[1] = C1;
+      ws.entries[e].C[2] = C2;
       const float* dLr = a.dL + 3 * (int64_t)E.ray;
       dout[0] = E.w * dLr[0] * C0 * (1.f - C0);
       dout[1] = E.w * dLr[1] * C1 * (1.f - C1);
@@ -443,71 +422,28 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
     }
     float dpre[HID], dz[NIN];
     mlp_backward_lane<M>(W, dout, pre, ve, dpre, dz);
-    if constexpr (TAPE) {
-      // the SDF and feature cotangents go to the sample's sorted slot; the box
-      // pass scatters them (SDF: the normal path and the opacity path at s_i,
-      // where this sample's alpha and the previous sample's meet; the rest of the
-      // opacity path is scattered by the per-ray walk)
-      if (slot >= 0) {
-        ScatRec r;
-        r.x[0] = x[0];
-        r.x[1] = x[1];
-        r.x[2] = x[2];
-        r.dg[0] = r.dg[1] = r.dg[2] = 0.f;
-        if (ve && !(G.flags & FLAG_NV_ONE)) normal_dg(v, nm, dz, r.dg);
-        r.a0 = ve ? a.tau * sigmoidf(-a.tau * E.s0) * (E.gdl_prev - E.gdl) : 0.f;
-        const bool fs = ve && !(G.flags & FLAG_NO_FS);
-        r.df[0] = fs ? dz[0] : 0.f;
-        r.df[1] = fs ? dz[1] : 0.f;
-        r.df[2] = fs ? dz[2] : 0.f;
-        r.valid = ve ? 1 : 0;
-        r.pad[0] = r.pad[1] = 0.f;
-        ws.srecs[slot] = r;
-      }
-    } else {
-      // SDF through the normal (the opacity path is scattered by the per-ray pass)
-      if (a.g_sdf && !(G.flags & FLAG_NV_ONE)) {
-        float* row = L.u.sc[lane];
+    // SDF through the normal (the opacity path is scattered by the per-ray pass)
+    if (a.g_sdf && !(G.flags & FLAG_NV_ONE)) {
+      float* row = L.u.sc[lane];
 #pragma unroll
-        for (int q = 0; q < 64; ++q) row[q] = 0.f;
-        if (ve) {
-          int k0[3];
-          cell_k(x, G.R, G.inv_h, k0);
-          L.k0[lane][0] = k0[0];
-          L.k0[lane][1] = k0[1];
-          L.k0[lane][2] = k0[2];
-          normal_backward_patch(patch_of_row(row, k0), k0, G, x, v, nm, dz);
-        }
-        wave_sync();
-        sdf_patch_flush(L.u.sc, L.k0, n, lane, G.R, a.g_sdf);
-        wave_sync();
+      for (int q = 0; q < 64; ++q) row[q] = 0.f;
+      if (ve) {
+        int k0[3];
+        cell_k(x, G.R, G.inv_h, k0);
+        L.k0[lane][0] = k0[0];
+        L.k0[lane][1] = k0[1];
+        L.k0[lane][2] = k0[2];
+        normal_backward_patch(patch_of_row(row, k0), k0, G, x, v, nm, dz);
       }
-      if (!(G.flags & FLAG_NO_FS) && a.g_feat) {
-        const Cell cs = cell_d(x, G.R, G.inv_h);
-        feat_scatter_wave(L.u.sc, L.fb, ve, cs, dz, n, lane, G.R, a.g_feat);
-      }
+      wave_sync();
+      sdf_patch_flush(L.u.sc, L.k0, n, lane, G.R, a.g_sdf);
+      wave_sync();
     }
-    if (TAPE && ws.probe_bins) {
-      // the sample's probe record goes to its own sorted slot
-      if (slot >= 0) {
-        const double xs[3] = {E.x[0], E.x[1], E.x[2]};
-        const Cell cp = cell_d(xs, G.P, G.inv_hp);
-        ProbeRec pr;
-        pr.cell = cp.base;
-        pr.f[0] = cp.fx;
-        pr.f[1] = cp.fy;
-        pr.f[2] = cp.fz;
-        pr.v[0] = E.v[0];
-        pr.v[1] = E.v[1];
-        pr.v[2] = E.v[2];
-        pr.dfa[0] = ve ? dz[3] : 0.f;
-        pr.dfa[1] = ve ? dz[4] : 0.f;
-        pr.dfa[2] = ve ? dz[5] : 0.f;
-        pr.dfa[3] = ve ? dz[6] : 0.f;
-        pr.pad = 0.f;
-        ws.precs[slot] = pr;
-      }
-    } else if (ws.probe_bins) {
+    if (!(G.flags & FLAG_NO_FS) && a.g_feat) {
+      const Cell cs = cell_d(x, G.R, G.inv_h);
+      feat_scatter_wave(L.u.sc, L.fb, ve, cs, dz, n, lane, G.R, a.g_feat);
+    }
+    if (ws.probe_bins) {
       // file dL/dF_a under the probe cell (the cell of the stored position, as
       // counted by the march pass)
       double xs[3] = {0.0, 0.0, 0.0};
@@ -1054,7 +990,7 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
                                                ws));
   } else {
     PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,
-        hipLaunchKernelGGL((bwd_shade_kernel<ST, FT, NSH, M, false>), sgrid, dim3(BLOCK), 0, s, a,
+        hipLaunchKernelGGL((bwd_shade_kernel<ST, FT, NSH, M>), sgrid, dim3(BLOCK), 0, s, a,
                            ws))));
   }
   if (a.g_mlp)
