@@ -17,6 +17,7 @@ namespace psdf {
 
 constexpr int SBLOCK = 256;
 
+// (blocks of up to SBLOCK threads, a multiple of 64)
 __device__ __forceinline__ void block_add(float val, float* dst) {
   __shared__ float part[SBLOCK / 64];
   val = wave_sum(val);
@@ -24,7 +25,7 @@ __device__ __forceinline__ void block_add(float val, float* dst) {
   __syncthreads();
   if (threadIdx.x == 0) {
     float s = 0.f;
-    for (int w = 0; w < SBLOCK / 64; ++w) s += part[w];
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
     if (s != 0.f) atomic_add_f32(dst, s);
   }
 }
@@ -164,7 +165,7 @@ __global__ void __launch_bounds__(SBLOCK) step_tv3v_kernel(TvArgs t, StepArgs a)
   const int R = t.R, rowlen = R * C;
   unsigned bx, by, bz;
   xcd_block3(bx, by, bz);
-  const int xi = (bx * SBLOCK + threadIdx.x) * 4, j = by, k = bz;
+  const int xi = (bx * blockDim.x + threadIdx.x) * 4, j = by, k = bz;
   const bool valid = xi < rowlen;
   const float npairs = 3.0f * (float)R * (float)R * (float)(R - 1);
   const float scale = t.lambda / (npairs * (float)C);
@@ -288,8 +289,11 @@ static void launch_tv(const TvArgs& t, int C, const StepArgs& a, hipStream_t s) 
     return;
   }
   if (C == 3 && R % 4 == 0) {
-    const dim3 grid4((rowlen / 4 + SBLOCK - 1) / SBLOCK, R, R);
-    hipLaunchKernelGGL(step_tv3v_kernel, grid4, dim3(SBLOCK), 0, s, t, a);
+    // a row of 3R/4 float4s per block when it fits (no idle lanes at R = 256)
+    const unsigned n4 = rowlen / 4;
+    const unsigned threads = min((unsigned)SBLOCK, (n4 + 63) / 64 * 64);
+    const dim3 grid4((n4 + threads - 1) / threads, R, R);
+    hipLaunchKernelGGL(step_tv3v_kernel, grid4, dim3(threads), 0, s, t, a);
     return;
   }
   const dim3 grid((rowlen + SBLOCK - 1) / SBLOCK, R, R);
