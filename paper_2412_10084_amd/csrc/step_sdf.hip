@@ -7,7 +7,7 @@
 //   dL/ds_m = lambda / M * sum_a (q_{m-e_a,a} - q_{m+e_a,a}) / 2h,  M = (R-2)^3.
 // A workgroup owns a 64 x 8 column tile and marches it along z through a chunk
 // of 16 planes.  Three s planes (tile + 2 halo) and three q planes (tile + 1
-// halo: 3 components and the node's loss term) rotate through LDS, so every s
+// halo, 3 components) rotate through LDS, so every s
 // value is read from memory about 1.6 times (halos) instead of 25 times and
 // every q is evaluated once per tile.  The next two s planes and the next two
 // planes' gradients and moments are in flight while a plane is processed.
@@ -35,7 +35,7 @@ constexpr int QXW = ETX + 2, QYW = ETY + 2, QN = QXW * QYW;  // q plane region (
 
 struct EikLds {
   float s[3][SN];     // s planes, slot z % 3
-  float q[3][4][QN];  // q_x, q_y, q_z, (|g| - 1)^2 per plane, slot z % 3
+  float q[3][3][QN];  // q_x, q_y, q_z per plane, slot z % 3
   int bmin[BTN], bmax[BTN];
   float part[ETHREADS / 64];
 };
@@ -94,7 +94,11 @@ __device__ __forceinline__ void s_plane_store(EikLds& L, int z, const float v[SP
 }
 
 // q of plane z over the tile + 1 halo, from s planes z-1, z, z+1
-__device__ __forceinline__ void q_plane(EikLds& L, int R, int x0, int y0, int z, float inv2h) {
+// q of plane z over the tile and its halo; returns this thread's share of the
+// eikonal loss of the tile's own nodes when `own_plane`
+__device__ __forceinline__ float q_plane(EikLds& L, int R, int x0, int y0, int z, float inv2h,
+                                         bool own_plane) {
+  float loss = 0.f;
   const float* __restrict__ sm = L.s[zslot(z - 1)];
   const float* __restrict__ s0 = L.s[zslot(z)];
   const float* __restrict__ sp = L.s[zslot(z + 1)];
@@ -113,8 +117,10 @@ __device__ __forceinline__ void q_plane(EikLds& L, int R, int x0, int y0, int z,
     q[0 * QN + idx] = f * gxv;
     q[1 * QN + idx] = f * gyv;
     q[2 * QN + idx] = f * gzv;
-    q[3 * QN + idx] = inner ? e * e : 0.f;
+    // own nodes: the tile's columns inside the grid (the loss counts interior ones)
+    if (own_plane && inner && lx >= 1 && lx <= ETX && ly >= 1 && ly <= ETY) loss += e * e;
   }
+  return loss;
 }
 
 __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, int* bounds_enc) {
@@ -146,11 +152,11 @@ __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, in
   }
   s_plane_fetch(s, R, x0, y0, zs + 1, v);
   __syncthreads();
-  q_plane(L, R, x0, y0, zs - 1, inv2h);
+  float loss = q_plane(L, R, x0, y0, zs - 1, inv2h, false);
   __syncthreads();
   s_plane_store(L, zs + 1, v);
   __syncthreads();
-  q_plane(L, R, x0, y0, zs, inv2h);
+  loss += q_plane(L, R, x0, y0, zs, inv2h, true);
   s_plane_fetch(s, R, x0, y0, zs + 2, v);
   s_plane_fetch(s, R, x0, y0, zs + 3, v2);
 
@@ -194,7 +200,6 @@ __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, in
   gmv_fetch(zs, gn_, mn_, vn_);
   gmv_fetch(zs + 1, gn2, mn2, vn2);
 
-  float loss = 0.f;
   for (int z = zs; z < ze; ++z) {
     float gc[2] = {gn_[0], gn_[1]}, mc[2] = {mn_[0], mn_[1]}, vc[2] = {vn_[0], vn_[1]};
 #pragma unroll
@@ -210,7 +215,7 @@ __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, in
     for (int u = 0; u < SPER; ++u) v[u] = v2[u];
     if (z + 4 < ze + 2) s_plane_fetch(s, R, x0, y0, z + 4, v2);
     __syncthreads();
-    q_plane(L, R, x0, y0, z + 1, inv2h);
+    loss += q_plane(L, R, x0, y0, z + 1, inv2h, z + 1 < ze);
     __syncthreads();
     const float* qm = &L.q[zslot(z - 1)][0][0];
     const float* q0 = &L.q[zslot(z)][0][0];
@@ -229,7 +234,6 @@ __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, in
       const float ge = (q0[0 * QN + qc - 1] - q0[0 * QN + qc + 1]) +
                        (q0[1 * QN + qc - QXW] - q0[1 * QN + qc + QXW]) +
                        (qm[2 * QN + qc] - qp[2 * QN + qc]);
-      if (own) loss += q0[3 * QN + qc];
       const float G = gc[c] + coef * ge;
       float m = mc[c], vv = vc[c];
       const float p0 = L.s[zslot(z)][sc];
