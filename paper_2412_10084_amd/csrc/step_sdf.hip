@@ -7,7 +7,8 @@
 //   dL/ds_m = lambda / M * sum_a (q_{m-e_a,a} - q_{m+e_a,a}) / 2h,  M = (R-2)^3.
 // A workgroup owns a 64 x 8 column tile and marches it along z through a chunk
 // of 16 planes.  Three s planes (tile + 2 halo) and three q planes (tile + 1
-// halo, 3 components) rotate through LDS, so every s
+// halo: q_x, q_y of the current and next plane, q_z of three) rotate through
+// LDS, so every s
 // value is read from memory about 1.6 times (halos) instead of 25 times and
 // every q is evaluated once per tile.  The next two s planes and the next two
 // planes' gradients and moments are in flight while a plane is processed.
@@ -35,7 +36,8 @@ constexpr int QXW = ETX + 2, QYW = ETY + 2, QN = QXW * QYW;  // q plane region (
 
 struct EikLds {
   float s[3][SN];     // s planes, slot z % 3
-  float q[3][3][QN];  // q_x, q_y, q_z per plane, slot z % 3
+  float qxy[2][2][QN];  // q_x, q_y of plane z in slot z % 2 (only plane z needs them)
+  float qz[3][QN];      // q_z of plane z in slot z % 3 (planes z-1, z+1 need it)
   int bmin[BTN], bmax[BTN];
   float part[ETHREADS / 64];
 };
@@ -102,7 +104,8 @@ __device__ __forceinline__ float q_plane(EikLds& L, int R, int x0, int y0, int z
   const float* __restrict__ sm = L.s[zslot(z - 1)];
   const float* __restrict__ s0 = L.s[zslot(z)];
   const float* __restrict__ sp = L.s[zslot(z + 1)];
-  float* q = &L.q[zslot(z)][0][0];
+  float* qxy = &L.qxy[z & 1][0][0];
+  float* qz = L.qz[zslot(z)];
   for (int idx = threadIdx.x; idx < QN; idx += ETHREADS) {
     const int ly = idx / QXW, lx = idx - ly * QXW;
     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
@@ -114,9 +117,9 @@ __device__ __forceinline__ float q_plane(EikLds& L, int R, int x0, int y0, int z
     const float e = gn - 1.0f;
     const bool inner = gx >= 1 && gy >= 1 && z >= 1 && gx <= R - 2 && gy <= R - 2 && z <= R - 2;
     const float f = inner && gn > 0.f ? 2.0f * e / gn : 0.f;
-    q[0 * QN + idx] = f * gxv;
-    q[1 * QN + idx] = f * gyv;
-    q[2 * QN + idx] = f * gzv;
+    qxy[0 * QN + idx] = f * gxv;
+    qxy[1 * QN + idx] = f * gyv;
+    qz[idx] = f * gzv;
     // own nodes: the tile's columns inside the grid (the loss counts interior ones)
     if (own_plane && inner && lx >= 1 && lx <= ETX && ly >= 1 && ly <= ETY) loss += e * e;
   }
@@ -217,9 +220,9 @@ __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, in
     __syncthreads();
     loss += q_plane(L, R, x0, y0, z + 1, inv2h, z + 1 < ze);
     __syncthreads();
-    const float* qm = &L.q[zslot(z - 1)][0][0];
-    const float* q0 = &L.q[zslot(z)][0][0];
-    const float* qp = &L.q[zslot(z + 1)][0][0];
+    const float* qm = L.qz[zslot(z - 1)];
+    const float* q0 = &L.qxy[z & 1][0][0];
+    const float* qp = L.qz[zslot(z + 1)];
     const __amdgpu_buffer_rsrc_t wo = plane_rsrc(a.sdf_out, z, R, R, 4);
     const __amdgpu_buffer_rsrc_t wm = plane_rsrc(a.m_sdf, z, R, R, 4);
     const __amdgpu_buffer_rsrc_t wv = plane_rsrc(a.v_sdf, z, R, R, 4);
@@ -233,7 +236,7 @@ __global__ void __launch_bounds__(ETHREADS) step_sdf_tiled_kernel(StepArgs a, in
       const int qc = (ty + 4 * c + 1) * QXW + (tx + 1);
       const float ge = (q0[0 * QN + qc - 1] - q0[0 * QN + qc + 1]) +
                        (q0[1 * QN + qc - QXW] - q0[1 * QN + qc + QXW]) +
-                       (qm[2 * QN + qc] - qp[2 * QN + qc]);
+                       (qm[qc] - qp[qc]);
       const float G = gc[c] + coef * ge;
       float m = mc[c], vv = vc[c];
       const float p0 = L.s[zslot(z)][sc];
