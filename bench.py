@@ -298,7 +298,7 @@ TRAFFIC_KERNELS = {
     # the kernels each entry point launches on the benchmark's path (taped training step)
     "render_backward": ("psdf::bwd_ws_clear_kernel",
                         "psdf::scan_sums_kernel", "psdf::scan_partials_kernel",
-                        "psdf::scan_offsets_kernel", "psdf::tape_place_kernel",
+                        "psdf::scan_offsets_kernel",
                         "psdf::tape_walk_kernel", "void psdf::tape_shade_kernel<0>", "void psdf::mlp_round_kernel",
                         "psdf::mlp_reduce_kernel", "psdf::bwd_box_kernel",
                         "void psdf::probe_reduce_kernel<9>",

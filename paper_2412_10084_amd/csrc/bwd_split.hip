@@ -51,7 +51,7 @@ int64_t fixed_bytes(int64_t B, int P) {
          kMlpPart + al256(NMLP * 4);
 }
 constexpr int64_t kPerSample =
-    (int64_t)sizeof(BwdEntry) + (int64_t)sizeof(ProbeRec) + (int64_t)sizeof(ScatRec) + 4;
+    (int64_t)sizeof(BwdEntry) + (int64_t)sizeof(ProbeRec) + (int64_t)sizeof(ScatRec);
 // box-pass batches: each occupied block of cells ends at most one partial batch
 int64_t ndesc_of(int P, int64_t cap) { return nblk_of(P) + 1 + cap / 64; }
 }  // namespace
@@ -91,8 +91,6 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   w.precs = reinterpret_cast<ProbeRec*>(p + fixed_bytes(B, P) + w.cap * (int64_t)sizeof(BwdEntry));
   w.srecs = reinterpret_cast<ScatRec*>(p + fixed_bytes(B, P) +
                                        w.cap * (int64_t)(sizeof(BwdEntry) + sizeof(ProbeRec)));
-  w.islot = reinterpret_cast<int*>(
-      p + fixed_bytes(B, P) + w.cap * (int64_t)(sizeof(BwdEntry) + sizeof(ProbeRec) + sizeof(ScatRec)));
   w.nsorted = reinterpret_cast<int*>(p + 16);
   w.ndesc = ndesc_of(P, w.cap);
   w.bdesc = reinterpret_cast<int2*>(p + fixed_bytes(B, P) + w.cap * kPerSample);
@@ -512,18 +510,37 @@ __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdW
   float db2[3] = {0.f, 0.f, 0.f};
   const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;
   for (int64_t b = gw; b < nbat; b += (int64_t)gridDim.x * WAVES) {
-    // entries in write order (coalesced); records go to the entry's sorted slot
+    // entries in write order (coalesced); records go to the entry's slot in
+    // probe-cell-key order
     const int64_t e = b * 64 + lane;
     const BwdEntry& E = ws.entries[min(e, total - 1)];
-    int slot = -1;
-    bool ve = false;
+    bool counted = false, ve = false;
+    int pk = 0;
     if (e < total) {
       const int lw = E.lw;
       if (lw >= 0) {
-        slot = ws.islot[e];
+        counted = true;
+        pk = E.pkey;
         ve = ws.overflow[lw] == 0;
       }
     }
+    // slots: one atomic per distinct key of the batch (the forward counted the
+    // samples per key), issued now and read only when the records are written
+    bool lead = false;
+    int gcount = 0, my_leader = 0;
+    uint64_t my_grp = 0;
+    for_each_key_group(counted, pk, [&](int k, int leader, uint64_t grp) {
+      if (lane == leader) {
+        lead = true;
+        gcount = (int)__popcll(grp);
+      }
+      if ((grp >> lane) & 1ull) {
+        my_leader = leader;
+        my_grp = grp;
+      }
+    });
+    int gbase = 0;
+    if (lead) gbase = atomicAdd(ws.pcursor + pk, gcount);
     float z[NIN];
 #pragma unroll
     for (int j = 0; j < NIN; ++j) z[j] = ve ? E.z[j] : 0.f;
@@ -542,7 +559,9 @@ __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdW
     mlp_backward_lane<M, true>(W, dout, pre, ve, dpre, dz);
     if (a.g_mlp) mlp_dw_wave<M>(D, lane, ve, z, hid, dpre, dout, acc_w1, acc_w2, db2);
     wave_sync();
-    if (slot >= 0) {
+    const int gb = __shfl(gbase, my_leader, 64);
+    if (counted) {
+      const int slot = gb + lane_rank(my_grp);
       const double x[3] = {E.x[0], E.x[1], E.x[2]};
       // SDF and feature cotangents for the box pass: the normal path and the
       // opacity path at s_i, where this sample's alpha and the previous sample's
@@ -726,40 +745,9 @@ __global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs
 }
 
 // ---------------------------------------------------------------------------
-// taped schedule: placement of the recorded entries (the forward counted them
-// per probe-cell key), and the per-ray walk that runs before the shading pass
-// (the colours come from the forward)
+// taped schedule: the per-ray walk that runs before the shading pass (the
+// colours come from the forward)
 // ---------------------------------------------------------------------------
-// sorted slot of every recorded sample (cells in key order, the samples of a
-// cell contiguous): islot[entry] = slot, -1 for a slot that holds no sample
-__global__ void __launch_bounds__(BLOCK) tape_place_kernel(RenderArgs a, BwdWs ws) {
-  const int lane = threadIdx.x & 63;
-  const int64_t total = min((int64_t)min(*ws.counter, (unsigned long long)ws.cap), ws.cap);
-  for (int64_t e0 = ((int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 64; e0 < total;
-       e0 += (int64_t)gridDim.x * WAVES * 64) {
-    const int64_t e = e0 + lane;
-    bool counted = false;
-    int pc = 0;
-    if (e < total) {
-      // the key the forward computed and counted
-      const BwdEntry& E = ws.entries[e];
-      counted = E.lw >= 0;
-      pc = E.pkey;
-    }
-    int first = 0, my_leader = 0;
-    uint64_t my_grp = 0;
-    for_each_key_group(counted, pc, [&](int k, int leader, uint64_t grp) {
-      if (lane == leader) first = atomicAdd(ws.pcursor + k, (int)__popcll(grp));
-      if ((grp >> lane) & 1ull) {
-        my_leader = leader;
-        my_grp = grp;
-      }
-    });
-    first = __shfl(first, my_leader, 64);
-    if (e < total) ws.islot[e] = counted ? first + lane_rank(my_grp) : -1;
-  }
-}
-
 struct WalkLds {
   RayD ray[64];
   int si[64];
@@ -972,11 +960,6 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
     hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(scan_offsets_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);
-  }
-  if (from_tape) {
-    const int64_t cw = (ws.cap + 63) / 64;
-    const dim3 cgrid((unsigned)max((int64_t)1, min((cw + WAVES - 1) / WAVES, (int64_t)2048)));
-    hipLaunchKernelGGL(tape_place_kernel, cgrid, dim3(BLOCK), 0, s, a, ws);
   }
   if (from_tape && a.g_sdf) hipLaunchKernelGGL(tape_walk_kernel, wgrid, dim3(BLOCK), 0, s, a, ws);
   // enough waves to fill the chip; each loops over batches of 64 entries

@@ -98,7 +98,6 @@ struct BwdWs {
   int2* bdesc;         // [ndesc] (first sorted slot, samples): up to 64 samples of one
                        // block of 2x2x2 probe cells
   int* nsorted;        // [1] samples filed in probe-cell order (taped schedule)
-  int* islot;          // [cap] sorted slot of each entry, -1: none (taped schedule)
   float* mlp_part;     // [kMlpWaves][227] MLP gradient partials of the shading waves
   float* mlp_r;        // [227] the MLP with its weights rounded as the shading pass rounds them
   BwdEntry* entries;   // [cap]
