@@ -608,8 +608,19 @@ __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdW
       }
     }
   }
-  // MLP gradient: one row of partials per wave, summed by mlp_reduce_kernel
-  if (a.g_mlp) mlp_grad_store(ws.mlp_part + gw * NMLP, lane, acc_w1, acc_w2, db2);
+  // MLP gradient: the block's four waves add their partials in LDS and the block
+  // writes one row, summed by mlp_reduce_kernel
+  static_assert(WAVES == 4, "four waves per block");
+  if (a.g_mlp) {
+    wave_sync();
+    mlp_grad_store(&D.st[0][0], lane, acc_w1, acc_w2, db2);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NMLP) {
+      const float s = (dlds[0].st[0][t] + dlds[1].st[0][t]) + (dlds[2].st[0][t] + dlds[3].st[0][t]);
+      ws.mlp_part[(int64_t)blockIdx.x * NMLP + t] = s;
+    }
+  }
 }
 
 // the MLP with its weights (not its biases) rounded for MLP type M
@@ -622,12 +633,12 @@ __global__ void __launch_bounds__(256) mlp_round_kernel(const float* W, float* W
   }
 }
 
-// g_mlp[k] += sum over the shading waves of their partials (fixed order)
-__global__ void __launch_bounds__(256) mlp_reduce_kernel(BwdWs ws, int nwaves, float* g_mlp) {
+// g_mlp[k] += sum of the rows of partials (one per shading wave or block; fixed order)
+__global__ void __launch_bounds__(256) mlp_reduce_kernel(BwdWs ws, int nrows, float* g_mlp) {
   __shared__ float part[4];
   const int k = blockIdx.x;
   float acc = 0.f;
-  for (int w = threadIdx.x; w < nwaves; w += 256) acc += ws.mlp_part[(int64_t)w * NMLP + k];
+  for (int w = threadIdx.x; w < nrows; w += 256) acc += ws.mlp_part[(int64_t)w * NMLP + k];
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -977,8 +988,8 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
                            ws))));
   }
   if (a.g_mlp)
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(NMLP), dim3(256), 0, s, ws, (int)(sgrid.x * WAVES),
-                       a.g_mlp);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(NMLP), dim3(256), 0, s, ws,
+                       (int)(from_tape ? sgrid.x : sgrid.x * WAVES), a.g_mlp);
   if (from_tape && (a.g_sdf || a.g_feat)) {
     const dim3 bgrid((unsigned)max((int64_t)1, min(want, (int64_t)2048)));
     hipLaunchKernelGGL(bwd_box_kernel, bgrid, dim3(BLOCK), 0, s, a, ws);
