@@ -189,7 +189,7 @@ int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, 
                          int64_t workspace_bytes, int32_t flags, void* stream);
 
 /* Bytes of a backward workspace (or forward tape) for B rays and a P^3 probe
- * grid with room for `max_samples` shaded samples (272 bytes each, plus 12
+ * grid with room for `max_samples` shaded samples (288 bytes each, plus 12
  * bytes per 64 rays, about 12 bytes per probe cell and 3.6 MiB for the MLP
  * gradient partials of the shading waves); -1 if an argument is out of range. */
 int64_t psdf_backward_workspace_bytes(int64_t B, int32_t P, int64_t max_samples);

@@ -253,21 +253,40 @@ __device__ __forceinline__ void sdf_cross_add(float* q, int sy, int sz, const fl
 }
 
 // SDF box pass over the lanes with `part` set: the opacity gradient at s_i
-// (coefficient a0, trilinear at x) and the central-difference path (cotangent
-// dg of the FD gradient at x).  Returns false, having done nothing, when their
-// nodes do not fit in `cap` floats (wave-uniform).
+// (coefficient a0, trilinear at x), the central-difference path (cotangent dg of
+// the FD gradient at x) and, where sample i+1 is not shaded itself, the opacity
+// gradient at s_{i+1} (coefficient a1, trilinear at x + off; with `direct1` it
+// is added to the grid directly instead, which a single lane's box always
+// allows).  Returns false, having done nothing, when the nodes do not fit in
+// `cap` floats (wave-uniform).
 __device__ __forceinline__ bool sdf_box_pass(float* box, int cap, int lane, bool part,
                                              const double x[3], const float dg[3], float a0,
+                                             const float off[3], float a1, bool direct1,
                                              const Geo& G, float* g_sdf) {
-  int k0[3] = {0, 0, 0};
+  int k0[3] = {0, 0, 0}, k1[3] = {0, 0, 0};
+  float f1[3] = {0.f, 0.f, 0.f};
+  const bool any1 = part && a1 != 0.f;
   if (part) cell_k(x, G.R, G.inv_h, k0);
+  if (any1) {
+    const double kmax = (double)(G.R - 2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) axis_cell_d(x[a] + (double)off[a], G.inv_h, kmax, k1[a], f1[a]);
+  }
+  const bool has1 = any1 && !direct1;
   int lo[3], ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = wave_min_i(part ? k0[a] - 1 : 0x7FFFFFFF);  // nodes k0-1 .. k0+2
-    ext[a] = wave_max_i(part ? k0[a] + 2 : -0x7FFFFFFF) - lo[a] + 1;
+    // nodes k0-1 .. k0+2, and k1 .. k1+1 for the successor sample
+    const int l = !part ? 0x7FFFFFFF : has1 ? min(k0[a] - 1, k1[a]) : k0[a] - 1;
+    const int h = !part ? -0x7FFFFFFF : has1 ? max(k0[a] + 2, k1[a] + 1) : k0[a] + 2;
+    lo[a] = wave_min_i(l);
+    ext[a] = wave_max_i(h) - lo[a] + 1;
   }
   if ((int64_t)ext[0] * ext[1] * ext[2] > cap) return false;
+  if (any1 && direct1) {
+    const Cell c1{(k1[2] * G.R + k1[1]) * G.R + k1[0], f1[0], f1[1], f1[2]};
+    scatter8(g_sdf, G.R, c1, a1);
+  }
   const int vol = ext[0] * ext[1] * ext[2];
   const int sy = ext[0], sz = ext[0] * ext[1];
   float f[3] = {0.f, 0.f, 0.f}, c[3] = {0.f, 0.f, 0.f}, bnd = 0.f;
@@ -280,8 +299,8 @@ __device__ __forceinline__ bool sdf_box_pass(float* box, int cap, int lane, bool
       inner = inner && k0[a] >= 1 && k0[a] <= G.R - 3 && x[a] + G.h <= 1.0 && x[a] - G.h >= -1.0;
       c[a] = dg[a] / (float)((x[a] + G.h) - (x[a] - G.h));
     }
-    // every node of the patch gets at most |a0| + sum |c_a| (weights <= 1)
-    bnd = fabsf(a0) + fabsf(c[0]) + fabsf(c[1]) + fabsf(c[2]);
+    // every node gets at most |a0| + sum |c_a| + |a1| from a lane (weights <= 1)
+    bnd = fabsf(a0) + fabsf(c[0]) + fabsf(c[1]) + fabsf(c[2]) + (has1 ? fabsf(a1) : 0.f);
   }
   const float B = wave_max_nonneg(bnd);
   const bool fixed = !wave_any(part && !inner) && B < kFixedMaxBound;
@@ -289,8 +308,17 @@ __device__ __forceinline__ bool sdf_box_pass(float* box, int cap, int lane, bool
   box_clear(box, vol, lane);
   wave_sync();
   float* q = box + (k0[2] - 1 - lo[2]) * sz + (k0[1] - 1 - lo[1]) * sy + (k0[0] - 1 - lo[0]);
+  // the successor's 8 corners
+  float* q1 = box + (k1[2] - lo[2]) * sz + (k1[1] - lo[1]) * sy + (k1[0] - lo[0]);
+  float w1[8];
+  corner_w(Cell{0, f1[0], f1[1], f1[2]}, w1);
   if (fixed) {
     if (part) sdf_cross_add<true>(q, sy, sz, f, c, a0, sc);
+    if (has1) {
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+        box_add<true>(q1 + (cc & 1) + ((cc >> 1) & 1) * sy + ((cc >> 2) & 1) * sz, a1 * w1[cc], sc);
+    }
     wave_sync();
     box_flush<1, true>(box, 1.f / sc, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_sdf, lane);
   } else {
@@ -302,6 +330,11 @@ __device__ __forceinline__ bool sdf_box_pass(float* box, int cap, int lane, bool
         if (a0 != 0.f) patch_add<true>(D, k0, x, G.R, G.inv_h, a0);
         if (dg[0] != 0.f || dg[1] != 0.f || dg[2] != 0.f) fd_patch<true>(D, k0, G, x, dg);
       }
+    }
+    if (has1) {
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+        box_add<false>(q1 + (cc & 1) + ((cc >> 1) & 1) * sy + ((cc >> 2) & 1) * sz, a1 * w1[cc], 1.f);
     }
     wave_sync();
     box_flush<1, false>(box, 1.f, ext[0], ext[1], ext[2], lo[0], lo[1], lo[2], G.R, g_sdf, lane);
@@ -367,18 +400,19 @@ __device__ __forceinline__ bool feat_box_pass(float* box, int cap, int lane, boo
 }
 
 // Runs a box pass over the lanes with `ve` set: all of them at once when their
-// nodes fit, else in groups of 16 lanes, then 4, then one (a single lane's nodes
-// always fit a box of at least 64 floats).
+// nodes fit, else in groups of 16 lanes, then 4, then one.  pass(part, single):
+// `single` marks the one-lane level, where the pass must fit (its own nodes
+// always fit a box of at least 64 floats; farther terms go to the grid).
 template <typename Pass>
 __device__ __forceinline__ void box_in_groups(bool ve, int lane, Pass pass) {
   if (!wave_any(ve)) return;
-  if (pass(ve)) return;
+  if (pass(ve, false)) return;
   bool pending = ve;
   for (int gs = 16; gs >= 1; gs >>= 2) {
     for (int g0 = 0; g0 < 64; g0 += gs) {
       const bool part = pending && (unsigned)(lane - g0) < (unsigned)gs;
       if (!wave_any(part)) continue;
-      if (pass(part)) pending = pending && !part;
+      if (pass(part, gs == 1)) pending = pending && !part;
     }
     if (!wave_any(pending)) return;
   }

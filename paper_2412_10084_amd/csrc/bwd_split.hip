@@ -102,7 +102,7 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   return w;
 }
 
-static_assert(sizeof(BwdEntry) == 160 && sizeof(ProbeRec) == 48 && sizeof(ScatRec) == 64,
+static_assert(sizeof(BwdEntry) == 160 && sizeof(ProbeRec) == 48 && sizeof(ScatRec) == 80,
               "record layouts");
 
 // waves = 1: reset the slot counter and the overflow flags (before a march or a
@@ -587,6 +587,11 @@ __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdW
       r.df[1] = fs ? dz[1] : 0.f;
       r.df[2] = fs ? dz[2] : 0.f;
       r.valid = ve ? 1 : 0;
+      r.off[0] = E.nx_off[0];
+      r.off[1] = E.nx_off[1];
+      r.off[2] = E.nx_off[2];
+      const bool nx = r.off[0] != 0.f || r.off[1] != 0.f || r.off[2] != 0.f;
+      r.a1 = ve && nx ? a.tau * sigmoidf(-a.tau * E.s1) * E.gdl : 0.f;
       r.pad[0] = r.pad[1] = 0.f;
       ws.srecs[slot] = r;
       if (ws.probe_bins) {
@@ -680,13 +685,16 @@ __global__ void __launch_bounds__(BLOCK) bwd_box_kernel(RenderArgs a, BwdWs ws) 
       r.dg[0] = r.dg[1] = r.dg[2] = 0.f;
       r.a0 = 0.f;
       r.df[0] = r.df[1] = r.df[2] = 0.f;
+      r.off[0] = r.off[1] = r.off[2] = 0.f;
+      r.a1 = 0.f;
     }
     if (a.g_sdf)
-      box_in_groups(ve, lane, [&](bool part) {
-        return sdf_box_pass(box, kBoxCap, lane, part, r.x, r.dg, r.a0, G, a.g_sdf);
+      box_in_groups(ve, lane, [&](bool part, bool single) {
+        return sdf_box_pass(box, kBoxCap, lane, part, r.x, r.dg, r.a0, r.off, r.a1, single, G,
+                            a.g_sdf);
       });
     if (do_f)
-      box_in_groups(ve, lane, [&](bool part) {
+      box_in_groups(ve, lane, [&](bool part, bool) {
         return feat_box_pass(box, kBoxCap, lane, part, r.x, r.df, G, a.g_feat);
       });
   }
@@ -792,8 +800,6 @@ __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws
   RayD r;
   ray_setup_d(ro[0], ro[1], ro[2], rd[0], rd[1], rd[2], a.N, r);
   L.ray[lane] = r;
-  const int R = a.R;
-  const double inv_h = 0.5 * (a.R - 1);
   float Rc[3] = {0.f, 0.f, 0.f};  // remaining colour of this lane's ray
   int nx_i = -2, nx_slot = -1;    // the ray's entry processed last (the next in sample order)
   int base = ws.last[lw];
@@ -803,12 +809,10 @@ __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws
     L.mine[lane] = 0ull;
     wave_sync();
     int key = 0, prev = -1;
-    float s1 = 0.f;
     if (lane < n) {
       const BwdEntry& E = ws.entries[base + lane];
       key = E.key;
       prev = E.prev;
-      s1 = E.s1;
       atomicOr(&L.mine[key & 63], 1ull << lane);
       L.si[lane] = key >> 6;
       L.w[lane] = E.w;
@@ -845,14 +849,20 @@ __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws
       const int nin = L.nin[lane];
       BwdEntry& E = ws.entries[base + lane];
       E.gdl = gdl;
-      E.next_in = nin;
+      // s_{i+1} belongs to no entry: its share of the opacity gradient is added
+      // with this sample's by the box pass, at x_i + off
+      float off[3] = {0.f, 0.f, 0.f};
       if (!nin) {
-        // s_{i+1} belongs to no entry: its share of the opacity gradient goes here
         const RayD& rr = L.ray[key & 63];
-        double x1[3];
+        double x0[3], x1[3];
+        sample_pos(rr, sample_t(rr, key >> 6), x0);
         sample_pos(rr, sample_t(rr, (key >> 6) + 1), x1);
-        scatter8(a.g_sdf, R, cell_d(x1, R, inv_h), a.tau * sigmoidf(-a.tau * s1) * gdl);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) off[c] = (float)(x1[c] - x0[c]);
       }
+      E.nx_off[0] = off[0];
+      E.nx_off[1] = off[1];
+      E.nx_off[2] = off[2];
     }
     base = __shfl(prev, 0, 64);
     n = 64;

@@ -55,9 +55,9 @@ struct BwdEntry {
   // written by the per-ray walk of a taped backward
   float gdl;      // dL/d dl_i
   float gdl_prev; // dL/d dl_{i-1} when sample i-1 of the ray is an entry, else 0
-  int next_in;    // 1: sample i+1 of the ray is an entry
   int pkey;       // key of the probe cell of x (the binning order of the backward)
-  float pad[2];
+  float nx_off[3];// x_{i+1} - x_i when sample i+1 of the ray is not an entry (the
+                  // opacity gradient at s_{i+1} goes with this sample), else 0
 };
 
 // Gradient record of one shaded sample for the probe grid, placed in probe-cell order.
@@ -77,6 +77,8 @@ struct ScatRec {
   float a0;       // dL/ds_i through the opacities of samples i and i-1
   float df[3];    // dL/d(spatial features at x)
   int valid;      // 0: the slot holds no sample to scatter
+  float off[3];   // x_{i+1} - x_i when the opacity gradient at s_{i+1} goes here
+  float a1;       // dL/ds_{i+1} (trilinear at x + off), else 0
   float pad[2];
 };
 

@@ -118,9 +118,8 @@ __device__ __forceinline__ void fwd_batch(const RenderArgs& a, const Geo& G, Fwd
         e.gn = nm.gn;
         e.gdl = 0.f;
         e.gdl_prev = 0.f;
-        e.next_in = 0;
         e.pkey = pkey;
-        e.pad[0] = e.pad[1] = 0.f;
+        e.nx_off[0] = e.nx_off[1] = e.nx_off[2] = 0.f;
         ws.entries[base + lane] = e;
       }
       // the backward's probe-cell histogram

@@ -112,7 +112,7 @@ def test_backward_workspace_validation():
     B = 1000
     need = ps.backward_workspace_bytes(B, 16, 0)
     assert need > 0
-    assert ps.backward_workspace_bytes(B, 16, 10) == need + 10 * 272
+    assert ps.backward_workspace_bytes(B, 16, 10) == need + 10 * 288
     assert ps.backward_workspace_bytes(B, 32, 0) > need
     # misaligned workspace
     assert L.psdf_render_backward(C.byref(_field()), C.byref(_opts()), B, FAKE, FAKE, FAKE, FAKE,
