@@ -181,9 +181,30 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
   }
 }
 
+// log(1 + y) for 0 <= y <= 1 as 2 atanh(t), t = y / (2 + y) <= 1/3: the odd series
+// t + t^3/3 + t^5/5 + ... summed to t^15 (the first term left out is below 2^-25 of the
+// sum), with the quotient corrected by one Newton step.  Within 2 ulp of log1p for
+// normal y, a fifth of the instructions of the library routine, which carries extra
+// precision throughout.
+__device__ __forceinline__ float log1p_unit(float y) {
+  const float d = 2.0f + y;
+  const float r = __builtin_amdgcn_rcpf(d);
+  float t = y * r;
+  t = fmaf(fmaf(-t, d, y), r, t);
+  const float s = t * t;
+  float q = 2.0f / 15.0f;
+  q = fmaf(q, s, 2.0f / 13.0f);
+  q = fmaf(q, s, 2.0f / 11.0f);
+  q = fmaf(q, s, 2.0f / 9.0f);
+  q = fmaf(q, s, 2.0f / 7.0f);
+  q = fmaf(q, s, 2.0f / 5.0f);
+  q = fmaf(q, s, 2.0f / 3.0f);
+  return fmaf(t * s, q, 2.0f * t);
+}
+
 // log of the logistic Phi(x) = 1/(1+e^-x), overflow free
 __device__ __forceinline__ float log_sigmoid(float x) {
-  return fminf(x, 0.0f) - log1pf(expf(-fabsf(x)));
+  return fminf(x, 0.0f) - log1p_unit(expf(-fabsf(x)));
 }
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
 
