@@ -170,6 +170,9 @@ __device__ __forceinline__ CellVals fetch_cell_if(const T* __restrict__ g, int R
 // March of one ray per lane over samples i = 0 .. N-1 with loads in flight
 // ahead of use: the bounds of sample i+2 and the corners of sample i+1.
 //   s0 = s_i (valid when m0), v1 = corners of sample i+1 (fetched when m0 || m1)
+// Where no lane of the wave needs the corners of a sample (all in skipped
+// bricks), the wave neither fetches nor interpolates them: w1 (wave-uniform)
+// says whether v1 holds a fetch.
 struct MarchState {
   MarchU mu;
   Cell c2;
@@ -178,6 +181,7 @@ struct MarchState {
   CellVals v1;
   float s0;
   bool m0, m1;
+  bool w1;
 };
 
 template <typename ST>
@@ -199,6 +203,7 @@ __device__ __forceinline__ void march_begin(const ST* __restrict__ sdf, int R, c
   q0.base = M.m0 ? c0.base : 0;
   M.s0 = tri1(sdf, R, q0);
   M.v1 = fetch_cell_if(sdf, R, c1, M.m0 || M.m1);
+  M.w1 = true;
 }
 
 // Step i (0 <= i < N-1): returns s_i, s_{i+1} and whether sample i may be
@@ -207,20 +212,25 @@ template <typename ST>
 __device__ __forceinline__ void march_next(const ST* __restrict__ sdf, int R, const Bricks& K,
                                            bool hit, int i, int N, MarchState& M, float& s_i,
                                            float& s_n, bool& may_i) {
-  const CellVals cur = M.v1;
+  // s_{i+1}, from the corners fetched one step ago (unused where none were)
+  s_n = 0.f;
+  if (M.w1) s_n = interp_cell(M.v1);  // wave-uniform
   bool m2 = false;
   if (i + 2 < N) {  // wave-uniform
     m2 = hit && brick_may(K, M.b2);
-    M.v1 = fetch_cell_if(sdf, R, M.c2, M.m1 || m2);
+    const bool need = M.m1 || m2;
+    const Cell c = M.c2;
+    // the bounds of sample i+3 go out before the corners of sample i+2
     if (i + 3 < N) {
       march_step(M.mu);
       M.c2 = march_cell_b(M.mu, R, K.nb, M.k2);
       M.b2 = brick_load(K, hit, M.k2);
     }
+    M.w1 = __ballot(need) != 0;
+    if (M.w1) M.v1 = fetch_cell_if(sdf, R, c, need);
   }
   s_i = M.s0;
   may_i = M.m0;
-  s_n = interp_cell(cur);
   M.s0 = s_n;
   M.m0 = M.m1;
   M.m1 = m2;
