@@ -77,30 +77,6 @@ __device__ __forceinline__ void feat_scatter_wave(float (*sc)[65], int* fb, bool
 // whole wave.
 // ---------------------------------------------------------------------------
 
-// Wave-wide min / max (call with every lane active), on DPP lane moves: a scan
-// within each row of 16 lanes (shifts 1, 2, 4, 8), then rows combined by the row
-// broadcasts of lanes 15 and 31, so lane 63 holds the result.
-__device__ __forceinline__ int wave_min_i(int v) {
-  constexpr int kId = 0x7FFFFFFF;
-  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x111, 0xf, 0xf, false));  // row_shr:1
-  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x112, 0xf, 0xf, false));  // row_shr:2
-  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x114, 0xf, 0xf, false));  // row_shr:4
-  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x118, 0xf, 0xf, false));  // row_shr:8
-  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
-  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
-  return __builtin_amdgcn_readlane(v, 63);
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-  constexpr int kId = -0x7FFFFFFF - 1;
-  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x111, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x112, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x114, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x118, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x142, 0xa, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x143, 0xc, 0xf, false));
-  return __builtin_amdgcn_readlane(v, 63);
-}
-
 // zero the first n floats of a 16-byte aligned box whose capacity is a multiple
 // of 4 floats (n <= capacity)
 __device__ __forceinline__ void box_clear(float* box, int n, int lane) {

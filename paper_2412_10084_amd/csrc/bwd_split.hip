@@ -92,6 +92,7 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   w.srecs = reinterpret_cast<ScatRec*>(p + fixed_bytes(B, P) +
                                        w.cap * (int64_t)(sizeof(BwdEntry) + sizeof(ProbeRec)));
   w.nsorted = reinterpret_cast<int*>(p + 16);
+  w.mbox = reinterpret_cast<int*>(p + 32);
   w.ndesc = ndesc_of(P, w.cap);
   w.bdesc = reinterpret_cast<int2*>(p + fixed_bytes(B, P) + w.cap * kPerSample);
   w.n_waves = nw;
@@ -99,6 +100,7 @@ BwdWs bwd_ws_carve(void* base, int64_t B, int P, int64_t bytes) {
   w.nsum = nsum_of(P);
   w.probe_bins = 0;
   w.bins = 0;
+  w.range = 0;
   return w;
 }
 
@@ -114,6 +116,7 @@ __global__ void __launch_bounds__(256) bwd_ws_clear_kernel(BwdWs ws, int waves) 
     *ws.pocc = 0;
     *ws.nbatch = 0;
   }
+  if (i < 6) ws.mbox[i] = i < 3 ? 0x7FFFFFFF : -1;
   if (waves && i < ws.n_waves) ws.overflow[i] = 0;
   if (ws.bins && i < ws.nkeys) ws.pcount[i] = 0;
 }

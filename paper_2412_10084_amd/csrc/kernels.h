@@ -100,6 +100,8 @@ struct BwdWs {
   int2* bdesc;         // [ndesc] (first sorted slot, samples): up to 64 samples of one
                        // block of 2x2x2 probe cells
   int* nsorted;        // [1] samples filed in probe-cell order (taped schedule)
+  int* mbox;           // [6] brick box (min x, y, z, max x, y, z) of the bricks that may pass
+                       // the skip rule (taped forward with brick bounds)
   float* mlp_part;     // [kMlpWaves][227] MLP gradient partials of the shading waves
   float* mlp_r;        // [227] the MLP with its weights rounded as the shading pass rounds them
   BwdEntry* entries;   // [cap]
@@ -110,6 +112,7 @@ struct BwdWs {
   int64_t nkeys, nsum;  // probe-cell keys (bins) and scan blocks
   int probe_bins;      // 1: the probe gradient goes through the cell bins
   int bins;            // 1: samples are counted per probe cell (probe bins or taped order)
+  int range;           // 1: the taped forward marches each wave over the samples in mbox
 };
 
 // bytes of a workspace with room for `cap` samples; carve() lays it out

@@ -175,10 +175,20 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a, BwdWs w
   int my_first = 0, my_last = 0, my_cnt = 0;
   int head = 0, tail = 0;  // wave-uniform ring cursors (sequence numbers)
   const Bricks K = make_bricks(a.bounds, a.R, a.skip_thr);
+  // samples first .. last_s are stepped (wave-uniform); outside the interval no
+  // lane of the wave can have a sample in a brick that passes the bounds test, so
+  // no sample there is active and the march has nothing to compute
+  int first = 0, last_s = a.N - 2;
+  if (tape && ws.range) {
+    int lo, hi;
+    may_range(r, G.inv_h, a.N, hit, ws.mbox, lo, hi);
+    first = wave_min_i(lo);
+    last_s = min(wave_max_i(hi), a.N - 2);
+  }
   MarchState ms;
-  march_begin(sdf, a.R, K, r, G.inv_h, hit, a.N, ms);
-  for (int i = 0;; ++i) {
-    const bool stepping = i < a.N - 1;  // wave-uniform
+  if (first <= last_s) march_begin_at(sdf, a.R, K, r, G.inv_h, hit, a.N, first, ms);
+  for (int i = first;; ++i) {
+    const bool stepping = i <= last_s;  // wave-uniform
     if (stepping) {
       float s_i, s_n;
       bool may;
@@ -243,6 +253,58 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a, BwdWs w
   }
 }
 
+// Brick box of the bricks whose bounds pass the skip test (brick_may): 16 bricks
+// per thread, a block-wide min / max, six integer atomics per block.
+constexpr int kBoxPer = 16;
+
+__global__ void __launch_bounds__(256) may_box_kernel(Bricks K, int* box) {
+  __shared__ int red[6][4];
+  const int nb = K.nb, n = nb * nb * nb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int lo[3] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF}, hi[3] = {-1, -1, -1};
+  const int base = blockIdx.x * (256 * kBoxPer) + threadIdx.x;
+  float2 mm[kBoxPer];
+#pragma unroll
+  for (int j = 0; j < kBoxPer; ++j) {
+    const int b = base + j * 256;
+    mm[j] = K.b[b < n ? b : 0];
+  }
+#pragma unroll
+  for (int j = 0; j < kBoxPer; ++j) {
+    const int b = base + j * 256;
+    if (b < n && brick_may(K, mm[j])) {
+      const int c[3] = {b % nb, (b / nb) % nb, b / (nb * nb)};
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = min(lo[q], c[q]);
+        hi[q] = max(hi[q], c[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    lo[q] = wave_min_i(lo[q]);
+    hi[q] = wave_max_i(hi[q]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      red[q][wv] = lo[q];
+      red[3 + q][wv] = hi[q];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int q = threadIdx.x;
+    int v = red[q][0];
+    for (int w = 1; w < 4; ++w) v = q < 3 ? min(v, red[q][w]) : max(v, red[q][w]);
+    if (q < 3 ? v != 0x7FFFFFFF : v != -1) {
+      if (q < 3) atomicMin(box + q, v);
+      else atomicMax(box + q, v);
+    }
+  }
+}
+
 hipError_t launch_render_forward(const RenderArgs& a, const BwdWs* tape, int sdf_dt, int feat_dt,
                                  int mlp_dt, int n_sh, hipStream_t s) {
   const dim3 grid((unsigned)((a.B + BLOCK - 1) / BLOCK));
@@ -253,6 +315,13 @@ hipError_t launch_render_forward(const RenderArgs& a, const BwdWs* tape, int sdf
     ws.bins = 1;  // the forward counts its samples per probe-cell key
     const hipError_t e = launch_bwd_ws_clear(ws, s);
     if (e != hipSuccess) return e;
+    const Bricks K = make_bricks(a.bounds, a.R, a.skip_thr);
+    ws.range = K.b ? 1 : 0;
+    if (ws.range) {
+      const int n = K.nb * K.nb * K.nb, per = 256 * kBoxPer;
+      hipLaunchKernelGGL(may_box_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0, s,
+                         K, ws.mbox);
+    }
   }
   const int on = tape ? 1 : 0;
   PSDF_DT_SWITCH(sdf_dt, feat_dt, PSDF_SH_SWITCH(n_sh, PSDF_MLP_SWITCH(mlp_dt,

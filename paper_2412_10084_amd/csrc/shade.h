@@ -117,7 +117,7 @@ struct Bricks {
   float thr;
 };
 
-__device__ __forceinline__ Bricks make_bricks(const float* bounds, int R, float skip_thr) {
+__host__ __device__ inline Bricks make_bricks(const float* bounds, int R, float skip_thr) {
   Bricks k;
   k.b = skip_thr > 0.f ? reinterpret_cast<const float2*>(bounds) : nullptr;
   k.nb = ((R - 2) >> BRICK_SHIFT) + 1;
@@ -184,11 +184,14 @@ struct MarchState {
   bool w1;
 };
 
+// Begin at sample F (wave-uniform): the coordinate is advanced from sample 0 by the
+// same F additions a march from sample 0 makes, so every later value is identical.
 template <typename ST>
-__device__ __forceinline__ void march_begin(const ST* __restrict__ sdf, int R, const Bricks& K,
-                                            const RayD& r, double inv_h, bool hit, int N,
-                                            MarchState& M) {
+__device__ __forceinline__ void march_begin_at(const ST* __restrict__ sdf, int R, const Bricks& K,
+                                               const RayD& r, double inv_h, bool hit, int N, int F,
+                                               MarchState& M) {
   march_init(r, inv_h, M.mu);
+  for (int j = 0; j < F; ++j) march_step(M.mu);
   int k0, k1;
   const Cell c0 = march_cell_b(M.mu, R, K.nb, k0);
   march_step(M.mu);
@@ -196,14 +199,56 @@ __device__ __forceinline__ void march_begin(const ST* __restrict__ sdf, int R, c
   const float2 b0 = brick_load(K, hit, k0), b1 = brick_load(K, hit, k1);
   march_step(M.mu);
   M.c2 = march_cell_b(M.mu, R, K.nb, M.k2);
-  M.b2 = brick_load(K, hit && N > 2, M.k2);
+  M.b2 = brick_load(K, hit && N > F + 2, M.k2);
   M.m0 = hit && brick_may(K, b0);
-  M.m1 = hit && N > 1 && brick_may(K, b1);
+  M.m1 = hit && N > F + 1 && brick_may(K, b1);
   Cell q0 = c0;
   q0.base = M.m0 ? c0.base : 0;
   M.s0 = tri1(sdf, R, q0);
   M.v1 = fetch_cell_if(sdf, R, c1, M.m0 || M.m1);
   M.w1 = true;
+}
+
+template <typename ST>
+__device__ __forceinline__ void march_begin(const ST* __restrict__ sdf, int R, const Bricks& K,
+                                            const RayD& r, double inv_h, bool hit, int N,
+                                            MarchState& M) {
+  march_begin_at(sdf, R, K, r, inv_h, hit, N, 0, M);
+}
+
+// Samples of a ray that may lie in a brick passing the bounds test.  `box` holds
+// the brick coordinates (min x, y, z, max x, y, z) of every such brick; the march
+// coordinate of sample i is u_0 + i du, so the samples inside the box, widened by
+// one cell, form one interval of i, returned widened by one sample (the
+// accumulated coordinate differs from u_0 + i du by ~1e-12 of a cell).  Empty:
+// lo = N, hi = -1.
+__device__ __forceinline__ void may_range(const RayD& r, double inv_h, int N, bool hit,
+                                          const int* box, int& lo, int& hi) {
+  lo = N;
+  hi = -1;
+  if (!hit || box[3] < box[0]) return;
+  MarchU m;
+  march_init(r, inv_h, m);
+  double tlo = -1e300, thi = 1e300;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double cells = (double)(1 << BRICK_SHIFT);  // cells per brick edge
+    const double blo = cells * box[a] - 1.0, bhi = cells * (box[3 + a] + 1) + 1.0;
+    const double u = m.u[a], d = m.du[a];
+    if (d > 0.0) {
+      tlo = fmax(tlo, (blo - u) / d);
+      thi = fmin(thi, (bhi - u) / d);
+    } else if (d < 0.0) {
+      tlo = fmax(tlo, (bhi - u) / d);
+      thi = fmin(thi, (blo - u) / d);
+    } else if (u < blo || u > bhi) {
+      return;
+    }
+  }
+  const double l = fmax(floor(tlo) - 1.0, 0.0), h = fmin(ceil(thi) + 1.0, (double)(N - 1));
+  if (!(l <= h)) return;
+  lo = (int)l;
+  hi = (int)h;
 }
 
 // Step i (0 <= i < N-1): returns s_i, s_{i+1} and whether sample i may be
@@ -288,6 +333,30 @@ __device__ __forceinline__ void for_each_key_group(bool on, int key, F&& f) {
     f(k, leader, grp);
     todo &= ~grp;
   }
+}
+
+// Wave-wide min / max (call with every lane active), on DPP lane moves: a scan
+// within each row of 16 lanes (shifts 1, 2, 4, 8), then rows combined by the row
+// broadcasts of lanes 15 and 31, so lane 63 holds the result.
+__device__ __forceinline__ int wave_min_i(int v) {
+  constexpr int kId = 0x7FFFFFFF;
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = min(v, __builtin_amdgcn_update_dpp(kId, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+  constexpr int kId = -0x7FFFFFFF - 1;
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x111, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x112, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x114, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x118, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x142, 0xa, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // grid geometry handed to the shading code

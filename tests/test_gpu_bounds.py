@@ -84,6 +84,31 @@ def test_forward_with_bounds_is_identical(R, P, shape, skip):
     assert np.count_nonzero(ref["rgb"].sum(1)) > 500
 
 
+@pytest.mark.parametrize("R,P,shape,skip", [(64, 16, "sphere", 4.0), (65, 16, "torus", 2.0),
+                                            (33, 8, "sphere", 4.0), (64, 16, "empty", 4.0)])
+def test_taped_forward_range_is_identical(R, P, shape, skip):
+    """A taped forward with bounds steps each wave only over the samples that can lie
+    in the box of the bricks passing the bounds test; every output equals the plain
+    march without bounds bit for bit (including a field with no such brick)."""
+    import paper_2412_10084_amd as ps
+    f = scene(5, R, P, shape="sphere" if shape == "empty" else shape)
+    if shape == "empty":
+        f.sdf[...] = 0.75  # no sample passes the skip rule anywhere
+    o, d = rays(8, 32, 16)
+    o, d = o[:4093], d[:4093]
+    fld = device_field(f)
+    plain = gpu_forward(fld, o, d, 96, skip=skip)
+    fld.bounds = ps.sdf_bounds(fld.sdf)
+    tape = ps.backward_workspace(o.shape[0], fld.probes.shape[0], 1 << 20)
+    taped = gpu_forward(fld, o, d, 96, skip=skip, tape=tape)
+    for k in ("rgb", "aux", "depth_wsum"):
+        np.testing.assert_array_equal(taped[k], plain[k], err_msg=k)
+    if shape == "empty":
+        assert not taped["rgb"].any()
+    else:
+        assert np.count_nonzero(taped["rgb"].sum(1)) > 500
+
+
 def test_forward_with_bounds_fp16_sdf():
     f = scene(0, 64, 16)
     o, d = rays(8, 32, 16)
