@@ -303,7 +303,7 @@ TRAFFIC_KERNELS = {
                         "psdf::mlp_reduce_kernel", "psdf::bwd_box_kernel",
                         "void psdf::probe_reduce_kernel<9>",
                         "void psdf::render_bwd_kernel<float, float, 9, 0>"),
-    "render_forward": ("void psdf::render_fwd_kernel<float, float, 9, 0>",),
+    "render_forward": ("psdf::may_box_kernel", "void psdf::render_fwd_kernel<float, float, 9, 0>"),
     "grid_step": ("psdf::zero3_kernel", "psdf::bounds_init_kernel", "psdf::step_sdf_tiled_kernel",
                   "psdf::bounds_decode_kernel", "psdf::step_tv3v_kernel",
                   "void psdf::step_tv4_kernel<36>", "psdf::step_mlp_kernel"),

@@ -253,9 +253,9 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(RenderArgs a, BwdWs w
   }
 }
 
-// Brick box of the bricks whose bounds pass the skip test (brick_may): 16 bricks
+// Brick box of the bricks whose bounds pass the skip test (brick_may): 4 bricks
 // per thread, a block-wide min / max, six integer atomics per block.
-constexpr int kBoxPer = 16;
+constexpr int kBoxPer = 4;
 
 __global__ void __launch_bounds__(256) may_box_kernel(Bricks K, int* box) {
   __shared__ int red[6][4];

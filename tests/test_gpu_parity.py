@@ -143,11 +143,11 @@ def test_backward_accumulates_and_null_groups():
 # ---------------------------------------------------------------------------
 # L1 loss kernel
 # ---------------------------------------------------------------------------
-def test_l1_loss_kernel():
+@pytest.mark.parametrize("B", [5000, 5001, 262144])  # float4 path, scalar path, train256 batch
+def test_l1_loss_kernel(B):
     import paper_2412_10084_amd as ps
     t = torch()
     rng = np.random.default_rng(3)
-    B = 5000
     rgb = rng.uniform(size=(B, 3)).astype(np.float32)
     tgt = rng.uniform(size=(B, 3)).astype(np.float32)
     tgt[:7] = rgb[:7]
