@@ -35,15 +35,17 @@ def log(msg):
 
 
 class KernelTimer:
-    """Events around each launch on torch's current stream (the launch stream)."""
+    """Events around each launch on torch's current stream (the launch stream); `only`
+    limits them to the named entry points."""
 
-    def __init__(self, torch):
+    def __init__(self, torch, only=None):
         self.torch = torch
         self.pending = []
         self.enabled = False
+        self.only = only
 
     def run(self, name, fn):
-        if not self.enabled:
+        if not self.enabled or (self.only is not None and name not in self.only):
             fn()
             return
         t = self.torch
@@ -126,12 +128,32 @@ def train_step(ps, w, st, step, timer):
     st["master"] = dict(sdf=out["sdf"], feat=out["feat"], probes=out["probes"], mlp=p["mlp"])
 
 
-def time_training(torch, ps, w, st, steps, warmup, label):
-    timer = KernelTimer(torch)
+def clone_state(torch, st, memo=None):
+    """Copy of a training state: tensors cloned (a tensor held twice stays one tensor),
+    containers rebuilt, everything else shared."""
+    memo = {} if memo is None else memo
+    if isinstance(st, torch.Tensor):
+        if id(st) not in memo:
+            memo[id(st)] = st.clone()
+        return memo[id(st)]
+    if isinstance(st, dict):
+        return {k: clone_state(torch, v, memo) for k, v in st.items()}
+    if isinstance(st, (list, tuple)):
+        return type(st)(clone_state(torch, v, memo) for v in st)
+    return st
+
+
+def time_training(torch, ps, w, st, steps, warmup, label, live=("grid_step",)):
+    """ms per step over `steps` timed steps, and the mean time of each entry point.
+    In the timed steps only the `live` entry points (the roofline's) are bracketed by
+    events: an event pair around every entry point adds ~25 us to a 0.9 ms step. The
+    other entry points are timed in a second, untimed pass of as many steps."""
+    timer = KernelTimer(torch, only=set(live))
     for i in range(warmup):
         train_step(ps, w, st, i + 1, timer)
     torch.cuda.synchronize()
     log(f"{label}: warmup done ({warmup} steps)")
+    snap = clone_state(torch, st)
     timer.enabled = True
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -142,7 +164,15 @@ def time_training(torch, ps, w, st, steps, warmup, label):
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
-    kern = timer.summary()
+    # the same steps again from the state the timed ones started from
+    every = KernelTimer(torch)
+    every.enabled = True
+    for i in range(steps):
+        train_step(ps, w, snap, warmup + i + 1, every)
+    torch.cuda.synchronize()
+    del snap
+    kern = every.summary()
+    kern.update(timer.summary())
     log(f"{label}: {ms:.3f} ms/step, kernels " + ", ".join(f"{k} {v:.3f}" for k, v in kern.items()))
     return ms, kern
 
@@ -370,8 +400,8 @@ def main():
                     help="also run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the render step is measured on "
-                                   "one MI355X; --gpus must be 1"}))
+        print(json.dumps({"error": "the render step is measured on one MI355X (one process, "
+                                   "one GPU); --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -1,0 +1,37 @@
+"""Host-side pieces of the benchmark driver (no GPU): the state copy its per-entry
+timing pass starts from, the event filter of the timed pass, and the one-GPU rule."""
+import json
+import subprocess
+import sys
+from pathlib import Path
+
+import torch
+
+import bench
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def test_clone_state_keeps_aliasing_and_copies_tensors():
+    a, b = torch.arange(4.0), torch.ones(2)
+    st = {"master": {"sdf": a, "mlp": b}, "spare": {"sdf": a}, "order": [b, 3], "half": None}
+    c = bench.clone_state(torch, st)
+    assert c["master"]["sdf"] is c["spare"]["sdf"] and c["master"]["mlp"] is c["order"][0]
+    assert c["master"]["sdf"] is not a and c["order"][1] == 3 and c["half"] is None
+    c["master"]["sdf"].add_(1.0)
+    assert torch.equal(a, torch.arange(4.0))
+
+
+def test_kernel_timer_only_brackets_the_named_entry_points():
+    calls = []
+    t = bench.KernelTimer(torch, only={"grid_step"})
+    t.enabled = True
+    t.run("render_forward", lambda: calls.append("f"))  # no events: runs on the CPU
+    assert calls == ["f"] and t.pending == []
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "--gpus must be 1" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
