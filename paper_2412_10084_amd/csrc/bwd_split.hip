@@ -26,6 +26,19 @@
 // A wave whose entries do not fit into the workspace is flagged and handled by
 // the fused kernel afterwards (its partial entries are skipped; their probe
 // records carry zeros).
+//
+// Taped schedule (the forward recorded its shaded samples with their MLP inputs,
+// normal and probe-cell key, and counted them per probe cell): no march.
+//   walk   -- per ray, dL/d dl_i of every entry, that of the previous sample when
+//             it is an entry, and the offset x_{i+1} - x_i when the next sample
+//             is not one (its opacity term then travels with sample i);
+//   shade  -- waves take the entries in probe-cell order, 64 slots of one block
+//             of 2x2x2 probe cells at a time: MLP reverse mode (weight gradient
+//             on MFMA), one probe record and one scatter record per sample;
+//   box    -- per block of probe cells, the SDF cotangents (FD normal, opacity
+//             at s_i and at x_i + offset) and the feature cotangents are summed
+//             in LDS boxes (fixed-point integer adds) and flushed row by row;
+//   probes -- as pass 4 above, over the shading pass's records.
 #include "bwd_common.h"
 #include "dispatch.h"
 
