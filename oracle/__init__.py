@@ -26,7 +26,8 @@ _lp = C.POINTER(C.c_int64)
 
 class _Field(C.Structure):
     _fields_ = [("R", C.c_int32), ("P", C.c_int32), ("n_feat", C.c_int32), ("n_sh", C.c_int32),
-                ("n_ang", C.c_int32), ("hidden", C.c_int32), ("sdf", _dp), ("feat", _dp),
+                ("n_ang", C.c_int32), ("hidden", C.c_int32), ("mlp_layers", C.c_int32),
+                ("sdf", _dp), ("feat", _dp),
                 ("probes", _dp), ("mlp", _dp)]
 
 
@@ -43,17 +44,32 @@ class _StepOpts(C.Structure):
 
 
 NO_FS, NO_FA, NV_ONE = 1, 2, 4
+SH_REFLECT, FRESNEL_PAPER = 8, 16
+MAX_N = 1 << 20  # largest sample count the render calls accept
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _ok(rc: int, what: str):
+    if rc != 0:
+        raise OracleError(f"oracle {what} rejected its arguments (rc={rc})")
 
 
 def lib():
+    """The oracle library: oracle/liboracle.so, or the build named by the
+    PSDF_ORACLE_LIB environment variable (a sanitised build, say)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("PSDF_ORACLE_LIB") or LIB_PATH
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             _build()
-        _lib = C.CDLL(LIB_PATH)
+        _lib = C.CDLL(path)
         _lib.orc_logsigmoid.restype = C.c_double
         _lib.orc_composite.restype = C.c_double
         _lib.orc_l1_loss.restype = C.c_double
+        _lib.orc_mlp_size.restype = C.c_int64
     return _lib
 
 
@@ -78,13 +94,17 @@ class OField:
     n_feat: int = 3
     n_ang: int = 4
     hidden: int = 16
+    layers: int = 1
 
     def cstruct(self) -> _Field:
         return _Field(self.R, self.P, self.n_feat, self.n_sh, self.n_ang, self.hidden,
-                      _p(self.sdf), _p(self.feat), _p(self.probes), _p(self.mlp))
+                      self.layers, _p(self.sdf), _p(self.feat), _p(self.probes), _p(self.mlp))
+
+    def n_inputs(self, flags: int = 0) -> int:
+        return self.n_feat + self.n_ang + (6 if flags & FRESNEL_PAPER else 3)
 
 
-def make_field(sdf, feat, probes, mlp, n_sh=None, hidden=16) -> OField:
+def make_field(sdf, feat, probes, mlp, n_sh=None, hidden=16, layers=1) -> OField:
     sdf, feat, probes, mlp = _d(sdf), _d(feat), _d(probes), _d(mlp)
     R = sdf.shape[0]
     P = probes.shape[0]
@@ -93,7 +113,7 @@ def make_field(sdf, feat, probes, mlp, n_sh=None, hidden=16) -> OField:
         n_sh = probes.shape[3]
     n_ang = probes.shape[-1]
     return OField(R=R, P=P, n_sh=n_sh, sdf=sdf, feat=feat, probes=probes, mlp=mlp,
-                  n_feat=n_feat, n_ang=n_ang, hidden=hidden)
+                  n_feat=n_feat, n_ang=n_ang, hidden=hidden, layers=layers)
 
 
 def field_from(fld, half: bool = False, half_sdf: bool = False) -> OField:
@@ -104,7 +124,8 @@ def field_from(fld, half: bool = False, half_sdf: bool = False) -> OField:
         feat, probes = feat.astype(np.float16), probes.astype(np.float16)
     if half_sdf:
         sdf = sdf.astype(np.float16)
-    return make_field(sdf, feat, probes, fld.mlp, n_sh=fld.n_sh)
+    return make_field(sdf, feat, probes, fld.mlp, n_sh=fld.n_sh, hidden=fld.hidden,
+                      layers=fld.layers)
 
 
 # ---------------------------------------------------------------------------
@@ -146,13 +167,32 @@ def logsigmoid(x):
     return lib().orc_logsigmoid(C.c_double(x))
 
 
-def mlp_forward(mlp, z, hidden=16):
+def sh_grad(n_sh, v):
+    """(n_sh, 3): gradient of each SH polynomial at v"""
+    dY = np.zeros(48)
+    rc = lib().orc_sh_grad(C.c_int(n_sh), _p(_d(v)), _p(dY))
+    if rc != 0:
+        raise ValueError(n_sh)
+    return dY[:3 * n_sh].reshape(n_sh, 3)
+
+
+def mlp_size(n_in, hidden=16, layers=1) -> int:
+    return int(lib().orc_mlp_size(C.c_int(n_in), C.c_int(hidden), C.c_int(layers)))
+
+
+def mlp_forward(mlp, z, hidden=16, layers=1):
+    """returns C, out, hid, pre; hid and pre are (layers, hidden) for layers > 1"""
     z = _d(z)
     n_in = z.shape[0]
-    pre, hid = np.zeros(hidden), np.zeros(hidden)
+    mlp = _d(mlp)
+    if mlp.size != mlp_size(n_in, hidden, layers):
+        raise ValueError(f"mlp has {mlp.size} values, expected {mlp_size(n_in, hidden, layers)}")
+    pre, hid = np.zeros(layers * hidden), np.zeros(layers * hidden)
     out, Cc = np.zeros(3), np.zeros(3)
-    lib().orc_mlp_forward(_p(_d(mlp)), C.c_int(n_in), C.c_int(hidden), _p(z), _p(pre),
-                          _p(hid), _p(out), _p(Cc))
+    lib().orc_mlp_forward(_p(mlp), C.c_int(n_in), C.c_int(hidden), C.c_int(layers), _p(z),
+                          _p(pre), _p(hid), _p(out), _p(Cc))
+    if layers > 1:
+        hid, pre = hid.reshape(layers, hidden), pre.reshape(layers, hidden)
     return Cc, out, hid, pre
 
 
@@ -166,9 +206,18 @@ def composite(s, active, tau):
     return alpha, T, w, logT
 
 
+def _check_field(of: OField, flags: int):
+    fs = of.cstruct()
+    _ok(lib().orc_field_check(C.byref(fs), C.c_int32(flags)), "field")
+    n = mlp_size(of.n_inputs(flags), of.hidden, of.layers)
+    if of.mlp.size != n:
+        raise OracleError(f"mlp has {of.mlp.size} values, the colour model needs {n}")
+
+
 def shade(of: OField, x, v, flags=0):
+    _check_field(of, flags)
     Cc = np.zeros(3)
-    z = np.zeros(of.n_feat + of.n_ang + 3)
+    z = np.zeros(of.n_inputs(flags))
     fs = of.cstruct()
     lib().orc_shade(C.byref(fs), C.c_int32(flags), _p(_d(x)), _p(_d(v)), _p(Cc), _p(z))
     return Cc, z
@@ -183,10 +232,12 @@ def render_forward(of: OField, rays_o, rays_d, n_samples, tau=64.0, skip_voxels=
     rgb, aux = np.zeros((B, 3)), np.zeros((B, 4))
     dw, margin = np.zeros((B, 2)), np.zeros(B)
     ns = np.zeros(B, dtype=np.int32)
+    _check_field(of, flags)
     fs = of.cstruct()
     op = _Opts(n_samples, tau, skip_voxels, flags)
-    lib().orc_render_forward(C.byref(fs), C.byref(op), C.c_int64(B), _p(o), _p(d), _p(rgb),
-                             _p(aux), _p(dw), _p(margin), ns.ctypes.data_as(_ip))
+    _ok(lib().orc_render_forward(C.byref(fs), C.byref(op), C.c_int64(B), _p(o), _p(d), _p(rgb),
+                                 _p(aux), _p(dw), _p(margin), ns.ctypes.data_as(_ip)),
+        "render_forward")
     return dict(rgb=rgb, aux=aux, depth_wsum=dw, margin=margin, n_shaded=ns)
 
 
@@ -196,10 +247,12 @@ def render_backward(of: OField, rays_o, rays_d, dL_drgb, n_samples, tau=64.0, sk
     B = o.shape[0]
     g = dict(sdf=np.zeros_like(of.sdf), feat=np.zeros_like(of.feat),
              probes=np.zeros_like(of.probes), mlp=np.zeros_like(of.mlp))
+    _check_field(of, flags)
     fs = of.cstruct()
     op = _Opts(n_samples, tau, skip_voxels, flags)
-    lib().orc_render_backward(C.byref(fs), C.byref(op), C.c_int64(B), _p(o), _p(d), _p(dL),
-                              _p(g["sdf"]), _p(g["feat"]), _p(g["probes"]), _p(g["mlp"]))
+    _ok(lib().orc_render_backward(C.byref(fs), C.byref(op), C.c_int64(B), _p(o), _p(d), _p(dL),
+                                  _p(g["sdf"]), _p(g["feat"]), _p(g["probes"]), _p(g["mlp"])),
+        "render_backward")
     return g
 
 
@@ -281,9 +334,11 @@ def sphere_trace(of: OField, cams: np.ndarray, W: int, H: int, pixel_ids=None, e
     n = ids.shape[0]
     out, th, mg = np.zeros((n, 3)), np.zeros(n), np.zeros(n)
     steps = np.zeros(n, dtype=np.int32)
+    _check_field(of, flags)
     fs = of.cstruct()
-    lib().orc_sphere_trace(C.byref(fs), C.c_int32(flags), C.c_double(eps), C.c_int32(max_steps),
-                           C.c_int32(V), _p(cams), C.c_int32(W), C.c_int32(H),
-                           ids.ctypes.data_as(_lp), C.c_int64(n), _p(out), _p(th),
-                           steps.ctypes.data_as(_ip), _p(mg))
+    _ok(lib().orc_sphere_trace(C.byref(fs), C.c_int32(flags), C.c_double(eps),
+                               C.c_int32(max_steps), C.c_int32(V), _p(cams), C.c_int32(W),
+                               C.c_int32(H), ids.ctypes.data_as(_lp), C.c_int64(n), _p(out),
+                               _p(th), steps.ctypes.data_as(_ip), _p(mg)),
+        "sphere_trace")
     return dict(rgb=out, t_hit=th, steps=steps, margin=mg)

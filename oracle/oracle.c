@@ -20,7 +20,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define MAXN 1024   /* max samples per ray */
+#define ORC_MAX_N 1048576 /* largest N the render entry points accept */
 #define MAXIN 64    /* max MLP inputs */
 #define MAXH 128    /* max MLP hidden width */
 #define MAXSH 16
@@ -47,9 +47,9 @@ int orc_ray_box(const double o[3], const double d[3], double* tn, double* tf) {
 }
 
 /* ---------------------------------------------------------------------------
- * Trilinear interpolation on an align-corners grid (Sec. 3.2: "the voxels
- * tri-linearly interpolate the 8 nearest probes"; the same operator serves the
- * SDF and spatial features).  Reading: per axis u = (x+1)/h,
+ * Trilinear interpolation on an align-corners grid (Sec. 3.2, Eqs.
+ * sh_eval1/sh_eval2: a point blends its 8 surrounding probes with trilinear
+ * weights w_i; the same operator serves the SDF and spatial features).  Reading: per axis u = (x+1)/h,
  * k0 = clamp(floor(u), 0, R-2), f = u - k0; weight of corner (dx,dy,dz) is the
  * product over axes of (f if d=1 else 1-f).
  * ------------------------------------------------------------------------- */
@@ -153,25 +153,42 @@ double orc_logsigmoid(double x) { return fmin(x, 0.0) - log1p(exp(-fabs(x))); }
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
 /* ---------------------------------------------------------------------------
- * Colour MLP (Sec. 4: ReLU hidden layer(s), sigmoid output).  One hidden layer
- * of `hidden` units: pre1 = W1 z + b1, hid = max(pre1, 0), out = W2 hid + b2,
- * C = sigmoid(out).  Packed weights: W1[hidden][n_in] row-major, b1, W2[3][hidden], b2.
+ * Colour MLP (Sec. 4: ReLU hidden layers, sigmoid output layer).  `layers`
+ * hidden layers of `hidden` units: a_0 = z, pre_l = W_l a_{l-1} + b_l,
+ * a_l = max(pre_l, 0), out = Wo a_L + bo, C = sigmoid(out).  Packed weights, in
+ * this order: for each hidden layer W_l[hidden][n_{l-1}] row-major (n_0 = n_in,
+ * else hidden) and b_l[hidden]; then Wo[3][hidden] and bo[3].  pre and hid hold
+ * layers x hidden values (layer-major).
  * ------------------------------------------------------------------------- */
-void orc_mlp_forward(const double* mlp, int n_in, int hidden, const double* z, double* pre1,
-                     double* hid, double out[3], double C[3]) {
-  const double* W1 = mlp;
-  const double* b1 = W1 + hidden * n_in;
-  const double* W2 = b1 + hidden;
-  const double* b2 = W2 + 3 * hidden;
-  for (int k = 0; k < hidden; ++k) {
-    double acc = b1[k];
-    for (int j = 0; j < n_in; ++j) acc += W1[k * n_in + j] * z[j];
-    pre1[k] = acc;
-    hid[k] = acc > 0.0 ? acc : 0.0;
+int64_t orc_mlp_size(int n_in, int hidden, int layers) {
+  int64_t n = 0;
+  for (int l = 0; l < layers; ++l) n += (int64_t)hidden * (l == 0 ? n_in : hidden) + hidden;
+  return n + 3 * (int64_t)hidden + 3;
+}
+
+void orc_mlp_forward(const double* mlp, int n_in, int hidden, int layers, const double* z,
+                     double* pre, double* hid, double out[3], double C[3]) {
+  const double* p = mlp;
+  const double* a = z;
+  int n_prev = n_in;
+  for (int l = 0; l < layers; ++l) {
+    const double* W = p;
+    const double* b = W + hidden * n_prev;
+    for (int k = 0; k < hidden; ++k) {
+      double acc = b[k];
+      for (int j = 0; j < n_prev; ++j) acc += W[k * n_prev + j] * a[j];
+      pre[l * hidden + k] = acc;
+      hid[l * hidden + k] = acc > 0.0 ? acc : 0.0;
+    }
+    p = b + hidden;
+    a = hid + l * hidden;
+    n_prev = hidden;
   }
+  const double* Wo = p;
+  const double* bo = Wo + 3 * hidden;
   for (int c = 0; c < 3; ++c) {
-    double acc = b2[c];
-    for (int k = 0; k < hidden; ++k) acc += W2[c * hidden + k] * hid[k];
+    double acc = bo[c];
+    for (int k = 0; k < hidden; ++k) acc += Wo[c * hidden + k] * a[k];
     out[c] = acc;
     C[c] = sigmoid(acc);
   }
@@ -205,55 +222,147 @@ double orc_composite(int N, const double* s, const int32_t* active, double tau, 
 }
 
 /* ---------------------------------------------------------------------------
- * Colour of one sample (Sec. 3.1 Eq. newparametrization, Sec. 3.2 Eqs.
- * sh_eval1/sh_eval2, Sec. 4):
- *   F_s = trilinear spatial features at x,
- *   bhat_j = sum_i w_i b_ij (trilinear over the 8 probes),  F_a = sum_j bhat_j Y_j(v),
- *   c = n.v with n the normalised SDF gradient,
- *   C = MLP([F_s, F_a, c, c^2, c^4]).
- * Readings: SH is evaluated in the view direction v (pointing from the sample
- * to the camera); the incidence inputs are (c, c^2, c^4).
+ * Gradient of each real SH polynomial of orc_sh_basis with respect to its
+ * argument (x, y, z), taken on the polynomials themselves: dY[j][a] = dY_j/dx_a.
+ * Needed where the SH argument depends on the normal (reflected vector).
+ * ------------------------------------------------------------------------- */
+int orc_sh_grad(int n_sh, const double v[3], double* dY) {
+  const double pi = acos(-1.0);
+  double x = v[0], y = v[1], z = v[2];
+  if (n_sh != 1 && n_sh != 4 && n_sh != 9 && n_sh != 16) return -1;
+  for (int q = 0; q < 3 * n_sh; ++q) dY[q] = 0.0;
+  if (n_sh >= 4) {
+    double c1 = sqrt(3.0 / (4.0 * pi));
+    dY[3 * 1 + 1] = c1;
+    dY[3 * 2 + 2] = c1;
+    dY[3 * 3 + 0] = c1;
+  }
+  if (n_sh >= 9) {
+    double c2 = 0.5 * sqrt(15.0 / pi), c6 = 0.25 * sqrt(5.0 / pi), c8 = 0.25 * sqrt(15.0 / pi);
+    dY[3 * 4 + 0] = c2 * y;
+    dY[3 * 4 + 1] = c2 * x;
+    dY[3 * 5 + 1] = c2 * z;
+    dY[3 * 5 + 2] = c2 * y;
+    dY[3 * 6 + 2] = 6.0 * c6 * z;
+    dY[3 * 7 + 0] = c2 * z;
+    dY[3 * 7 + 2] = c2 * x;
+    dY[3 * 8 + 0] = 2.0 * c8 * x;
+    dY[3 * 8 + 1] = -2.0 * c8 * y;
+  }
+  if (n_sh >= 16) {
+    double a9 = 0.25 * sqrt(35.0 / (2.0 * pi)), a10 = 0.5 * sqrt(105.0 / pi);
+    double a11 = 0.25 * sqrt(21.0 / (2.0 * pi)), a12 = 0.25 * sqrt(7.0 / pi);
+    double a14 = 0.25 * sqrt(105.0 / pi);
+    dY[3 * 9 + 0] = 6.0 * a9 * x * y;
+    dY[3 * 9 + 1] = 3.0 * a9 * (x * x - y * y);
+    dY[3 * 10 + 0] = a10 * y * z;
+    dY[3 * 10 + 1] = a10 * x * z;
+    dY[3 * 10 + 2] = a10 * x * y;
+    dY[3 * 11 + 1] = a11 * (5.0 * z * z - 1.0);
+    dY[3 * 11 + 2] = 10.0 * a11 * y * z;
+    dY[3 * 12 + 2] = a12 * (15.0 * z * z - 3.0);
+    dY[3 * 13 + 0] = a11 * (5.0 * z * z - 1.0);
+    dY[3 * 13 + 2] = 10.0 * a11 * x * z;
+    dY[3 * 14 + 0] = 2.0 * a14 * x * z;
+    dY[3 * 14 + 1] = -2.0 * a14 * y * z;
+    dY[3 * 14 + 2] = a14 * (x * x - y * y);
+    dY[3 * 15 + 0] = 3.0 * a9 * (x * x - y * y);
+    dY[3 * 15 + 1] = -6.0 * a9 * x * y;
+  }
+  return 0;
+}
+
+/* Number of incidence inputs of the colour model: (c, c^2, c^4), or
+ * (1 - c)^0 .. (1 - c)^5 with ORC_FRESNEL_PAPER. */
+static int n_incidence(int32_t flags) { return (flags & ORC_FRESNEL_PAPER) ? 6 : 3; }
+
+int orc_n_inputs(const orc_field* f, int32_t flags) {
+  return f->n_feat + f->n_ang + n_incidence(flags);
+}
+
+/* 0 if the field's shape fits the fixed-size scratch of this file (MLP inputs,
+ * hidden width, SH order, layer count), else -1 */
+int orc_field_check(const orc_field* f, int32_t flags) {
+  if (f->R < 2 || f->P < 2) return -1;
+  if (f->n_sh != 1 && f->n_sh != 4 && f->n_sh != 9 && f->n_sh != 16) return -1;
+  if (f->n_ang < 1 || f->n_ang > 16 || f->n_feat < 0) return -1;
+  if (orc_n_inputs(f, flags) > MAXIN) return -1;
+  if (f->hidden < 1 || f->hidden > MAXH || f->mlp_layers < 1 || f->mlp_layers > 2) return -1;
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Colour of one sample (Sec. 3.1 Eqs. classic/newparametrization, Sec. 3.2
+ * Eqs. spherical_harmonics, sh_eval1/sh_eval2, Sec. 4):
+ *   n = g / |g| with g the SDF gradient, c = n.v (v points from the sample to
+ *   the camera);
+ *   the SH argument is v, or with ORC_SH_REFLECT the reflection of v about the
+ *   normal, r = 2 (n.v) n - v (Sec. 3.1 defines r as the reflected vector for
+ *   the view direction v; r = v at normal incidence);
+ *   F_s = trilinear spatial features at x;
+ *   bhat_j = sum_i w_i b_ij over the 8 probes, F_a = sum_j bhat_j Y_j(arg);
+ *   incidence inputs from c' = c (or 1 with ORC_NV_ONE): (c', c'^2, c'^4), or
+ *   with ORC_FRESNEL_PAPER the powers (1 - c')^0 .. (1 - c')^5 of Eq.
+ *   newparametrization;
+ *   C = MLP([F_s, F_a, incidence inputs]).
+ * The reflection always uses the true n.v; ORC_NV_ONE only replaces the
+ * incidence inputs.
  * ------------------------------------------------------------------------- */
 typedef struct {
-  double g[3], gn, n[3], c;
-  double z[MAXIN], pre1[MAXH], hid[MAXH], out[3], C[3];
-  double Y[MAXSH];
+  double g[3], gn, n[3], c, cin, arg[3];
+  double z[MAXIN], pre[2 * MAXH], hid[2 * MAXH], out[3], C[3];
+  double Y[MAXSH], bhat[MAXSH * 16];
 } shade_state;
 
 static void shade_full(const orc_field* f, int32_t flags, const double x[3], const double v[3],
                        shade_state* st) {
   int nf = f->n_feat, na = f->n_ang, nsh = f->n_sh;
-  int n_in = nf + na + 3;
-  orc_sh_basis(nsh, v, st->Y);
+  int n_in = orc_n_inputs(f, flags);
   /* normal and incidence cosine */
   orc_sdf_gradient(f->sdf, f->R, x, st->g);
   st->gn = sqrt(st->g[0] * st->g[0] + st->g[1] * st->g[1] + st->g[2] * st->g[2]);
   double inv = 1.0 / fmax(st->gn, 1e-30);
   for (int a = 0; a < 3; ++a) st->n[a] = st->g[a] * inv;
-  st->c = (flags & ORC_NV_ONE) ? 1.0 : st->n[0] * v[0] + st->n[1] * v[1] + st->n[2] * v[2];
+  st->c = st->n[0] * v[0] + st->n[1] * v[1] + st->n[2] * v[2];
+  st->cin = (flags & ORC_NV_ONE) ? 1.0 : st->c;
+  /* SH argument */
+  for (int a = 0; a < 3; ++a)
+    st->arg[a] = (flags & ORC_SH_REFLECT) ? 2.0 * st->c * st->n[a] - v[a] : v[a];
+  orc_sh_basis(nsh, st->arg, st->Y);
   /* spatial features */
   if (flags & ORC_NO_FS) {
     for (int k = 0; k < nf; ++k) st->z[k] = 0.0;
   } else {
     orc_trilinear(f->feat, f->R, nf, x, st->z);
   }
-  /* angular features: interpolate the coefficients, then evaluate the basis */
+  /* angular features: interpolate the coefficients (Eq. sh_eval2), then
+   * evaluate the basis */
   if (flags & ORC_NO_FA) {
     for (int a = 0; a < na; ++a) st->z[nf + a] = 0.0;
+    for (int q = 0; q < nsh * na; ++q) st->bhat[q] = 0.0;
   } else {
-    double bhat[MAXSH * 16];
-    orc_trilinear(f->probes, f->P, nsh * na, x, bhat);
+    orc_trilinear(f->probes, f->P, nsh * na, x, st->bhat);
     for (int a = 0; a < na; ++a) {
       double acc = 0.0;
-      for (int j = 0; j < nsh; ++j) acc += bhat[j * na + a] * st->Y[j];
+      for (int j = 0; j < nsh; ++j) acc += st->bhat[j * na + a] * st->Y[j];
       st->z[nf + a] = acc;
     }
   }
-  double c = st->c;
-  st->z[nf + na + 0] = c;
-  st->z[nf + na + 1] = c * c;
-  st->z[nf + na + 2] = c * c * c * c;
-  orc_mlp_forward(f->mlp, n_in, f->hidden, st->z, st->pre1, st->hid, st->out, st->C);
+  double c = st->cin;
+  double* zi = st->z + nf + na;
+  if (flags & ORC_FRESNEL_PAPER) {
+    double p = 1.0;
+    for (int m = 0; m < 6; ++m) {
+      zi[m] = p;
+      p *= 1.0 - c;
+    }
+  } else {
+    zi[0] = c;
+    zi[1] = c * c;
+    zi[2] = c * c * c * c;
+  }
+  orc_mlp_forward(f->mlp, n_in, f->hidden, f->mlp_layers, st->z, st->pre, st->hid, st->out,
+                  st->C);
 }
 
 void orc_shade(const orc_field* f, int32_t flags, const double x[3], const double v[3],
@@ -262,7 +371,7 @@ void orc_shade(const orc_field* f, int32_t flags, const double x[3], const doubl
   shade_full(f, flags, x, v, &st);
   for (int c = 0; c < 3; ++c) C[c] = st.C[c];
   if (z_out)
-    for (int j = 0; j < f->n_feat + f->n_ang + 3; ++j) z_out[j] = st.z[j];
+    for (int j = 0; j < orc_n_inputs(f, flags); ++j) z_out[j] = st.z[j];
 }
 
 /* ---------------------------------------------------------------------------
@@ -277,10 +386,36 @@ typedef struct {
   int hit;
   double o[3], d[3], v[3], tn, tf, dt;
   int N;
-  double t[MAXN], x[MAXN][3], s[MAXN], alpha[MAXN], T[MAXN], w[MAXN];
-  int32_t active[MAXN];
+  /* per-sample arrays of length N (ray_state_alloc) */
+  double *t, (*x)[3], *s, *alpha, *T, *w;
+  int32_t* active;
   double logT_final, margin;
 } ray_state;
+
+/* One allocation holding a ray_state and its N-sample arrays; NULL if out of
+ * memory.  Released with free(). */
+static ray_state* ray_state_alloc(int N) {
+  size_t n = (size_t)N;
+  size_t bytes = sizeof(ray_state) + n * (5 * sizeof(double) + 3 * sizeof(double)) +
+                 n * sizeof(int32_t);
+  ray_state* r = (ray_state*)calloc(1, bytes);
+  if (!r) return NULL;
+  double* p = (double*)(r + 1);
+  r->t = p;
+  p += n;
+  r->x = (double(*)[3])p;
+  p += 3 * n;
+  r->s = p;
+  p += n;
+  r->alpha = p;
+  p += n;
+  r->T = p;
+  p += n;
+  r->w = p;
+  p += n;
+  r->active = (int32_t*)p;
+  return r;
+}
 
 static void march(const orc_field* f, const orc_render_opts* opt, const double* o_in,
                   const double* d_in, ray_state* r) {
@@ -317,14 +452,24 @@ static void march(const orc_field* f, const orc_render_opts* opt, const double* 
  * Forward render (Sec. 3.3): c = sum_i T_i alpha_i C_i.  Also returned:
  * aux = (c, log T_final), depth_wsum = (sum_i w_i (t_i + dt/2), sum_i w_i),
  * margin (see march), n_shaded = samples with alpha > 0.  Misses give 0
- * (no background term).
+ * (no background term).  Returns 0, or -1 (nothing written) if N is outside
+ * [2, ORC_MAX_N] or memory runs out.
  * ------------------------------------------------------------------------- */
-void orc_render_forward(const orc_field* f, const orc_render_opts* opt, int64_t B,
-                        const double* rays_o, const double* rays_d, double* rgb, double* aux,
-                        double* depth_wsum, double* margin, int32_t* n_shaded) {
+int orc_render_forward(const orc_field* f, const orc_render_opts* opt, int64_t B,
+                       const double* rays_o, const double* rays_d, double* rgb, double* aux,
+                       double* depth_wsum, double* margin, int32_t* n_shaded) {
+  if (opt->n_samples < 2 || opt->n_samples > ORC_MAX_N) return -1;
+  if (orc_field_check(f, opt->flags)) return -1;
+  int failed = 0;
 #pragma omp parallel
   {
-  ray_state* r = (ray_state*)malloc(sizeof(ray_state));
+  ray_state* r = ray_state_alloc(opt->n_samples);
+  if (!r) {
+#pragma omp atomic write
+    failed = 1;
+  }
+#pragma omp barrier
+  if (!failed) {
 #pragma omp for schedule(dynamic, 16)
   for (int64_t b = 0; b < B; ++b) {
     march(f, opt, rays_o + 3 * b, rays_d + 3 * b, r);
@@ -353,8 +498,10 @@ void orc_render_forward(const orc_field* f, const orc_render_opts* opt, int64_t 
     if (margin) margin[b] = r->margin;
     if (n_shaded) n_shaded[b] = ns;
   }
+  }
   free(r);
   }
+  return failed ? -1 : 0;
 }
 
 /* ---------------------------------------------------------------------------
@@ -368,8 +515,10 @@ void orc_render_forward(const orc_field* f, const orc_render_opts* opt, int64_t 
  *  alpha_i = -expm1(dl_i): d alpha_i/d s_i = (1-alpha_i) tau sigma(-tau s_i),
  *      d alpha_i / d s_{i+1} = -(1-alpha_i) tau sigma(-tau s_{i+1}), zero when the
  *      max(., 0) clamp is active or the sample is inactive;
- *  then the MLP, the cosine (d c/d g = (v - c n)/|g|), the finite-difference
- *  stencil, and the trilinear weights scatter into nodes.
+ *  then the MLP, the normal n (through the incidence inputs, d c/d n = v, and
+ *  with the reflected SH argument through r = 2 (n.v) n - v), n = g/|g|
+ *  (d n/d g = (I - n n^T)/|g|), the finite-difference stencil, and the
+ *  trilinear weights scatter into nodes.
  * ------------------------------------------------------------------------- */
 static void add_atomic(double* p, double v) {
 #pragma omp atomic
@@ -385,43 +534,67 @@ static void scatter_tri(double* grid, int R, int C, const double x[3], const dou
       if (val[ch] != 0.0) add_atomic(&grid[idx[c] * C + ch], w[c] * val[ch]);
 }
 
+/* reverse mode of orc_mlp_forward: adds the weight gradients into g_mlp and
+ * returns dL/dz */
+static void mlp_backward(const double* mlp, int n_in, int H, int L, const double* z,
+                         const double* pre, const double* hid, const double dout[3],
+                         double* g_mlp, double* dz) {
+  const double* Wl[2];
+  double* gWl[2];
+  int64_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    Wl[l] = mlp + off;
+    gWl[l] = g_mlp + off;
+    off += (int64_t)H * (l == 0 ? n_in : H) + H;
+  }
+  const double* Wo = mlp + off;
+  double* gWo = g_mlp + off;
+  double* gbo = gWo + 3 * H;
+  const double* aL = hid + (L - 1) * H;
+  double da[MAXH], dpre[MAXH];
+  for (int c = 0; c < 3; ++c) {
+    add_atomic(&gbo[c], dout[c]);
+    for (int k = 0; k < H; ++k) add_atomic(&gWo[c * H + k], dout[c] * aL[k]);
+  }
+  for (int k = 0; k < H; ++k) {
+    double acc = 0.0;
+    for (int c = 0; c < 3; ++c) acc += Wo[c * H + k] * dout[c];
+    da[k] = acc;
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    int n_prev = l == 0 ? n_in : H;
+    const double* a_prev = l == 0 ? z : hid + (l - 1) * H;
+    const double* W = Wl[l];
+    double* gW = gWl[l];
+    double* gb = gW + H * n_prev;
+    /* ReLU: derivative 1 iff pre-activation > 0 */
+    for (int k = 0; k < H; ++k) dpre[k] = pre[l * H + k] > 0.0 ? da[k] : 0.0;
+    for (int k = 0; k < H; ++k) {
+      add_atomic(&gb[k], dpre[k]);
+      for (int j = 0; j < n_prev; ++j) add_atomic(&gW[k * n_prev + j], dpre[k] * a_prev[j]);
+    }
+    double* dst = l == 0 ? dz : da;
+    double tmp[MAXH > MAXIN ? MAXH : MAXIN];
+    for (int j = 0; j < n_prev; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < H; ++k) acc += W[k * n_prev + j] * dpre[k];
+      tmp[j] = acc;
+    }
+    for (int j = 0; j < n_prev; ++j) dst[j] = tmp[j];
+  }
+}
+
 static void shade_backward(const orc_field* f, int32_t flags, const double x[3],
                            const double v[3], const shade_state* st, const double dC[3],
                            double* g_sdf, double* g_feat, double* g_probes, double* g_mlp) {
-  int nf = f->n_feat, na = f->n_ang, nsh = f->n_sh, H = f->hidden;
-  int n_in = nf + na + 3;
-  const double* W1 = f->mlp;
-  const double* W2 = W1 + H * n_in + H;
-  double* gW1 = g_mlp;
-  double* gb1 = gW1 + H * n_in;
-  double* gW2 = gb1 + H;
-  double* gb2 = gW2 + 3 * H;
+  int nf = f->n_feat, na = f->n_ang, nsh = f->n_sh;
+  int n_in = orc_n_inputs(f, flags);
   /* sigmoid output */
   double dout[3];
   for (int c = 0; c < 3; ++c) dout[c] = dC[c] * st->C[c] * (1.0 - st->C[c]);
-  double dhid[MAXH];
-  for (int k = 0; k < H; ++k) {
-    double acc = 0.0;
-    for (int c = 0; c < 3; ++c) acc += W2[c * H + k] * dout[c];
-    dhid[k] = acc;
-  }
-  for (int c = 0; c < 3; ++c) {
-    add_atomic(&gb2[c], dout[c]);
-    for (int k = 0; k < H; ++k) add_atomic(&gW2[c * H + k], dout[c] * st->hid[k]);
-  }
-  /* ReLU: derivative 1 iff pre-activation > 0 */
-  double dpre[MAXH];
-  for (int k = 0; k < H; ++k) dpre[k] = st->pre1[k] > 0.0 ? dhid[k] : 0.0;
   double dz[MAXIN];
-  for (int j = 0; j < n_in; ++j) {
-    double acc = 0.0;
-    for (int k = 0; k < H; ++k) acc += W1[k * n_in + j] * dpre[k];
-    dz[j] = acc;
-  }
-  for (int k = 0; k < H; ++k) {
-    add_atomic(&gb1[k], dpre[k]);
-    for (int j = 0; j < n_in; ++j) add_atomic(&gW1[k * n_in + j], dpre[k] * st->z[j]);
-  }
+  mlp_backward(f->mlp, n_in, f->hidden, f->mlp_layers, st->z, st->pre, st->hid, dout, g_mlp,
+               dz);
   /* spatial features */
   if (!(flags & ORC_NO_FS)) scatter_tri(g_feat, f->R, nf, x, dz);
   /* probes: d/d b_ij = w_i Y_j dF_a */
@@ -431,15 +604,47 @@ static void shade_backward(const orc_field* f, int32_t flags, const double x[3],
       for (int a = 0; a < na; ++a) gb[j * na + a] = st->Y[j] * dz[nf + a];
     scatter_tri(g_probes, f->P, nsh * na, x, gb);
   }
-  /* incidence cosine -> normal -> SDF gradient stencil */
+  /* cotangent of the unit normal n */
+  int through_normal = 0;
+  double dn[3] = {0.0, 0.0, 0.0};
   if (!(flags & ORC_NV_ONE)) {
-    double c = st->c;
-    double dc = dz[nf + na] + 2.0 * c * dz[nf + na + 1] + 4.0 * c * c * c * dz[nf + na + 2];
+    const double* dzi = dz + nf + na;
+    double c = st->c, dc = 0.0;
+    if (flags & ORC_FRESNEL_PAPER) {
+      /* d/dc (1 - c)^m = -m (1 - c)^(m-1) */
+      double p = 1.0;
+      for (int m = 1; m < 6; ++m) {
+        dc -= m * p * dzi[m];
+        p *= 1.0 - c;
+      }
+    } else {
+      dc = dzi[0] + 2.0 * c * dzi[1] + 4.0 * c * c * c * dzi[2];
+    }
+    for (int a = 0; a < 3; ++a) dn[a] += dc * v[a];
+    through_normal = 1;
+  }
+  if ((flags & ORC_SH_REFLECT) && !(flags & ORC_NO_FA)) {
+    /* F_a,k = sum_j bhat_jk Y_j(r): dL/dr = sum_j (sum_k bhat_jk dF_a,k) grad Y_j(r);
+     * r = 2 (n.v) n - v: dL/dn = 2 (dL/dr . n) v + 2 (n.v) dL/dr */
+    double dY[3 * MAXSH], dr[3] = {0.0, 0.0, 0.0};
+    orc_sh_grad(nsh, st->arg, dY);
+    for (int j = 0; j < nsh; ++j) {
+      double e = 0.0;
+      for (int a = 0; a < na; ++a) e += st->bhat[j * na + a] * dz[nf + a];
+      for (int q = 0; q < 3; ++q) dr[q] += e * dY[3 * j + q];
+    }
+    double rn = dr[0] * st->n[0] + dr[1] * st->n[1] + dr[2] * st->n[2];
+    for (int a = 0; a < 3; ++a) dn[a] += 2.0 * rn * v[a] + 2.0 * st->c * dr[a];
+    through_normal = 1;
+  }
+  if (through_normal) {
+    /* n = g / max(|g|, 1e-30) */
     double dg[3];
     if (st->gn >= 1e-30) {
-      for (int a = 0; a < 3; ++a) dg[a] = dc * (v[a] - c * st->n[a]) / st->gn;
+      double nd = dn[0] * st->n[0] + dn[1] * st->n[1] + dn[2] * st->n[2];
+      for (int a = 0; a < 3; ++a) dg[a] = (dn[a] - nd * st->n[a]) / st->gn;
     } else {
-      for (int a = 0; a < 3; ++a) dg[a] = dc * v[a] / 1e-30;
+      for (int a = 0; a < 3; ++a) dg[a] = dn[a] / 1e-30;
     }
     double h = 2.0 / (double)(f->R - 1);
     for (int a = 0; a < 3; ++a) {
@@ -456,26 +661,35 @@ static void shade_backward(const orc_field* f, int32_t flags, const double x[3],
 
 static double sigm_neg(double tau, double s) { return 1.0 / (1.0 + exp(tau * s)); }
 
-void orc_render_backward(const orc_field* f, const orc_render_opts* opt, int64_t B,
-                         const double* rays_o, const double* rays_d, const double* dL_drgb,
-                         double* g_sdf, double* g_feat, double* g_probes, double* g_mlp) {
+int orc_render_backward(const orc_field* f, const orc_render_opts* opt, int64_t B,
+                        const double* rays_o, const double* rays_d, const double* dL_drgb,
+                        double* g_sdf, double* g_feat, double* g_probes, double* g_mlp) {
+  if (opt->n_samples < 2 || opt->n_samples > ORC_MAX_N) return -1;
+  if (orc_field_check(f, opt->flags)) return -1;
+  const int N = opt->n_samples;
+  int failed = 0;
 #pragma omp parallel
   {
-  ray_state* r = (ray_state*)malloc(sizeof(ray_state));
+  ray_state* r = ray_state_alloc(N);
   shade_state* st = (shade_state*)malloc(sizeof(shade_state));
-  double(*C)[3] = (double(*)[3])malloc(sizeof(double[MAXN][3]));
-  double* ds = (double*)malloc(sizeof(double[MAXN]));
+  double(*C)[3] = (double(*)[3])malloc((size_t)N * sizeof(double[3]));
+  double* ds = (double*)malloc((size_t)N * sizeof(double));
+  if (!r || !st || !C || !ds) {
+#pragma omp atomic write
+    failed = 1;
+  }
+#pragma omp barrier
+  if (!failed) {
 #pragma omp for schedule(dynamic, 16)
   for (int64_t b = 0; b < B; ++b) {
     const double* dL = dL_drgb + 3 * b;
     if (dL[0] == 0.0 && dL[1] == 0.0 && dL[2] == 0.0) continue;
-    for (int i = 0; i < opt->n_samples; ++i) {
+    for (int i = 0; i < N; ++i) {
       ds[i] = 0.0;
       C[i][0] = C[i][1] = C[i][2] = 0.0;
     }
     march(f, opt, rays_o + 3 * b, rays_d + 3 * b, r);
     if (r->hit) {
-      int N = r->N;
       for (int i = 0; i < N; ++i) {
         if (!(r->alpha[i] > 0.0)) continue;
         orc_shade(f, opt->flags, r->x[i], r->v, C[i], NULL);
@@ -504,11 +718,13 @@ void orc_render_backward(const orc_field* f, const orc_render_opts* opt, int64_t
         if (ds[i] != 0.0) scatter_tri(g_sdf, f->R, 1, r->x[i], &ds[i]);
     }
   }
+  }
   free(ds);
   free(C);
   free(st);
   free(r);
   }
+  return failed ? -1 : 0;
 }
 
 /* ---------------------------------------------------------------------------
@@ -645,11 +861,12 @@ void orc_grid_step(int R, int P, int n_feat, int n_pc, int n_mlp, double* sdf, d
  * pixel_ids index views x H x W (v*H*W + py*W + px).  margin = closest
  * approach of a decision to its threshold (|s - eps|, |t - t_f|).
  * ------------------------------------------------------------------------- */
-void orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max_steps,
-                      int32_t V, const double* cams, int32_t W, int32_t H,
-                      const int64_t* pixel_ids, int64_t n_pix, double* out, double* t_hit,
-                      int32_t* steps, double* margin) {
+int orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max_steps,
+                     int32_t V, const double* cams, int32_t W, int32_t H,
+                     const int64_t* pixel_ids, int64_t n_pix, double* out, double* t_hit,
+                     int32_t* steps, double* margin) {
   (void)V;
+  if (orc_field_check(f, flags)) return -1;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t q = 0; q < n_pix; ++q) {
     int64_t id = pixel_ids[q];
@@ -695,4 +912,5 @@ void orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max
     if (steps) steps[q] = k;
     if (margin) margin[q] = mg;
   }
+  return 0;
 }

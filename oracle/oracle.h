@@ -29,16 +29,19 @@ typedef struct {
   int32_t n_sh;         /* SH coefficients per probe: 1, 4, 9, 16 */
   int32_t n_ang;        /* angular feature channels n_a */
   int32_t hidden;       /* MLP hidden width */
+  int32_t mlp_layers;   /* hidden layers: 1, or 2 (Sec. 4) */
   const double* sdf;    /* [R][R][R] */
   const double* feat;   /* [R][R][R][n_feat] */
   const double* probes; /* [P][P][P][n_sh][n_ang] */
-  const double* mlp;    /* W1[hidden][n_in], b1[hidden], W2[3][hidden], b2[3] */
+  const double* mlp;    /* per hidden layer W_l[hidden][n_prev], b_l[hidden]; Wo[3][hidden], bo[3] */
 } orc_field;
 
 /* flags */
 #define ORC_NO_FS 1       /* F_s := 0 (visual ablation, Fig. "MLP components") */
 #define ORC_NO_FA 2       /* F_a := 0 */
-#define ORC_NV_ONE 4      /* n.v := 1 (Fresnel ablation, Table "Ablation") */
+#define ORC_NV_ONE 4      /* n.v := 1 in the incidence inputs (Fresnel ablation, Table "Ablation") */
+#define ORC_SH_REFLECT 8  /* SH evaluated at the reflected vector r (Sec. 3.1, Fig. overview) */
+#define ORC_FRESNEL_PAPER 16 /* incidence inputs (1-n.v)^0..5 (Eq. newparametrization) */
 
 typedef struct {
   int32_t n_samples;    /* N */
@@ -60,22 +63,28 @@ void orc_tri_corners(int R, const double x[3], int64_t idx[8], double w[8]);
 void orc_sdf_gradient(const double* sdf, int R, const double x[3], double g[3]);
 int orc_sh_basis(int n_sh, const double v[3], double* Y);
 double orc_logsigmoid(double x);
-void orc_mlp_forward(const double* mlp, int n_in, int hidden, const double* z,
-                     double* pre1, double* hid, double out[3], double C[3]);
+int orc_sh_grad(int n_sh, const double v[3], double* dY);
+int64_t orc_mlp_size(int n_in, int hidden, int layers);
+void orc_mlp_forward(const double* mlp, int n_in, int hidden, int layers, const double* z,
+                     double* pre, double* hid, double out[3], double C[3]);
+int orc_n_inputs(const orc_field* f, int32_t flags);
+int orc_field_check(const orc_field* f, int32_t flags);
 double orc_composite(int N, const double* s, const int32_t* active, double tau,
                      double* alpha, double* T, double* w);
 void orc_shade(const orc_field* f, int32_t flags, const double x[3], const double v[3],
                double C[3], double* z_out);
 
 /* ---- the render step ---- */
-void orc_render_forward(const orc_field* f, const orc_render_opts* opt, int64_t B,
-                        const double* rays_o, const double* rays_d, double* rgb,
-                        double* aux, double* depth_wsum, double* margin,
-                        int32_t* n_shaded);
-void orc_render_backward(const orc_field* f, const orc_render_opts* opt, int64_t B,
-                         const double* rays_o, const double* rays_d,
-                         const double* dL_drgb, double* g_sdf, double* g_feat,
-                         double* g_probes, double* g_mlp);
+/* the render entry points return 0, or -1 for N outside [2, 2^20], a field
+ * shape outside the supported set, or an allocation failure */
+int orc_render_forward(const orc_field* f, const orc_render_opts* opt, int64_t B,
+                       const double* rays_o, const double* rays_d, double* rgb,
+                       double* aux, double* depth_wsum, double* margin,
+                       int32_t* n_shaded);
+int orc_render_backward(const orc_field* f, const orc_render_opts* opt, int64_t B,
+                        const double* rays_o, const double* rays_d,
+                        const double* dL_drgb, double* g_sdf, double* g_feat,
+                        double* g_probes, double* g_mlp);
 double orc_l1_loss(int64_t B, const double* rgb, const double* target, double* dL_drgb);
 void orc_regularizers(int R, int P, int n_feat, int n_pc, const double* sdf,
                       const double* feat, const double* probes, double lambda_eik,
@@ -87,10 +96,10 @@ void orc_grid_step(int R, int P, int n_feat, int n_pc, int n_mlp, double* sdf, d
                    double* probes, double* mlp, const double* g_sdf, const double* g_feat,
                    const double* g_probes, const double* g_mlp, double* m, double* v,
                    int64_t step, const orc_step_opts* opt, double losses[3]);
-void orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max_steps,
-                      int32_t V, const double* cams, int32_t W, int32_t H,
-                      const int64_t* pixel_ids, int64_t n_pix, double* out, double* t_hit,
-                      int32_t* steps, double* margin);
+int orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max_steps,
+                     int32_t V, const double* cams, int32_t W, int32_t H,
+                     const int64_t* pixel_ids, int64_t n_pix, double* out, double* t_hit,
+                     int32_t* steps, double* margin);
 
 #ifdef __cplusplus
 }

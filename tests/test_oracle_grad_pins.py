@@ -16,33 +16,59 @@ import workloads as wl
 RNG = np.random.default_rng(77)
 
 
-def _tiny_scene(seed=11, R=6, P=3, n_sh=9):
-    f = wl.random_field(seed, R, P, n_sh=n_sh)
+def _bias_slices(n_in, hidden, layers):
+    """index ranges of the biases in the packed MLP"""
+    out, off = [], 0
+    for l in range(layers):
+        off += hidden * (n_in if l == 0 else hidden)
+        out.append((off, off + hidden))
+        off += hidden
+    off += 3 * hidden
+    out.append((off, off + 3))
+    return out
+
+
+def _tiny_scene(seed=11, R=6, P=3, n_sh=9, model="workload"):
+    f = wl.random_field(seed, R, P, n_sh=n_sh, model=model)
     rng = np.random.default_rng(seed + 1)
     sdf = f.sdf.astype(np.float64) + 0.05 * rng.standard_normal(f.sdf.shape)
     mlp = f.mlp.astype(np.float64)
-    mlp[160:176] = 0.05 * rng.standard_normal(16)
-    mlp[224:227] = 0.05 * rng.standard_normal(3)
+    n_in = wl.N_IN if model == "workload" else wl.PAPER_N_IN
+    for lo, hi in _bias_slices(n_in, f.hidden, f.layers):
+        mlp[lo:hi] = 0.05 * rng.standard_normal(hi - lo)
     cams = wl.fibonacci_cameras(8, 4, 2)
     o, d = wl.camera_rays(cams, 4, 2)
     sel = rng.choice(o.shape[0], 8, replace=False)
     return (sdf, f.feat.astype(np.float64), f.probes.astype(np.float64), mlp,
-            o[sel].astype(np.float64), d[sel].astype(np.float64))
+            o[sel].astype(np.float64), d[sel].astype(np.float64), f.hidden, f.layers)
 
 
-def _objective(params, o, d, r, N, tau, skip, flags=0):
-    of = oracle.make_field(*params)
+def _objective(params, o, d, r, N, tau, skip, flags=0, hidden=16, layers=1):
+    of = oracle.make_field(*params, hidden=hidden, layers=layers)
     out = oracle.render_forward(of, o, d, N, tau=tau, skip_voxels=skip, flags=flags)
     return float(np.sum(out["rgb"] * r))
 
 
-@pytest.mark.parametrize("skip,flags,tau", [(0.0, 0, 8.0), (3.0, 0, 8.0), (0.0, oracle.NV_ONE, 5.0)])
-def test_p10_backward_matches_finite_differences(skip, flags, tau):
-    sdf, feat, probes, mlp, o, d = _tiny_scene()
+P10_CASES = [
+    (0.0, 0, 8.0, "workload", 9),
+    (3.0, 0, 8.0, "workload", 9),
+    (0.0, oracle.NV_ONE, 5.0, "workload", 9),
+    # reflected-vector SH (Sec. 3.1-3.2), alone and with the incidence input ablated
+    (0.0, oracle.SH_REFLECT, 8.0, "workload", 9),
+    (0.0, oracle.SH_REFLECT | oracle.NV_ONE, 8.0, "workload", 16),
+    # the paper's colour model: r, (1 - n.v)^0..5, two hidden layers of 32 (Sec. 4)
+    (0.0, oracle.SH_REFLECT | oracle.FRESNEL_PAPER, 8.0, "paper", 16),
+    (3.0, oracle.FRESNEL_PAPER, 8.0, "paper", 4),
+]
+
+
+@pytest.mark.parametrize("skip,flags,tau,model,n_sh", P10_CASES)
+def test_p10_backward_matches_finite_differences(skip, flags, tau, model, n_sh):
+    sdf, feat, probes, mlp, o, d, hidden, layers = _tiny_scene(n_sh=n_sh, model=model)
     N = 8
     r = RNG.standard_normal((o.shape[0], 3))
     params = [sdf, feat, probes, mlp]
-    of = oracle.make_field(*params)
+    of = oracle.make_field(*params, hidden=hidden, layers=layers)
     fwd = oracle.render_forward(of, o, d, N, tau=tau, skip_voxels=skip, flags=flags)
     assert np.count_nonzero(fwd["n_shaded"]) >= 4
     g = oracle.render_backward(of, o, d, r, N, tau=tau, skip_voxels=skip, flags=flags)
@@ -56,9 +82,9 @@ def test_p10_backward_matches_finite_differences(skip, flags, tau):
         for q in range(flat.size):
             keep = flat[q]
             flat[q] = keep + eps
-            jp = _objective(params, o, d, r, N, tau, skip, flags)
+            jp = _objective(params, o, d, r, N, tau, skip, flags, hidden, layers)
             flat[q] = keep - eps
-            jm = _objective(params, o, d, r, N, tau, skip, flags)
+            jm = _objective(params, o, d, r, N, tau, skip, flags, hidden, layers)
             flat[q] = keep
             fd = (jp - jm) / (2 * eps)
             err = abs(fd - gflat[q]) / scale
@@ -68,7 +94,7 @@ def test_p10_backward_matches_finite_differences(skip, flags, tau):
 
 
 def test_p10_gradients_accumulate():
-    sdf, feat, probes, mlp, o, d = _tiny_scene(seed=3)
+    sdf, feat, probes, mlp, o, d, _, _ = _tiny_scene(seed=3)
     of = oracle.make_field(sdf, feat, probes, mlp)
     r = RNG.standard_normal((o.shape[0], 3))
     g1 = oracle.render_backward(of, o, d, r, 8, tau=8.0)

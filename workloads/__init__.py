@@ -16,7 +16,8 @@ Conventions shared by every array:
     flat index (k*R + j)*R + i;
   * spatial features  feat[R][R][R][n_feat];
   * probes            probes[P][P][P][n_sh][n_ang];
-  * MLP               W1[hidden][n_in] row-major, b1[hidden], W2[3][hidden], b2[3].
+  * MLP               per hidden layer W_l[hidden][n_prev] row-major and b_l[hidden],
+                      then Wo[3][hidden], bo[3] (one hidden layer: W1, b1, W2, b2).
 """
 from __future__ import annotations
 
@@ -32,8 +33,18 @@ N_OUT = 3
 N_IN = N_FEAT + N_ANG + 3  # F_s, F_a, (c, c^2, c^4)
 
 
-def mlp_size(n_in: int = N_IN, hidden: int = HIDDEN, n_out: int = N_OUT) -> int:
-    return hidden * n_in + hidden + n_out * hidden + n_out
+# the paper's own colour model (Sec. 3.1 Eq. newparametrization, Sec. 4): incidence
+# inputs (1 - n.v)^0..5 and two hidden layers of 32
+PAPER_N_IN = N_FEAT + N_ANG + 6
+PAPER_HIDDEN = 32
+PAPER_LAYERS = 2
+
+
+def mlp_size(n_in: int = N_IN, hidden: int = HIDDEN, n_out: int = N_OUT, layers: int = 1) -> int:
+    n = 0
+    for l in range(layers):
+        n += hidden * (n_in if l == 0 else hidden) + hidden
+    return n + n_out * hidden + n_out
 
 
 # ----------------------------------------------------------------------------
@@ -141,15 +152,19 @@ def torus_sdf_nodes(R: int, major: float = 0.5, minor: float = 0.2) -> np.ndarra
 
 
 def xavier_uniform_mlp(rng: np.random.Generator, n_in: int = N_IN, hidden: int = HIDDEN,
-                       n_out: int = N_OUT) -> np.ndarray:
-    """Packed [W1 (hidden x n_in), b1, W2 (n_out x hidden), b2], Xavier-uniform
-    weights (bound sqrt(6/(fan_in+fan_out))), zero biases."""
-    a1 = math.sqrt(6.0 / (n_in + hidden))
-    a2 = math.sqrt(6.0 / (hidden + n_out))
-    w1 = rng.uniform(-a1, a1, size=(hidden, n_in))
-    w2 = rng.uniform(-a2, a2, size=(n_out, hidden))
-    return np.concatenate([w1.reshape(-1), np.zeros(hidden), w2.reshape(-1),
-                           np.zeros(n_out)]).astype(np.float32)
+                       n_out: int = N_OUT, layers: int = 1) -> np.ndarray:
+    """Packed [W_1 (hidden x n_in), b_1, ..., W_L (hidden x hidden), b_L, Wo (n_out x
+    hidden), bo], Xavier-uniform weights (bound sqrt(6/(fan_in+fan_out))), zero
+    biases; the matrices are drawn in that order."""
+    parts = []
+    fan = n_in
+    for _ in range(layers):
+        a = math.sqrt(6.0 / (fan + hidden))
+        parts += [rng.uniform(-a, a, size=(hidden, fan)).reshape(-1), np.zeros(hidden)]
+        fan = hidden
+    a = math.sqrt(6.0 / (hidden + n_out))
+    parts += [rng.uniform(-a, a, size=(n_out, hidden)).reshape(-1), np.zeros(n_out)]
+    return np.concatenate(parts).astype(np.float32)
 
 
 @dataclass
@@ -164,22 +179,34 @@ class Field:
     probes: np.ndarray   # (P, P, P, n_sh, n_ang)
     mlp: np.ndarray      # (mlp_size,)
     extra: dict = field(default_factory=dict)
+    hidden: int = HIDDEN
+    layers: int = 1
 
 
 def random_field(seed: int, R: int, P: int, n_sh: int = 9, shape: str = "sphere",
-                 std: float = 0.1) -> Field:
-    """Draw order (seed -> PCG64): features, probes, W1, W2 (biases are zero)."""
+                 std: float = 0.1, model: str = "workload") -> Field:
+    """Draw order (seed -> PCG64): features, probes, then the MLP matrices (biases
+    are zero).  model "workload": 10 -> 16 -> 3 (inputs F_s, F_a, c, c^2, c^4);
+    "paper": 13 -> 32 -> 32 -> 3 (inputs F_s, F_a, (1 - n.v)^0..5)."""
     rng = np.random.default_rng(seed)
     feat = (rng.standard_normal((R, R, R, N_FEAT), dtype=np.float32) * np.float32(std))
     probes = (rng.standard_normal((P, P, P, n_sh, N_ANG), dtype=np.float32) * np.float32(std))
-    mlp = xavier_uniform_mlp(rng)
+    if model == "workload":
+        hidden, layers = HIDDEN, 1
+        mlp = xavier_uniform_mlp(rng)
+    elif model == "paper":
+        hidden, layers = PAPER_HIDDEN, PAPER_LAYERS
+        mlp = xavier_uniform_mlp(rng, PAPER_N_IN, hidden, N_OUT, layers)
+    else:
+        raise ValueError(model)
     if shape == "sphere":
         sdf = sphere_sdf_nodes(R)
     elif shape == "torus":
         sdf = torus_sdf_nodes(R)
     else:
         raise ValueError(shape)
-    return Field(R=R, P=P, n_sh=n_sh, sdf=sdf, feat=feat, probes=probes, mlp=mlp)
+    return Field(R=R, P=P, n_sh=n_sh, sdf=sdf, feat=feat, probes=probes, mlp=mlp, hidden=hidden,
+                 layers=layers)
 
 
 def round_half(a: np.ndarray) -> np.ndarray:
