@@ -38,7 +38,9 @@
  *   memory owned by the caller; descriptor structs are host memory read during
  *   the call only.  Calls enqueue work on `stream` (a hipStream_t; NULL = the
  *   null stream) and return without synchronising.  The library allocates no
- *   device memory and keeps no per-call state.  Gradient buffers are
+ *   device memory and keeps no per-call state; its one piece of device memory,
+ *   the static scratch of psdf_render_backward_noalloc, is reset by each call of
+ *   that entry point before use.  Gradient buffers are
  *   accumulated into (+=); the caller zeroes them, or psdf_grid_step does.
  *
  * Errors
@@ -187,6 +189,31 @@ int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, 
                          const float* rays_o, const float* rays_d, const float* aux,
                          const float* dL_drgb, const psdf_grads* grads, void* workspace,
                          int64_t workspace_bytes, int32_t flags, void* stream);
+
+/*
+ * psdf_render_backward_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): psdf_render_backward with flags = 0 and, as its workspace, a
+ * static device array of the library of PSDF_NOALLOC_SCRATCH_BYTES (128 MiB),
+ * so the call allocates nothing (no hipMalloc, no hipFree, no allocating library
+ * routine).  Same arguments, results and accumulation (+=) as
+ * psdf_render_backward; waves of 64 rays whose shaded samples do not fit the
+ * scratch (about 360 000 samples at P = 128 beside the fixed part) run the
+ * fused schedule, so any batch gives the same gradients.
+ *   Limit: the fixed part of the workspace (12 bytes per 64 rays, about 12
+ *   bytes per probe cell of the P^3 grid, 3.6 MiB of MLP partials) must fit
+ *   the scratch; larger B or P return PSDF_EINVAL with a message.
+ *   Each GPU holds its own copy of the scratch from the first call made with
+ *   that device current until the process ends; the call uses the copy of the
+ *   current device.  Every call on one GPU shares that copy, and each call
+ *   resets the counters it relies on before use: calls that overlap on one
+ *   GPU (other streams, other host threads) race and give wrong gradients.
+ */
+#define PSDF_NOALLOC_SCRATCH_BYTES 134217728
+
+int psdf_render_backward_noalloc(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
+                                 const float* rays_o, const float* rays_d, const float* aux,
+                                 const float* dL_drgb, const psdf_grads* grads, void* stream);
 
 /* Bytes of a backward workspace (or forward tape) for B rays and a P^3 probe
  * grid with room for `max_samples` shaded samples (288 bytes each, plus 12

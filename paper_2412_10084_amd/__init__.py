@@ -24,9 +24,10 @@ BRICK = 8
 
 N_FEAT, N_ANG, HIDDEN, N_MLP = 3, 4, 16, 227
 
-EXPORTS = ("psdf_render_forward", "psdf_render_backward", "psdf_l1_loss", "psdf_grid_step",
-           "psdf_render_sphere_trace", "psdf_sdf_bounds", "psdf_backward_workspace_bytes",
-           "psdf_last_error", "psdf_abi_version")
+EXPORTS = ("psdf_render_forward", "psdf_render_backward", "psdf_render_backward_noalloc",
+           "psdf_l1_loss", "psdf_grid_step", "psdf_render_sphere_trace", "psdf_sdf_bounds",
+           "psdf_backward_workspace_bytes", "psdf_last_error", "psdf_abi_version")
+NOALLOC_SCRATCH_BYTES = 134217728
 
 
 class PsdfError(RuntimeError):
@@ -87,6 +88,7 @@ def lib():
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
         L.psdf_render_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i64, vp]
         L.psdf_render_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i64, i32, vp]
+        L.psdf_render_backward_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.psdf_backward_workspace_bytes.argtypes = [i64, i32, i64]
         L.psdf_l1_loss.argtypes = [i64, vp, vp, vp, vp, vp]
         L.psdf_grid_step.argtypes = [vp, vp]
@@ -232,6 +234,19 @@ def render_backward(field: Field, opts: RenderOpts, rays_o, rays_d, aux, dL_drgb
                                       _ptr(rays_d), _ptr(aux), _ptr(dL_drgb), C.byref(g),
                                       _ptr(workspace), _nbytes(workspace),
                                       BWD_FROM_TAPE if from_tape else 0, _stream(stream)))
+
+
+def render_backward_noalloc(field: Field, opts: RenderOpts, rays_o, rays_d, aux, dL_drgb,
+                            grads: dict, stream=None) -> None:
+    """render_backward with the entry-parallel schedule over the library's static
+    device scratch (NOALLOC_SCRATCH_BYTES): no workspace argument, no allocation.
+    Calls on one GPU share the scratch and must not overlap."""
+    fs, op = field.cstruct(), opts.cstruct()
+    g = _Grads(_ptr(grads.get("sdf")), _ptr(grads.get("feat")), _ptr(grads.get("probes")),
+               _ptr(grads.get("mlp")))
+    _check(lib().psdf_render_backward_noalloc(C.byref(fs), C.byref(op), rays_o.shape[0],
+                                              _ptr(rays_o), _ptr(rays_d), _ptr(aux),
+                                              _ptr(dL_drgb), C.byref(g), _stream(stream)))
 
 
 def l1_loss(rgb, target, dL_drgb, loss=None, stream=None) -> None:

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/probesdf.h"
 #include "kernels.h"
@@ -115,6 +116,41 @@ const int64_t kMaxRays = (int64_t)1 << 31;
 
 }  // namespace
 
+// Device scratch of psdf_render_backward_noalloc: a workspace of the
+// entry-parallel backward that no call allocates.  Every GPU the library runs on
+// holds its own copy until the process ends; all calls on one GPU share it.  In
+// host code `scratch` names a host-side stand-in, not the device array: kernels
+// and copies only ever see the device address taken below.
+__device__ __align__(256) unsigned char scratch[PSDF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current and kept for later calls.
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(PSDF_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PSDF_EHIP, "device id %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PSDF_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return PSDF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int psdf_abi_version(void) { return PSDF_ABI_VERSION; }
@@ -165,28 +201,39 @@ int64_t psdf_backward_workspace_bytes(int64_t B, int32_t P, int64_t max_samples)
   return psdf::bwd_ws_bytes(B, P, max_samples);
 }
 
-int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
+// Host-side validation shared by the backward entry points; fills `a`.
+static int prep_backward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
                          const float* rays_o, const float* rays_d, const float* aux,
-                         const float* dL_drgb, const psdf_grads* grads, void* workspace,
-                         int64_t workspace_bytes, int32_t flags, void* stream) {
+                         const float* dL_drgb, const psdf_grads* grads, psdf::RenderArgs& a) {
   int rc;
   if ((rc = check_field(field)) || (rc = check_opts(opts))) return rc;
   if (B < 0 || B > kMaxRays) return fail(PSDF_EINVAL, "B=%lld out of range", (long long)B);
   if (!grads) return fail(PSDF_EINVAL, "grads is NULL");
-  if (B == 0) return ok();
+  if (B == 0) return PSDF_OK;
   if ((rc = check_f32(rays_o, "rays_o")) || (rc = check_f32(rays_d, "rays_d")) ||
       (rc = check_f32(aux, "aux")) || (rc = check_f32(dL_drgb, "dL_drgb")))
     return rc;
   const float* gp[4] = {grads->sdf, grads->feat, grads->probes, grads->mlp};
   for (const float* p : gp)
     if (p && !aligned(p, 4)) return fail(PSDF_EALIGN, "gradient buffer misaligned");
-  psdf::RenderArgs a = render_args(field, opts, B, rays_o, rays_d);
+  a = render_args(field, opts, B, rays_o, rays_d);
   a.aux_in = aux;
   a.dL = dL_drgb;
   a.g_sdf = grads->sdf;
   a.g_feat = grads->feat;
   a.g_probes = grads->probes;
   a.g_mlp = grads->mlp;
+  return PSDF_OK;
+}
+
+int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
+                         const float* rays_o, const float* rays_d, const float* aux,
+                         const float* dL_drgb, const psdf_grads* grads, void* workspace,
+                         int64_t workspace_bytes, int32_t flags, void* stream) {
+  int rc;
+  psdf::RenderArgs a{};
+  if ((rc = prep_backward(field, opts, B, rays_o, rays_d, aux, dL_drgb, grads, a))) return rc;
+  if (B == 0) return ok();
   if (flags & ~PSDF_BWD_FROM_TAPE) return fail(PSDF_EINVAL, "unknown backward flags 0x%x", flags);
   if ((flags & PSDF_BWD_FROM_TAPE) && !workspace)
     return fail(PSDF_EINVAL, "PSDF_BWD_FROM_TAPE needs the workspace the forward recorded");
@@ -204,6 +251,30 @@ int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, 
                                                  field->mlp_dtype, field->sh_coeffs,
                                                  static_cast<hipStream_t>(stream)),
                     "render_backward launch");
+}
+
+int psdf_render_backward_noalloc(const psdf_field* field, const psdf_render_opts* opts, int64_t B,
+                                 const float* rays_o, const float* rays_d, const float* aux,
+                                 const float* dL_drgb, const psdf_grads* grads, void* stream) {
+  int rc;
+  psdf::RenderArgs a{};
+  if ((rc = prep_backward(field, opts, B, rays_o, rays_d, aux, dL_drgb, grads, a))) return rc;
+  if (B == 0) return ok();
+  const int64_t need = psdf::bwd_ws_bytes(B, field->P, 0);
+  if (need > (int64_t)PSDF_NOALLOC_SCRATCH_BYTES)
+    return fail(PSDF_EINVAL,
+                "B=%lld, P=%d need %lld bytes of fixed workspace, more than the %lld-byte static "
+                "scratch of psdf_render_backward_noalloc (use psdf_render_backward with a "
+                "workspace)",
+                (long long)B, field->P, (long long)need, (long long)PSDF_NOALLOC_SCRATCH_BYTES);
+  void* base = nullptr;
+  if ((rc = scratch_of_current_device(&base))) return rc;
+  const psdf::BwdWs ws = psdf::bwd_ws_carve(base, B, field->P, PSDF_NOALLOC_SCRATCH_BYTES);
+  return hip_status(psdf::launch_render_backward_split(a, ws, false, field->sdf_dtype,
+                                                       field->feat_dtype, field->mlp_dtype,
+                                                       field->sh_coeffs,
+                                                       static_cast<hipStream_t>(stream)),
+                    "render_backward_noalloc launch");
 }
 
 int psdf_l1_loss(int64_t B, const float* rgb, const float* target, float* dL_drgb, float* loss,

@@ -196,3 +196,28 @@ def test_grid_step_bounds_alignment():
     a = _step_args()
     a.sdf_bounds_out = a.sdf_bounds_out + 4
     assert L.psdf_grid_step(C.byref(a), None) == ps.EALIGN
+
+
+def test_backward_noalloc_validation():
+    """The allocation-free backward validates like render_backward and rejects
+    batches whose fixed workspace part exceeds its static scratch, before any
+    HIP call."""
+    L = ps.lib()
+    g = ps._Grads(FAKE, FAKE, FAKE, FAKE)
+    fn = L.psdf_render_backward_noalloc
+    assert fn(C.byref(_field()), C.byref(_opts()), 0, FAKE, FAKE, FAKE, FAKE, C.byref(g),
+              None) == ps.OK
+    assert fn(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, FAKE, FAKE, None,
+              None) == ps.EINVAL
+    assert fn(C.byref(_field()), C.byref(_opts()), 10, FAKE, FAKE, None, FAKE, C.byref(g),
+              None) == ps.EINVAL
+    assert fn(None, C.byref(_opts()), 10, FAKE, FAKE, FAKE, FAKE, C.byref(g), None) == ps.EINVAL
+    # P = 256: the probe-cell bins alone (3 x 4 B x 8 x 128^3) exceed 128 MiB
+    assert fn(C.byref(_field(P=256)), C.byref(_opts()), 10, FAKE, FAKE, FAKE, FAKE, C.byref(g),
+              None) == ps.EINVAL
+    assert "static scratch" in ps.last_error()
+    # 2^31 rays: the per-wave arrays alone (3 x 4 B x 2^25) exceed it
+    assert fn(C.byref(_field()), C.byref(_opts()), 1 << 31, FAKE, FAKE, FAKE, FAKE, C.byref(g),
+              None) == ps.EINVAL
+    assert "static scratch" in ps.last_error()
+    assert ps.backward_workspace_bytes(1 << 20, 128, 0) < ps.NOALLOC_SCRATCH_BYTES
