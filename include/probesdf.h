@@ -26,6 +26,8 @@
  *     probes  [P][P][P][sh_coeffs][n_ang]    FP32 or FP16   (b_ij)
  *     mlp     W1[hidden][n_in] row-major, b1[hidden], W2[3][hidden], b2[3],
  *             FP32, n_in = n_feat + n_ang + 3; MLP input z = [F_s, F_a, c, c^2, c^4]
+ *             (the workload colour model; the paper's own is described at
+ *             psdf_field)
  *             with c = n.v (v = -ray direction), hidden ReLU, sigmoid output.
  *   Rays: origins and directions [B][3] FP32 (directions need not be unit).
  *   Per ray: interval [t_n, t_f] = ray / cube intersection (t >= 0); N samples
@@ -62,7 +64,7 @@
 extern "C" {
 #endif
 
-#define PSDF_ABI_VERSION 3
+#define PSDF_ABI_VERSION 4
 
 #define PSDF_OK 0
 #define PSDF_EINVAL (-1)       /* null pointer, bad size or shape, aliasing */
@@ -72,16 +74,42 @@ extern "C" {
 
 typedef enum { PSDF_F32 = 0, PSDF_F16 = 1, PSDF_BF16 = 2 } psdf_dtype;
 
-/* render flags (ablations of the colour model, Sec. 5 "Ablations") */
+/* render flags: ablations of the colour model (Sec. 5 "Ablations") and the
+ * paper's own form of its inputs */
 #define PSDF_FLAG_NO_FS 1  /* F_s := 0 */
 #define PSDF_FLAG_NO_FA 2  /* F_a := 0 */
-#define PSDF_FLAG_NV_ONE 4 /* n.v := 1 (no incidence dependence) */
+#define PSDF_FLAG_NV_ONE 4 /* n.v := 1 in the incidence inputs (no incidence dependence) */
+/* SH evaluated at the reflection of v about the normal, r = 2 (n.v) n - v
+ * (Sec. 3.1 Eq. newparametrization, Sec. 3.2), instead of at v */
+#define PSDF_FLAG_SH_REFLECT 8
+/* incidence inputs (1 - n.v)^0 .. (1 - n.v)^5 (Eq. newparametrization) instead of
+ * (n.v, (n.v)^2, (n.v)^4); the MLP then has n_in = n_feat + n_ang + 6 inputs */
+#define PSDF_FLAG_FRESNEL_PAPER 16
+
+/* Most samples per ray of the paper colour model's kernels, which hold a ray's
+ * shaded samples in LDS. */
+#define PSDF_MODEL_MAX_SAMPLES 513
 
 /*
  * The scene parameters (Sec. 3.4: raw SDF values, spatial features, probe
  * coefficients and MLP weights).  Supported shapes: n_feat = 3, n_ang = 4,
- * mlp_hidden = 16, sh_coeffs in {1, 4, 9, 16}, 2 <= R, P <= 1024 with
- * R^3 * n_feat and P^3 * sh_coeffs * n_ang below 2^31.
+ * sh_coeffs in {1, 4, 9, 16}, 2 <= R, P <= 1024 with R^3 * n_feat and
+ * P^3 * sh_coeffs * n_ang below 2^31, and an MLP of (mlp_layers, mlp_hidden) =
+ * (1, 16) or (2, 32) hidden layers (Sec. 4 uses two of 32).
+ *
+ * Colour models.  The workload model -- one hidden layer of 16, SH at v, inputs
+ * (c, c^2, c^4) -- runs on the kernels described at each entry point.  The
+ * paper's own model -- any of PSDF_FLAG_SH_REFLECT, PSDF_FLAG_FRESNEL_PAPER or
+ * two hidden layers of 32 -- runs on kernels that take one ray per wave and one
+ * sample per lane, with these limits (else PSDF_EUNSUPPORTED): FP32 sdf;
+ * FP32 features with the FP32 MLP, or FP16 features with the FP16 / BF16 MLP;
+ * sh_coeffs 9 or 16; n_samples <= PSDF_MODEL_MAX_SAMPLES; no sphere tracing.
+ * Its forward records no tape, and its backward re-marches (a workspace or
+ * PSDF_BWD_FROM_TAPE is accepted and left unused).
+ * MLP packing for n_in inputs (n_in = n_feat + n_ang + 3, or + 6 with
+ * PSDF_FLAG_FRESNEL_PAPER), hidden width H, L hidden layers: W_0[H][n_in],
+ * b_0[H], (W_1[H][H], b_1[H] if L = 2), W_o[3][H], b_o[3]; psdf_grads.mlp has
+ * the same size.
  * Dtypes: sdf_dtype F32 | F16, feat_dtype F32 | F16 (features and probes),
  * mlp_dtype F32 | F16 | BF16 (the precision the MLP computes in; weights are
  * always passed FP32 and rounded to nearest-even on use).
@@ -118,6 +146,7 @@ typedef struct psdf_field {
   const void* probes;
   const float* mlp;
   const float* sdf_bounds; /* nullable, see above */
+  int32_t mlp_layers;      /* hidden layers of the MLP: 1 (mlp_hidden 16) or 2 (mlp_hidden 32) */
 } psdf_field;
 
 typedef struct psdf_render_opts {
@@ -160,10 +189,18 @@ int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, i
  * field, opts and rays: given dL/drgb [B][3] and the forward's aux [B][4], ADDS
  * dL/d(sdf, feat, probes, mlp) into `grads` (Sec. 3.3: the SDF and appearance
  * are optimised by back-propagating the colour loss through the rendering
- * equation).  The march is recomputed; nothing is stored by the forward.
- * Gradients accumulate with FP32 atomics, so the summation order (and the last
- * bits) varies from run to run.  Gradients are defined with respect to the
- * values the forward reads (FP16 storage: the rounded values).
+ * equation).  Without PSDF_BWD_FROM_TAPE the march is recomputed; with it the
+ * backward reads the samples the forward recorded in the workspace.
+ * Gradients are summed in FP32: global FP32 atomics, and in the taped
+ * schedule's SDF / feature box pass LDS boxes of 32-bit fixed point per batch of
+ * up to 64 samples (scale 2^30 / (64 B), B the batch's largest contribution of
+ * one sample to one node, so each add is within B / 2^25 of its FP32 value; a
+ * batch with a non-finite or huge B, or with samples at the grid boundary, adds
+ * in FP32).  The summation order (and the last bits) varies from run to run.
+ * The single-kernel schedule forms the colour remaining after sample i as the
+ * forward's rgb minus the colours before i, clamped to its exact range [0, T_i].
+ * Gradients are defined with respect to the values the forward reads (FP16
+ * storage: the rounded values).
  *   workspace, workspace_bytes: optional device buffer (256-byte aligned, at
  *     least psdf_backward_workspace_bytes(B, P, 0) bytes) for the
  *     entry-parallel schedule: a march pass writes the shaded samples there

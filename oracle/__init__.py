@@ -116,15 +116,22 @@ def make_field(sdf, feat, probes, mlp, n_sh=None, hidden=16, layers=1) -> OField
                   n_feat=n_feat, n_ang=n_ang, hidden=hidden, layers=layers)
 
 
-def field_from(fld, half: bool = False, half_sdf: bool = False) -> OField:
+def field_from(fld, half: bool = False, half_sdf: bool = False, mlp_round: str = "",
+               flags: int = 0) -> OField:
     """OField from a workloads.Field; `half` rounds features and probes to
-    float16 first (the values an FP16-storage path reads)."""
-    feat, probes, sdf = fld.feat, fld.probes, fld.sdf
+    float16 first (the values an FP16-storage path reads); `mlp_round` ("f16" or
+    "bf16") rounds the MLP weights (not the biases), the values a reduced-precision
+    MLP multiplies (`flags` gives the MLP's input count)."""
+    feat, probes, sdf, mlp = fld.feat, fld.probes, fld.sdf, fld.mlp
     if half:
         feat, probes = feat.astype(np.float16), probes.astype(np.float16)
     if half_sdf:
         sdf = sdf.astype(np.float16)
-    return make_field(sdf, feat, probes, fld.mlp, n_sh=fld.n_sh, hidden=fld.hidden,
+    if mlp_round:
+        import workloads as wl
+        n_in = fld.feat.shape[-1] + fld.probes.shape[-1] + (6 if flags & FRESNEL_PAPER else 3)
+        mlp = wl.round_mlp_weights(mlp, n_in, fld.hidden, fld.layers, mlp_round)
+    return make_field(sdf, feat, probes, mlp, n_sh=fld.n_sh, hidden=fld.hidden,
                       layers=fld.layers)
 
 

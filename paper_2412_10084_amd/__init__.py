@@ -17,12 +17,20 @@ LIB_PATH = os.path.join(HERE, "libprobesdf.so")
 
 F32, F16, BF16 = 0, 1, 2
 FLAG_NO_FS, FLAG_NO_FA, FLAG_NV_ONE = 1, 2, 4
+FLAG_SH_REFLECT, FLAG_FRESNEL_PAPER = 8, 16
+MODEL_MAX_SAMPLES = 513
 OK, EINVAL, EALIGN, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
-ABI_VERSION = 3
+ABI_VERSION = 4
 BWD_FROM_TAPE = 1
 BRICK = 8
 
 N_FEAT, N_ANG, HIDDEN, N_MLP = 3, 4, 16, 227
+
+
+def mlp_size(flags: int = 0, hidden: int = HIDDEN, layers: int = 1) -> int:
+    """Parameters of the packed colour MLP (227 for the workload model)."""
+    n_in = N_FEAT + N_ANG + (6 if flags & FLAG_FRESNEL_PAPER else 3)
+    return hidden * n_in + hidden + (layers - 1) * (hidden * hidden + hidden) + 3 * hidden + 3
 
 EXPORTS = ("psdf_render_forward", "psdf_render_backward", "psdf_render_backward_noalloc",
            "psdf_l1_loss", "psdf_grid_step", "psdf_render_sphere_trace", "psdf_sdf_bounds",
@@ -41,7 +49,8 @@ class _Field(C.Structure):
                 ("n_feat", C.c_int32), ("sh_coeffs", C.c_int32), ("n_ang", C.c_int32),
                 ("mlp_hidden", C.c_int32), ("sdf_dtype", C.c_int32), ("feat_dtype", C.c_int32),
                 ("mlp_dtype", C.c_int32), ("sdf", C.c_void_p), ("feat", C.c_void_p),
-                ("probes", C.c_void_p), ("mlp", C.c_void_p), ("sdf_bounds", C.c_void_p)]
+                ("probes", C.c_void_p), ("mlp", C.c_void_p), ("sdf_bounds", C.c_void_p),
+                ("mlp_layers", C.c_int32)]
 
 
 class _RenderOpts(C.Structure):
@@ -117,11 +126,27 @@ def _check(rc: int):
 
 
 def _ptr(t) -> Optional[int]:
+    """Device address of a tensor argument (or a raw pointer passed as an int).
+    Tensors must be dense and on the GPU: a strided view or a host tensor would
+    be read as packed device memory, so both raise instead."""
     if t is None:
         return None
     if isinstance(t, int):
         return t
+    if not t.is_cuda:
+        raise PsdfError(EINVAL, f"tensor of shape {tuple(t.shape)} is not on the GPU")
+    if not t.is_contiguous():
+        raise PsdfError(EINVAL, f"tensor of shape {tuple(t.shape)} is not contiguous")
     return t.data_ptr()
+
+
+def _f32(t, name: str):
+    """A float32 tensor argument (rays, colours, gradients, MLP weights)."""
+    if t is not None and not isinstance(t, int):
+        import torch
+        if t.dtype != torch.float32:
+            raise PsdfError(EINVAL, f"{name} must be float32, got {t.dtype}")
+    return t
 
 
 def _stream(stream):
@@ -146,6 +171,8 @@ class Field:
     mlp: object
     mlp_dtype: int = F32
     bounds: object = None
+    hidden: int = HIDDEN
+    layers: int = 1
 
     @staticmethod
     def _dt(t) -> int:
@@ -153,13 +180,16 @@ class Field:
         return {torch.float32: F32, torch.float16: F16}[t.dtype]
 
     def cstruct(self) -> _Field:
+        _f32(self.mlp, "mlp")
+        if not isinstance(self.probes, int) and self._dt(self.probes) != self._dt(self.feat):
+            raise PsdfError(EINVAL, "probes and feat must have the same dtype")
         R = self.sdf.shape[0]
         P = self.probes.shape[0]
         sh = self.probes.shape[3]
         return _Field(C.sizeof(_Field), R, P, self.feat.shape[-1], sh, self.probes.shape[-1],
-                      HIDDEN, self._dt(self.sdf), self._dt(self.feat), self.mlp_dtype,
+                      self.hidden, self._dt(self.sdf), self._dt(self.feat), self.mlp_dtype,
                       _ptr(self.sdf), _ptr(self.feat), _ptr(self.probes), _ptr(self.mlp),
-                      _ptr(self.bounds))
+                      _ptr(self.bounds), self.layers)
 
 
 @dataclass
@@ -199,6 +229,9 @@ def render_forward(field: Field, opts: RenderOpts, rays_o, rays_d, rgb, aux=None
                    depth_wsum=None, stream=None, tape=None) -> None:
     """tape: optional workspace (backward_workspace) in which the forward records its
     shaded samples for render_backward(..., from_tape=True)."""
+    for t, n in ((rays_o, "rays_o"), (rays_d, "rays_d"), (rgb, "rgb"), (aux, "aux"),
+                 (depth_wsum, "depth_wsum")):
+        _f32(t, n)
     fs, op = field.cstruct(), opts.cstruct()
     B = rays_o.shape[0] if not isinstance(rays_o, int) else None
     _check(lib().psdf_render_forward(C.byref(fs), C.byref(op), B, _ptr(rays_o), _ptr(rays_d),
@@ -227,6 +260,9 @@ def render_backward(field: Field, opts: RenderOpts, rays_o, rays_d, aux, dL_drgb
                     stream=None, workspace=None, from_tape: bool = False) -> None:
     """workspace: optional scratch for the entry-parallel schedule, or (from_tape) the
     tape the forward recorded for the same field, opts and rays."""
+    for t, n in ((rays_o, "rays_o"), (rays_d, "rays_d"), (aux, "aux"), (dL_drgb, "dL_drgb"),
+                 *((grads.get(k), "grads." + k) for k in ("sdf", "feat", "probes", "mlp"))):
+        _f32(t, n)
     fs, op = field.cstruct(), opts.cstruct()
     g = _Grads(_ptr(grads.get("sdf")), _ptr(grads.get("feat")), _ptr(grads.get("probes")),
                _ptr(grads.get("mlp")))
@@ -250,6 +286,8 @@ def render_backward_noalloc(field: Field, opts: RenderOpts, rays_o, rays_d, aux,
 
 
 def l1_loss(rgb, target, dL_drgb, loss=None, stream=None) -> None:
+    for t, n in ((rgb, "rgb"), (target, "target"), (dL_drgb, "dL_drgb"), (loss, "loss")):
+        _f32(t, n)
     _check(lib().psdf_l1_loss(rgb.shape[0], _ptr(rgb), _ptr(target), _ptr(dL_drgb), _ptr(loss),
                               _stream(stream)))
 
@@ -307,12 +345,31 @@ def sphere_trace(field: Field, cams, W: int, H: int, out, eps: float = 1e-3,
 # ---------------------------------------------------------------------------
 # autograd
 # ---------------------------------------------------------------------------
-def render(field: Field, opts: RenderOpts, rays_o, rays_d):
+def render(field: Field, opts: RenderOpts, rays_o, rays_d, tape_samples: Optional[int] = None):
     """Differentiable render: returns rgb (B, 3); gradients flow to field.sdf,
-    field.feat, field.probes and field.mlp (FP32 tensors) through the HIP
-    backward kernel."""
+    field.feat, field.probes and field.mlp through the HIP backward kernels.
+
+    The forward records its shaded samples into a tape (a backward workspace with
+    room for `tape_samples` samples; default 8 per ray, or N - 1 per ray without
+    the skip rule, capped at 2^24) that the backward reads (PSDF_BWD_FROM_TAPE).
+    Waves whose samples do not fit the tape are re-marched, so any size gives the
+    same gradients.  Gradients take the dtype of their parameter: FP16 feature or
+    probe tensors receive FP16 gradients (one rounding of the FP32 sums, coarse
+    below 6e-5 where FP16 is subnormal); keep FP32 masters for training (grid_step
+    writes FP16 render copies of them)."""
     return _RenderFn.apply(field.sdf, field.feat, field.probes, field.mlp, field.mlp_dtype, opts,
-                           rays_o, rays_d, field.bounds)
+                           rays_o, rays_d, field.bounds, tape_samples, (field.hidden, field.layers))
+
+
+def is_paper_model(field: Field, flags: int) -> bool:
+    """True when the render runs the paper colour model's kernels (no tape)."""
+    return (field.hidden, field.layers) != (HIDDEN, 1) or bool(
+        flags & (FLAG_SH_REFLECT | FLAG_FRESNEL_PAPER))
+
+
+def _default_tape_samples(B: int, opts: RenderOpts) -> int:
+    per_ray = 8 if opts.skip_voxels > 0 else max(opts.n_samples - 1, 1)
+    return min(B * per_ray, 1 << 24)
 
 
 def _make_autograd():
@@ -320,29 +377,41 @@ def _make_autograd():
 
     class RenderFn(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, sdf, feat, probes, mlp, mlp_dtype, opts, rays_o, rays_d, bounds):
+        def forward(ctx, sdf, feat, probes, mlp, mlp_dtype, opts, rays_o, rays_d, bounds,
+                    tape_samples, shape):
             B = rays_o.shape[0]
             rgb = torch.empty((B, 3), device=rays_o.device, dtype=torch.float32)
             aux = torch.empty((B, 4), device=rays_o.device, dtype=torch.float32)
-            fld = Field(sdf, feat, probes, mlp, mlp_dtype, bounds)
-            render_forward(fld, opts, rays_o, rays_d, rgb, aux)
+            fld = Field(sdf, feat, probes, mlp, mlp_dtype, bounds, *shape)
+            tape = None
+            if not is_paper_model(fld, opts.flags):  # the paper model's backward re-marches
+                cap = _default_tape_samples(B, opts) if tape_samples is None else int(tape_samples)
+                tape = backward_workspace(max(B, 1), probes.shape[0], cap, device=rays_o.device)
+            render_forward(fld, opts, rays_o, rays_d, rgb, aux, tape=tape)
             ctx.save_for_backward(sdf, feat, probes, mlp, rays_o, rays_d, aux)
-            ctx.bounds = bounds
+            ctx.tape = tape
+            ctx.bounds, ctx.shape = bounds, shape
             ctx.mlp_dtype, ctx.opts = mlp_dtype, opts
             return rgb
 
         @staticmethod
         def backward(ctx, g_rgb):
             sdf, feat, probes, mlp, rays_o, rays_d, aux = ctx.saved_tensors
-            fld = Field(sdf, feat, probes, mlp, ctx.mlp_dtype, ctx.bounds)
+            fld = Field(sdf, feat, probes, mlp, ctx.mlp_dtype, ctx.bounds, *ctx.shape)
             gs = torch.zeros(sdf.shape, device=sdf.device, dtype=torch.float32)
             gf = torch.zeros(feat.shape, device=sdf.device, dtype=torch.float32)
             gp = torch.zeros(probes.shape, device=sdf.device, dtype=torch.float32)
             gm = torch.zeros(mlp.shape, device=sdf.device, dtype=torch.float32)
-            render_backward(fld, ctx.opts, rays_o, rays_d, aux, g_rgb.contiguous(),
-                            dict(sdf=gs, feat=gf, probes=gp, mlp=gm))
+            # the tape is read once: a second backward through the same graph (retain_graph)
+            # re-marches with the tape as scratch
+            tape = ctx.tape
+            from_tape = tape is not None and not getattr(ctx, "tape_used", False)
+            render_backward(fld, ctx.opts, rays_o, rays_d, aux, g_rgb.float().contiguous(),
+                            dict(sdf=gs, feat=gf, probes=gp, mlp=gm), workspace=tape,
+                            from_tape=from_tape)
+            ctx.tape_used = True
             return (gs.to(sdf.dtype), gf.to(feat.dtype), gp.to(probes.dtype), gm, None, None,
-                    None, None, None)
+                    None, None, None, None, None)
 
     return RenderFn
 

@@ -19,7 +19,10 @@ BUILD = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libprobesdf.so")
 
 SOURCES = ["abi.cpp", "render_fwd.hip", "render_bwd.hip", "trace.hip", "loss.hip", "step.hip",
-           "bounds.hip", "bwd_split.hip", "step_sdf.hip"]
+           "bounds.hip", "bwd_split.hip", "step_sdf.hip", "render_model.hip",
+           # the paper-model kernel instances, several units so that they compile in parallel
+           "render_model_bwd32_f32.hip", "render_model_bwd32_f16.hip", "render_model_bwd32_bf16.hip",
+           "render_model_bwd16.hip", "render_model_fwd.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -50,7 +53,7 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB_PATH + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

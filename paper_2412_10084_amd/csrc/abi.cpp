@@ -40,9 +40,12 @@ int check_field(const psdf_field* f) {
     return fail(PSDF_EINVAL, "field.struct_size %u != %zu", f->struct_size, sizeof(psdf_field));
   if (f->R < 2 || f->R > 1024 || f->P < 2 || f->P > 1024)
     return fail(PSDF_EINVAL, "grid sizes R=%d P=%d outside [2, 1024]", f->R, f->P);
-  if (f->n_feat != 3 || f->n_ang != 4 || f->mlp_hidden != 16)
-    return fail(PSDF_EUNSUPPORTED, "compiled shape is n_feat=3 n_ang=4 hidden=16 (got %d %d %d)",
-                f->n_feat, f->n_ang, f->mlp_hidden);
+  if (f->n_feat != 3 || f->n_ang != 4)
+    return fail(PSDF_EUNSUPPORTED, "compiled shape is n_feat=3 n_ang=4 (got %d %d)", f->n_feat,
+                f->n_ang);
+  if (!((f->mlp_hidden == 16 && f->mlp_layers == 1) || (f->mlp_hidden == 32 && f->mlp_layers == 2)))
+    return fail(PSDF_EUNSUPPORTED, "MLP of %d hidden layer(s) of %d: compiled are 1 x 16 and 2 x 32",
+                f->mlp_layers, f->mlp_hidden);
   if (f->sh_coeffs != 1 && f->sh_coeffs != 4 && f->sh_coeffs != 9 && f->sh_coeffs != 16)
     return fail(PSDF_EUNSUPPORTED, "sh_coeffs=%d not in {1,4,9,16}", f->sh_coeffs);
   const double r3 = (double)f->R * f->R * f->R, p3 = (double)f->P * f->P * f->P;
@@ -74,7 +77,32 @@ int check_opts(const psdf_render_opts* o) {
     return fail(PSDF_EINVAL, "n_samples=%d outside [2, 4096]", o->n_samples);
   if (!(o->tau > 0.f) || !std::isfinite(o->tau)) return fail(PSDF_EINVAL, "tau must be finite > 0");
   if (!std::isfinite(o->skip_voxels)) return fail(PSDF_EINVAL, "skip_voxels must be finite");
-  if (o->flags & ~7) return fail(PSDF_EINVAL, "unknown flags 0x%x", o->flags);
+  if (o->flags & ~31) return fail(PSDF_EINVAL, "unknown flags 0x%x", o->flags);
+  return PSDF_OK;
+}
+
+// The paper's colour model (reflected SH argument, (1 - n.v)^0..5 inputs, or the
+// two-layer MLP of 32) runs on its own kernels, with these limits.
+bool paper_model(const psdf_field* f, int32_t flags) {
+  return f->mlp_hidden != 16 || f->mlp_layers != 1 ||
+         (flags & (PSDF_FLAG_SH_REFLECT | PSDF_FLAG_FRESNEL_PAPER)) != 0;
+}
+
+int check_paper_model(const psdf_field* f, const psdf_render_opts* o) {
+  if (f->sdf_dtype != PSDF_F32)
+    return fail(PSDF_EUNSUPPORTED, "the paper colour model needs an FP32 sdf");
+  if (!((f->feat_dtype == PSDF_F32 && f->mlp_dtype == PSDF_F32) ||
+        (f->feat_dtype == PSDF_F16 && f->mlp_dtype != PSDF_F32)))
+    return fail(PSDF_EUNSUPPORTED,
+                "the paper colour model pairs FP32 features with the FP32 MLP and FP16 features "
+                "with the FP16 / BF16 MLP (got feat_dtype %d, mlp_dtype %d)",
+                f->feat_dtype, f->mlp_dtype);
+  if (f->sh_coeffs != 9 && f->sh_coeffs != 16)
+    return fail(PSDF_EUNSUPPORTED, "the paper colour model takes sh_coeffs 9 or 16 (got %d)",
+                f->sh_coeffs);
+  if (o->n_samples > PSDF_MODEL_MAX_SAMPLES)
+    return fail(PSDF_EUNSUPPORTED, "the paper colour model takes n_samples <= %d (got %d)",
+                PSDF_MODEL_MAX_SAMPLES, o->n_samples);
   return PSDF_OK;
 }
 
@@ -182,6 +210,15 @@ int psdf_render_forward(const psdf_field* field, const psdf_render_opts* opts, i
   a.rgb = rgb;
   a.aux = aux;
   a.depth_wsum = depth_wsum;
+  if (paper_model(field, opts->flags)) {
+    if ((rc = check_paper_model(field, opts))) return rc;
+    if (tape && (rc = check_ws(tape, tape_bytes, B, field->P, "tape"))) return rc;
+    return hip_status(psdf::launch_render_model(a, false, field->sdf_dtype, field->feat_dtype,
+                                                field->mlp_dtype, field->sh_coeffs,
+                                                field->mlp_hidden, field->mlp_layers,
+                                                static_cast<hipStream_t>(stream)),
+                      "render_forward launch");
+  }
   psdf::BwdWs ws{};
   if (tape) {
     if ((rc = check_ws(tape, tape_bytes, B, field->P, "tape"))) return rc;
@@ -237,6 +274,16 @@ int psdf_render_backward(const psdf_field* field, const psdf_render_opts* opts, 
   if (flags & ~PSDF_BWD_FROM_TAPE) return fail(PSDF_EINVAL, "unknown backward flags 0x%x", flags);
   if ((flags & PSDF_BWD_FROM_TAPE) && !workspace)
     return fail(PSDF_EINVAL, "PSDF_BWD_FROM_TAPE needs the workspace the forward recorded");
+  if (paper_model(field, opts->flags)) {
+    if ((rc = check_paper_model(field, opts))) return rc;
+    if (workspace && (rc = check_ws(workspace, workspace_bytes, B, field->P, "workspace")))
+      return rc;
+    return hip_status(psdf::launch_render_model(a, true, field->sdf_dtype, field->feat_dtype,
+                                                field->mlp_dtype, field->sh_coeffs,
+                                                field->mlp_hidden, field->mlp_layers,
+                                                static_cast<hipStream_t>(stream)),
+                      "render_backward launch");
+  }
   if (workspace) {
     if ((rc = check_ws(workspace, workspace_bytes, B, field->P, "workspace"))) return rc;
     const psdf::BwdWs ws = psdf::bwd_ws_carve(workspace, B, field->P, workspace_bytes);
@@ -260,6 +307,14 @@ int psdf_render_backward_noalloc(const psdf_field* field, const psdf_render_opts
   psdf::RenderArgs a{};
   if ((rc = prep_backward(field, opts, B, rays_o, rays_d, aux, dL_drgb, grads, a))) return rc;
   if (B == 0) return ok();
+  if (paper_model(field, opts->flags)) {  // its reverse mode uses no workspace
+    if ((rc = check_paper_model(field, opts))) return rc;
+    return hip_status(psdf::launch_render_model(a, true, field->sdf_dtype, field->feat_dtype,
+                                                field->mlp_dtype, field->sh_coeffs,
+                                                field->mlp_hidden, field->mlp_layers,
+                                                static_cast<hipStream_t>(stream)),
+                      "render_backward_noalloc launch");
+  }
   const int64_t need = psdf::bwd_ws_bytes(B, field->P, 0);
   if (need > (int64_t)PSDF_NOALLOC_SCRATCH_BYTES)
     return fail(PSDF_EINVAL,
@@ -405,6 +460,8 @@ int psdf_render_sphere_trace(const psdf_field* field, const psdf_trace_opts* opt
     return fail(PSDF_EINVAL, "trace opts out of range");
   if (V < 0 || W < 0 || H < 0 || V > 65535 || W > 65535 * 16 || H > 65535 * 16)
     return fail(PSDF_EINVAL, "bad image size V=%d W=%d H=%d", V, W, H);
+  if (field->mlp_hidden != 16 || field->mlp_layers != 1)
+    return fail(PSDF_EUNSUPPORTED, "sphere tracing shades with the one-layer MLP of 16");
   if ((int64_t)V * W * H == 0) return ok();
   if ((rc = check_f32(cams, "cams")) || (rc = check_f32(out, "out"))) return rc;
   psdf::TraceArgs a{};

@@ -177,6 +177,9 @@ hipError_t launch_render_backward(const RenderArgs& a, int sdf_dt, int feat_dt, 
 hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws, bool from_tape,
                                         int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
                                         hipStream_t s);
+// the paper's colour model (model.h): forward (backward = false) or reverse mode
+hipError_t launch_render_model(const RenderArgs& a, bool backward, int sdf_dt, int feat_dt,
+                               int mlp_dt, int n_sh, int hidden, int layers, hipStream_t s);
 hipError_t launch_sphere_trace(const TraceArgs& a, int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
                                hipStream_t s);
 hipError_t launch_l1_loss(int64_t B, const float* rgb, const float* target, float* dL,

@@ -1,0 +1,373 @@
+// Kernels of the render step of the paper's own colour model (model.h): forward
+// and reverse mode with one ray per wave and one sample per lane.
+//
+// A wave takes its rays one at a time.  The 64 lanes evaluate 64 consecutive
+// samples of the ray at once (s_i by trilinear interpolation, s_{i+1} from the
+// next lane), the NeuS opacity (Sec. 3.3, Eq. neus, log domain) and the
+// transmittance as a wavefront prefix sum of log(1 - alpha) carried from chunk to
+// chunk.  The shaded samples of the ray (active, alpha > 0) are compacted into an
+// LDS list and shaded 64 per wave instruction stream, whatever their position on
+// the ray.  The reverse mode keeps the whole list, so the colour remaining
+// behind each sample, R_i = sum_{j>=i} w_j C_j, is an exact suffix sum (wavefront
+// suffix scans, last batch first), never a difference.
+#pragma once
+
+#include "model.h"
+
+namespace psdf {
+
+// shaded samples of one ray that a wave holds: N <= MODEL_EMAX + 1
+constexpr int MODEL_EMAX = 512;
+
+struct ModelEntries {
+  int i[MODEL_EMAX];      // sample index
+  float w[MODEL_EMAX];    // T_i alpha_i
+  float T[MODEL_EMAX];    // T_i
+  float s0[MODEL_EMAX];   // s_i
+  float s1[MODEL_EMAX];   // s_{i+1}
+};
+
+__device__ __forceinline__ float wave_prefix_incl(float v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const float y = __shfl_up(v, d, 64);
+    if (lane >= d) v += y;
+  }
+  return v;
+}
+
+__device__ __forceinline__ float wave_suffix_incl(float v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const float y = __shfl_down(v, d, 64);
+    if (lane + d < 64) v += y;
+  }
+  return v;
+}
+
+template <typename ST>
+__device__ __forceinline__ float sdf_at(const ST* __restrict__ sdf, const Geo& G, const RayD& r,
+                                        int i) {
+  double x[3];
+  sample_pos(r, sample_t(r, i), x);
+  return tri1(sdf, G.R, cell_d(x, G.R, G.inv_h));
+}
+
+// The ray's samples: opacity, transmittance and the list of shaded samples.
+// Returns the number of entries; logT = log T after the last sample.
+template <typename ST>
+__device__ __forceinline__ int model_march(const ST* __restrict__ sdf, const RenderArgs& a,
+                                           const Geo& G, const RayD& r, int lane, ModelEntries& E,
+                                           float& logT) {
+  int n = 0;
+  float carry = 0.0f;
+  const int N = a.N;
+  for (int c0 = 0; c0 < N - 1; c0 += 64) {  // wave-uniform
+    const int i = c0 + lane;
+    const float s_i = i < N ? sdf_at(sdf, G, r, i) : 0.0f;
+    float s_n = __shfl_down(s_i, 1, 64);
+    if (lane == 63) s_n = c0 + 64 < N ? sdf_at(sdf, G, r, c0 + 64) : 0.0f;
+    const bool act = i < N - 1 && (a.skip_thr <= 0.f || fabsf(s_i) <= a.skip_thr);
+    float dl = 0.0f;
+    bool sh = false;
+    if (act) {
+      dl = log_sigmoid(a.tau * s_n) - log_sigmoid(a.tau * s_i);
+      sh = dl < 0.0f;
+    }
+    const float ldl = sh ? dl : 0.0f;
+    const float incl = wave_prefix_incl(ldl, lane);
+    float excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0.0f;
+    const uint64_t mask = __ballot(sh);
+    if (sh) {
+      const float T = expf(carry + excl);
+      const int e = n + lane_rank(mask);
+      E.i[e] = i;
+      E.w[e] = T * -expm1f(dl);
+      E.T[e] = T;
+      E.s0[e] = s_i;
+      E.s1[e] = s_n;
+    }
+    n += (int)__popcll(mask);
+    carry += __shfl(incl, 63, 64);
+  }
+  logT = carry;
+  return n;
+}
+
+// rays [r0, r1) of this wave: contiguous ranges, remapped so that each XCD
+// (with its own L2) takes one contiguous part of the batch
+__device__ __forceinline__ void wave_rays(int64_t B, int64_t per_wave, int64_t& r0, int64_t& r1) {
+  const int64_t w = xcd_block(blockIdx.x, gridDim.x);
+  r0 = w * per_wave;
+  r1 = r0 + per_wave < B ? r0 + per_wave : B;
+}
+
+template <typename ST, typename FT, int NSH, int M, int H, int L>
+__global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per_wave) {
+  __shared__ ModelEntries E;
+  const int lane = threadIdx.x;
+  const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
+  const FT* __restrict__ feat = static_cast<const FT*>(a.feat);
+  const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
+  cfloat* __restrict__ W = const_mlp(a.mlp);
+  const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
+  const int nin = model_n_in(a.flags);
+  int64_t r0, r1;
+  wave_rays(a.B, per_wave, r0, r1);
+  for (int64_t ray = r0; ray < r1; ++ray) {
+    RayD r;
+    const bool hit = ray_setup_d(a.rays_o[3 * ray], a.rays_o[3 * ray + 1], a.rays_o[3 * ray + 2],
+                                 a.rays_d[3 * ray], a.rays_d[3 * ray + 1], a.rays_d[3 * ray + 2],
+                                 a.N, r);
+    float rgb[3] = {0.f, 0.f, 0.f}, depth = 0.f, wsum = 0.f, logT = 0.f;
+    if (hit) {
+      const int n = model_march(sdf, a, G, r, lane, E, logT);
+      wave_sync();
+      const float v[3] = {(float)-r.d[0], (float)-r.d[1], (float)-r.d[2]};
+      for (int b0 = 0; b0 < n; b0 += 64) {
+        const int e = b0 + lane;
+        float wc[3] = {0.f, 0.f, 0.f}, w = 0.f, wt = 0.f;
+        if (e < n) {
+          const int i = E.i[e];
+          double x[3];
+          sample_pos(r, sample_t(r, i), x);
+          ModelShade<NSH> S;
+          model_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, S);
+          float pre[L * H], out[3];
+          model_mlp_fwd<M, H, L>(W, nin, S.z, pre, out);
+          w = E.w[e];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) wc[c] = w * sigmoidf(out[c]);
+          wt = w * (float)(sample_t(r, i) + 0.5 * r.dt);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rgb[c] += wave_sum(wc[c]);
+        depth += wave_sum(wt);
+        wsum += wave_sum(w);
+      }
+      wave_sync();
+    }
+    if (lane == 0) {
+      a.rgb[3 * ray] = rgb[0];
+      a.rgb[3 * ray + 1] = rgb[1];
+      a.rgb[3 * ray + 2] = rgb[2];
+      if (a.aux) {
+        a.aux[4 * ray] = rgb[0];
+        a.aux[4 * ray + 1] = rgb[1];
+        a.aux[4 * ray + 2] = rgb[2];
+        a.aux[4 * ray + 3] = logT;
+      }
+      if (a.depth_wsum) {
+        a.depth_wsum[2 * ray] = depth;
+        a.depth_wsum[2 * ray + 1] = wsum;
+      }
+    }
+  }
+}
+
+template <int NSH>
+struct ModelBwdLds {
+  ModelEntries E;
+  float C[MODEL_EMAX][3];
+  float gdl[MODEL_EMAX];
+  union {
+    DwLds dw;
+    ProbeAcc<NSH> pa;
+    float sc[64][65];
+  } u;
+  int k0[64][3];
+  int fb[64];
+};
+
+// Reverse mode (gradients added into a.g_*): per ray, the march and the colours of
+// its shaded samples, the suffix walk for dL/d dl_i, then per batch of 64 shaded
+// samples the MLP and the interpolations in reverse, with
+//   dL/dC_i = w_i dL/drgb,  dL/d dl_i = dL/drgb . (R_i - T_i C_i),
+//   d dl_i/d s_i = -tau sigma(-tau s_i),  d dl_i/d s_{i+1} = tau sigma(-tau s_{i+1}).
+template <typename ST, typename FT, int NSH, int M, int H, int L>
+__global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per_wave) {
+  __shared__ ModelBwdLds<NSH> S_;
+  ModelBwdLds<NSH>& Ls = S_;
+  ModelEntries& E = Ls.E;
+  const int lane = threadIdx.x;
+  const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
+  const FT* __restrict__ feat = static_cast<const FT*>(a.feat);
+  const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
+  cfloat* __restrict__ W = const_mlp(a.mlp);
+  const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
+  const int nin = model_n_in(a.flags);
+  const bool reflect = (G.flags & FLAG_SH_REFLECT) && !(G.flags & FLAG_NO_FA);
+  ModelDw<H, L> D;
+  model_dw_zero(D);
+  bool any = false;
+  int64_t r0, r1;
+  wave_rays(a.B, per_wave, r0, r1);
+  for (int64_t ray = r0; ray < r1; ++ray) {
+    const float dL[3] = {a.dL[3 * ray], a.dL[3 * ray + 1], a.dL[3 * ray + 2]};
+    if (dL[0] == 0.f && dL[1] == 0.f && dL[2] == 0.f) continue;  // wave-uniform
+    RayD r;
+    if (!ray_setup_d(a.rays_o[3 * ray], a.rays_o[3 * ray + 1], a.rays_o[3 * ray + 2],
+                     a.rays_d[3 * ray], a.rays_d[3 * ray + 1], a.rays_d[3 * ray + 2], a.N, r))
+      continue;
+    float logT;
+    const int n = model_march(sdf, a, G, r, lane, E, logT);
+    if (n == 0) continue;
+    any = true;
+    wave_sync();
+    const float v[3] = {(float)-r.d[0], (float)-r.d[1], (float)-r.d[2]};
+    // colours of the shaded samples
+    for (int b0 = 0; b0 < n; b0 += 64) {
+      const int e = b0 + lane;
+      if (e < n) {
+        double x[3];
+        sample_pos(r, sample_t(r, E.i[e]), x);
+        ModelShade<NSH> S;
+        model_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, S);
+        float pre[L * H], out[3];
+        model_mlp_fwd<M, H, L>(W, nin, S.z, pre, out);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Ls.C[e][c] = sigmoidf(out[c]);
+      }
+    }
+    wave_sync();
+    // suffix walk, last batch first: R_e = sum_{e' >= e} w C
+    {
+      float carry[3] = {0.f, 0.f, 0.f};
+      for (int b0 = ((n - 1) >> 6) << 6; b0 >= 0; b0 -= 64) {
+        const int e = b0 + lane;
+        const bool ve = e < n;
+        float Rv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float wc = ve ? E.w[e] * Ls.C[e][c] : 0.f;
+          const float suf = wave_suffix_incl(wc, lane);
+          Rv[c] = suf + carry[c];
+          carry[c] += __shfl(suf, 0, 64);
+        }
+        if (ve) {
+          const float T = E.T[e];
+          Ls.gdl[e] = dL[0] * (Rv[0] - T * Ls.C[e][0]) + dL[1] * (Rv[1] - T * Ls.C[e][1]) +
+                      dL[2] * (Rv[2] - T * Ls.C[e][2]);
+        }
+      }
+    }
+    wave_sync();
+    // reverse mode of each batch
+    for (int b0 = 0; b0 < n; b0 += 64) {
+      const int e = b0 + lane;
+      const bool ve = e < n;
+      const int nb = min(64, n - b0);
+      double x[3] = {0.0, 0.0, 0.0};
+      ModelShade<NSH> S;
+      float pre[L * H], out[3], dout[3] = {0.f, 0.f, 0.f};
+      float gdl = 0.f, s0 = 0.f, s1 = 0.f;
+      int i = 0;
+      if (ve) {
+        i = E.i[e];
+        sample_pos(r, sample_t(r, i), x);
+        model_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, S);
+        model_mlp_fwd<M, H, L>(W, nin, S.z, pre, out);
+        const float w = E.w[e];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float C = sigmoidf(out[c]);
+          dout[c] = w * dL[c] * C * (1.f - C);
+        }
+        gdl = Ls.gdl[e];
+        s0 = E.s0[e];
+        s1 = E.s1[e];
+      } else {
+#pragma unroll
+        for (int k = 0; k < L * H; ++k) pre[k] = 0.f;
+#pragma unroll
+        for (int j = 0; j < MNIN; ++j) S.z[j] = 0.f;
+#pragma unroll
+        for (int j = 0; j < NSH; ++j) S.Y[j] = 0.f;
+      }
+      float dpre[L * H], dz[MNIN];
+      model_mlp_bwd<M, H, L>(W, nin, pre, dout, dpre, dz);
+      if (a.g_mlp) model_dw_batch<M, H, L>(Ls.u.dw, lane, ve, nin, S.z, pre, dpre, dout, D);
+      wave_sync();
+      // SDF: the FD-normal path and the opacity at s_i in the sample's 4x4x4 patch,
+      // the opacity at s_{i+1} at the next sample's cell
+      if (a.g_sdf) {
+        float* row = Ls.u.sc[lane];
+#pragma unroll
+        for (int q = 0; q < 64; ++q) row[q] = 0.f;
+        if (ve) {
+          float ev[NSH] = {};
+          if (reflect) probe_contract<FT, NSH>(probes, G, x, dz + NF, ev);
+          float dg[3] = {0.f, 0.f, 0.f};
+          if (!(G.flags & FLAG_NV_ONE) || reflect) model_normal_dg<NSH>(S, v, dz, ev, G.flags, dg);
+          int k0[3];
+          cell_k(x, G.R, G.inv_h, k0);
+          Ls.k0[lane][0] = k0[0];
+          Ls.k0[lane][1] = k0[1];
+          Ls.k0[lane][2] = k0[2];
+          const PatchDst Dp = patch_of_row(row, k0);
+          const float gs0 = -a.tau * sigmoidf(-a.tau * s0) * gdl;
+          if (gs0 != 0.f) patch_add(Dp, k0, x, G.R, G.inv_h, gs0);
+          if (dg[0] != 0.f || dg[1] != 0.f || dg[2] != 0.f) fd_patch(Dp, k0, G, x, dg);
+          const float gs1 = a.tau * sigmoidf(-a.tau * s1) * gdl;
+          if (gs1 != 0.f) {
+            double x1[3];
+            sample_pos(r, sample_t(r, i + 1), x1);
+            scatter8(a.g_sdf, G.R, cell_d(x1, G.R, G.inv_h), gs1);
+          }
+        }
+        wave_sync();
+        sdf_patch_flush(Ls.u.sc, Ls.k0, nb, lane, G.R, a.g_sdf);
+        wave_sync();
+      }
+      if (!(G.flags & FLAG_NO_FS) && a.g_feat)
+        feat_scatter_wave(Ls.u.sc, Ls.fb, ve, cell_d(x, G.R, G.inv_h), dz, nb, lane, G.R,
+                          a.g_feat);
+      if (!(G.flags & FLAG_NO_FA) && a.g_probes) {
+        probe_acc_clear<NSH>(Ls.u.pa, lane);
+        probe_scatter_wave<NSH>(Ls.u.pa, lane, ve,
+                                ve ? cell_d(x, G.P, G.inv_hp) : Cell{0, 0.f, 0.f, 0.f}, G.P, S.Y,
+                                dz + NF, a.g_probes);
+      }
+      wave_sync();
+    }
+  }
+  if (any && a.g_mlp) model_dw_flush<H, L>(D, lane, nin, a.g_mlp);
+}
+
+// Launch of the kernels of one MLP shape (H, L), direction and MLP arithmetic M;
+// the instances are spread over several translation units (render_model_*.hip).
+template <int H, int L, bool BWD, int M>
+hipError_t launch_model_hlm(const RenderArgs& a, int feat_dt, int n_sh, dim3 grid, int64_t per,
+                            hipStream_t s) {
+  typedef float ST;
+  auto go = [&](auto ft, auto nsh) {
+    typedef decltype(ft) FT;
+    constexpr int NSH = decltype(nsh)::value;
+    if constexpr (BWD)
+      hipLaunchKernelGGL((model_bwd_kernel<ST, FT, NSH, M, H, L>), grid, dim3(64), 0, s, a, per);
+    else
+      hipLaunchKernelGGL((model_fwd_kernel<ST, FT, NSH, M, H, L>), grid, dim3(64), 0, s, a, per);
+  };
+  typedef std::integral_constant<int, 9> S9;
+  typedef std::integral_constant<int, 16> S16;
+  // storage follows the arithmetic: FP32 features with the FP32 MLP, FP16 features
+  // with the FP16 / BF16 MLP
+  if (feat_dt != (M == MLP_F32 ? 0 : 1)) return hipErrorInvalidValue;
+  if constexpr (M == MLP_F32) {
+    if (n_sh == 9) go(float(), S9());
+    else if (n_sh == 16) go(float(), S16());
+    else return hipErrorInvalidValue;
+  } else {
+    if (n_sh == 9) go(_Float16(), S9());
+    else if (n_sh == 16) go(_Float16(), S16());
+    else return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#define PSDF_MODEL_INSTANCE(H, L, BWD, M)                                                    \
+  template hipError_t launch_model_hlm<H, L, BWD, M>(const RenderArgs&, int, int, dim3, int64_t, \
+                                                     hipStream_t);
+
+}  // namespace psdf

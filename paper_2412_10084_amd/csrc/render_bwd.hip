@@ -4,7 +4,9 @@
 //
 // With log(1 - alpha_i) = dl_i = log Phi(s_{i+1}) - log Phi(s_i) and the colour
 // remaining from sample i on, R_i = sum_{j>=i} w_j C_j (R_0 = rgb from the
-// forward's aux, R_{i+1} = R_i - w_i C_i):
+// forward's aux, R_{i+1} = R_i - w_i C_i; this single-kernel schedule meets the
+// samples in march order, so it cannot sum R_i from the back as the workspace
+// schedules do, and clamps it to its exact range [0, T_i] instead):
 //   dL/dC_i   = w_i dL/drgb,
 //   dL/d dl_i = dL/drgb . (R_i - T_i C_i),
 //   d dl_i/d s_i = -tau sigma(-tau s_i),  d dl_i/d s_{i+1} = tau sigma(-tau s_{i+1}).
@@ -89,7 +91,12 @@ __device__ __forceinline__ void bwd_batch(const RenderArgs& a, const Geo& G, Bwd
       const int s = my_first & (RING - 1);
       const float w = L.w[s], T = L.T[s];
       const float c0 = L.C[s][0], c1 = L.C[s][1], c2 = L.C[s][2];
-      L.gdl[s] = dl0 * (R[0] - T * c0) + dl1 * (R[1] - T * c1) + dl2 * (R[2] - T * c2);
+      // R_i = rgb - sum_{j<i} w_j C_j cancels where T_i is below the rounding error of
+      // rgb; the exact R_i lies in [0, T_i] (0 < C < 1, the weights from i on sum to at
+      // most T_i), so the clamp bounds the error of R_i by min(T_i, error of the subtraction)
+      const float r0 = fminf(fmaxf(R[0], 0.f), T), r1 = fminf(fmaxf(R[1], 0.f), T),
+                  r2 = fminf(fmaxf(R[2], 0.f), T);
+      L.gdl[s] = dl0 * (r0 - T * c0) + dl1 * (r1 - T * c1) + dl2 * (r2 - T * c2);
       R[0] -= w * c0;
       R[1] -= w * c1;
       R[2] -= w * c2;

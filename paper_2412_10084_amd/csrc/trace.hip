@@ -1,14 +1,39 @@
 // Sphere-traced inference render.  The paper's real-time renderer shades voxels
 // and volume renders them (supplementary "Performance Analysis"); this path
 // marches t <- t + s(x) from the cube entry until s < eps (hit) or t > t_f
-// (miss), at most max_steps evaluations, then shades the hit point once with
-// the same colour model (Sec. 3.1-3.2, Sec. 4).  Rays are generated in the
+// (miss), at most max_steps evaluations (positions and step lengths in FP64),
+// then shades the hit point once with the same colour model (Sec. 3.1-3.2, Sec. 4).  Rays are generated in the
 // kernel from the pinhole cameras; a block covers a 16 x 16 pixel tile of one
 // view so that a wave's rays (4 rows of 16) stay spatially coherent.
 #include "dispatch.h"
 #include "shade.h"
 
 namespace psdf {
+
+// Trilinear SDF at an FP64 point, interpolated in FP64 from the stored nodes.  The
+// trace sums its step lengths (t <- t + s over tens of steps), so an FP32
+// interpolation error of each s would accumulate in the hit point; in FP64 the hit
+// decisions and the hit point agree with an FP64 evaluation to rounding.
+template <typename T>
+__device__ __forceinline__ double tri1_d(const T* __restrict__ g, int R, double inv_h,
+                                         const double x[3]) {
+  int k[3];
+  double f[3];
+  const double kmax = (double)(R - 2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = (x[a] + 1.0) * inv_h;
+    const double fl = fmin(fmax(floor(u), 0.0), kmax);
+    k[a] = (int)fl;
+    f[a] = u - fl;
+  }
+  const int b = (k[2] * R + k[1]) * R + k[0], RR = R * R;
+  const float2 p00 = ld2(g, b), p10 = ld2(g, b + R), p01 = ld2(g, b + RR), p11 = ld2(g, b + RR + R);
+  auto lerp = [](double a, double c, double t) { return fma(t, c - a, a); };
+  const double a0 = lerp(p00.x, p00.y, f[0]), a1 = lerp(p10.x, p10.y, f[0]);
+  const double a2 = lerp(p01.x, p01.y, f[0]), a3 = lerp(p11.x, p11.y, f[0]);
+  return lerp(lerp(a0, a1, f[1]), lerp(a2, a3, f[1]), f[2]);
+}
 
 template <typename ST, typename FT, int NSH, int M>
 __global__ void __launch_bounds__(BLOCK) sphere_trace_kernel(TraceArgs a) {
@@ -56,12 +81,12 @@ __global__ void __launch_bounds__(BLOCK) sphere_trace_kernel(TraceArgs a) {
     for (int k = 0; k < a.max_steps; ++k) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) x[q] = fmin(fmax(fma(t, d[q], o[q]), -1.0), 1.0);
-      const float s = tri1(sdf, a.R, cell_d(x, a.R, G.inv_h));
-      if (s < a.eps) {
+      const double s = tri1_d(sdf, a.R, G.inv_h, x);
+      if (s < (double)a.eps) {
         hit = true;
         break;
       }
-      t += (double)s;
+      t += s;
       if (t > t1) break;
     }
   }

@@ -21,6 +21,23 @@ F16_GRAD_REL = 1e-2
 BF16_GRAD_REL = 3e-2
 SKIP_MARGIN = 1e-5        # rays whose |s| passes this close to the skip threshold are excluded
 
+# Element-wise gradient bound, beside the norm bound: |d_k| <= rtol |ref_k| + atol max|ref|.
+# FP32 sums of many contributions in an arbitrary order (FP32 atomics, or the taped box
+# pass's 32-bit fixed point with error below B / 2^25 per add, B the batch's largest
+# contribution) carry errors relative to the largest gradient, hence the atol term; the
+# mixed paths round the MLP's operands to FP16 / BF16, which no FP64 reference reproduces.
+GRAD_TOL = {
+    # prec: (norm grids, norm mlp, (rtol, atol) grids, (rtol, atol) mlp)
+    "fp32": (FP32_GRAD_REL, FP32_MLP_GRAD_REL, (1e-3, 1e-6), (1e-3, 1e-5)),
+    "f16": (F16_GRAD_REL, F16_GRAD_REL, (5e-2, 3e-2), (5e-2, 3e-2)),
+    "bf16": (BF16_GRAD_REL, BF16_GRAD_REL, (2e-1, 1.5e-1), (2e-1, 1.5e-1)),
+    # the paper's MLP (two ReLU layers of 32): operand rounding flips the ReLU mask of
+    # more units, and a flipped unit changes a sample's gradient by its whole term, so
+    # these errors grow like sqrt(u) (BF16 / FP16 measured ~3 = sqrt(8)), not like u
+    "f16_paper": (2e-2, 2e-2, (1e-1, 1e-1), (1e-1, 1e-1)),
+    "bf16_paper": (6e-2, 6e-2, (3e-1, 3e-1), (3e-1, 3e-1)),
+}
+
 
 def torch():
     import torch as _t
@@ -98,3 +115,39 @@ def color_check(got, ref, rel, abs_, mask=None):
 def norm_rel(got, ref):
     den = np.linalg.norm(ref)
     return float(np.linalg.norm(got - ref) / max(den, 1e-30))
+
+
+def elem_check(got, ref, rtol, atol):
+    """(number of entries outside rtol |ref| + atol max|ref|, worst err / bound)"""
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    bound = rtol * np.abs(ref) + atol * max(float(np.abs(ref).max(initial=0.0)), 1e-30)
+    err = np.abs(got - ref)
+    return int((err > bound).sum()), float((err / bound).max(initial=0.0))
+
+
+def grad_errors(g, g_ref, keys=("sdf", "feat", "probes", "mlp")):
+    """Per group: (norm-relative error, max |d| / max |ref|)."""
+    out = {}
+    for k in keys:
+        d = np.abs(np.asarray(g[k], np.float64) - np.asarray(g_ref[k], np.float64))
+        out[k] = (norm_rel(g[k], g_ref[k]),
+                  float(d.max(initial=0.0) / max(float(np.abs(g_ref[k]).max(initial=0.0)), 1e-30)))
+    return out
+
+
+def grad_check(g, g_ref, prec="fp32", keys=("sdf", "feat", "probes", "mlp")):
+    """Norm-relative and element-wise bounds of gradient groups against a reference
+    (every group is checked before the first failure is reported)."""
+    n_grid, n_mlp, e_grid, e_mlp = GRAD_TOL[prec]
+    fails = []
+    for k in keys:
+        nt, (rt, at) = (n_mlp, e_mlp) if k == "mlp" else (n_grid, e_grid)
+        e = norm_rel(g[k], g_ref[k])
+        if not e <= nt:
+            fails.append(f"{k}: norm-relative {e:.3g} > {nt}")
+        nbad, worst = elem_check(g[k], g_ref[k], rt, at)
+        if nbad:
+            fails.append(f"{k}: {nbad} entries outside {rt:g} |ref| + {at:g} max|ref| "
+                         f"(worst {worst:.3g} x bound)")
+    assert not fails, "; ".join(fails) + f" [all groups: {grad_errors(g, g_ref, keys)}]"

@@ -28,6 +28,7 @@ def test_exports_every_declared_symbol():
 
 def _field(**kw):
     f = ps._Field(C.sizeof(ps._Field), 64, 16, 3, 9, 4, 16, 0, 0, 0, FAKE, FAKE, FAKE, FAKE)
+    f.mlp_layers = 1
     for k, v in kw.items():
         setattr(f, k, v)
     return f
@@ -58,6 +59,8 @@ def test_empty_batch_ok():
     (dict(n_feat=4), ps.EUNSUPPORTED),
     (dict(sh_coeffs=5), ps.EUNSUPPORTED),
     (dict(mlp_hidden=32), ps.EUNSUPPORTED),
+    (dict(mlp_layers=2), ps.EUNSUPPORTED),
+    (dict(mlp_layers=0), ps.EUNSUPPORTED),
     (dict(feat_dtype=2), ps.EUNSUPPORTED),
     (dict(mlp_dtype=7), ps.EUNSUPPORTED),
     (dict(sdf=None), ps.EINVAL),
@@ -72,9 +75,42 @@ def test_field_validation(kw, code):
 
 
 @pytest.mark.parametrize("kw", [dict(n_samples=1), dict(n_samples=5000), dict(tau=0.0),
-                                dict(tau=float("nan")), dict(flags=8), dict(struct_size=3)])
+                                dict(tau=float("nan")), dict(flags=32), dict(struct_size=3)])
 def test_opts_validation(kw):
     assert _fwd(_field(), _opts(**kw)) == ps.EINVAL
+
+
+# the paper colour model's kernels and their limits
+PAPER = dict(mlp_hidden=32, mlp_layers=2)
+
+
+@pytest.mark.parametrize("fkw,okw", [
+    (dict(sdf_dtype=1, feat_dtype=1, mlp_dtype=1), dict()),  # FP16 sdf
+    (dict(mlp_dtype=1), dict()),                               # FP32 features, FP16 MLP
+    (dict(feat_dtype=1), dict()),                              # FP16 features, FP32 MLP
+    (dict(sh_coeffs=4), dict()),
+    (dict(), dict(n_samples=514)),
+])
+def test_paper_model_limits(fkw, okw):
+    assert _fwd(_field(**PAPER, **fkw), _opts(**okw), 10) == ps.EUNSUPPORTED
+    assert "paper colour model" in ps.last_error()
+    # the same limits hold when only a flag selects the paper model
+    if "mlp_layers" not in fkw:
+        f = _field(**fkw)
+        assert _fwd(f, _opts(flags=ps.FLAG_SH_REFLECT, **okw), 10) == ps.EUNSUPPORTED
+
+
+def test_paper_model_empty_batch_and_no_trace():
+    assert _fwd(_field(**PAPER), _opts(flags=ps.FLAG_SH_REFLECT | ps.FLAG_FRESNEL_PAPER)) == ps.OK
+    L = ps.lib()
+    to = ps._TraceOpts(C.sizeof(ps._TraceOpts), 1e-3, 256, 0)
+    assert L.psdf_render_sphere_trace(C.byref(_field(**PAPER)), C.byref(to), 1, FAKE, 8, 8, FAKE,
+                                      None) == ps.EUNSUPPORTED
+
+
+def test_mlp_sizes():
+    assert ps.mlp_size() == ps.N_MLP == 227
+    assert ps.mlp_size(ps.FLAG_FRESNEL_PAPER, 32, 2) == 32 * 13 + 32 + 32 * 32 + 32 + 3 * 32 + 3
 
 
 def test_null_descriptors_and_negative_batch():
@@ -221,3 +257,20 @@ def test_backward_noalloc_validation():
               None) == ps.EINVAL
     assert "static scratch" in ps.last_error()
     assert ps.backward_workspace_bytes(1 << 20, 128, 0) < ps.NOALLOC_SCRATCH_BYTES
+
+
+def test_binding_rejects_wrong_dtype_and_host_tensors():
+    """The binding refuses float64 and host tensors before anything reaches the library
+    (no GPU needed: the checks run on the host)."""
+    import torch
+    import paper_2412_10084_amd as ps
+    fld = ps.Field(sdf=torch.zeros(4, 4, 4), feat=torch.zeros(4, 4, 4, 3),
+                   probes=torch.zeros(2, 2, 2, 9, 4), mlp=torch.zeros(227))
+    o = torch.zeros(8, 3)
+    rgb = torch.zeros(8, 3)
+    with pytest.raises(ps.PsdfError, match="float32"):
+        ps.render_forward(fld, ps.RenderOpts(), o.double(), o, rgb)
+    with pytest.raises(ps.PsdfError, match="not on the GPU"):
+        ps.render_forward(fld, ps.RenderOpts(), o, o, rgb)
+    with pytest.raises(ps.PsdfError, match="float32"):
+        ps.l1_loss(rgb, rgb.half(), rgb)

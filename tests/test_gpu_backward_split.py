@@ -8,7 +8,7 @@ import pytest
 import oracle
 import workloads as wl
 from gpu_common import (BF16_GRAD_REL, F16_GRAD_REL, FP32_GRAD_REL, FP32_MLP_GRAD_REL,
-                        SKIP_MARGIN, device_field, gpu_backward, gpu_forward, norm_rel, rays,
+                        SKIP_MARGIN, device_field, gpu_backward, gpu_forward, grad_check, rays,
                         scene, torch)
 
 pytestmark = pytest.mark.gpu
@@ -33,9 +33,7 @@ def _case(N=96, skip=4.0, B=4093, flags=0, seed=0, shape="sphere", R=64, P=16):
 
 
 def _check(g, g_ref, tol=TOL):
-    for k, t in tol:
-        e = norm_rel(g[k], g_ref[k])
-        assert e <= t, f"{k}: {e:.3g} > {t}"
+    grad_check(g, g_ref, "fp32", keys=tuple(k for k, _ in tol))
 
 
 @pytest.mark.parametrize("cap", [1 << 20, 1000, 64, 0])
@@ -50,8 +48,7 @@ def test_split_backward_matches_oracle(cap):
     g = gpu_backward(fld, do, dd, aux, dL, N, skip=skip, workspace=cap)
     _check(g, g_ref)
     g_fused = gpu_backward(fld, do, dd, aux, dL, N, skip=skip)
-    for k, t in TOL:
-        assert norm_rel(g[k], g_fused[k]) <= t, k
+    grad_check(g, g_fused, "fp32")
 
 
 @pytest.mark.parametrize("flags", [1, 2, 4])
@@ -85,7 +82,7 @@ def test_split_backward_mixed(mlp_dt, gtol):
     ft = scene(1, 64, 16, shape="torus")
     o, d = rays(8, 32, 16)
     N = 64
-    of_h = oracle.field_from(f, half=True)
+    of_h = oracle.field_from(f, half=True, mlp_round=("f16", "bf16")[mlp_dt - 1])
     ref = oracle.render_forward(of_h, o, d, N)
     tgt = oracle.render_forward(oracle.field_from(ft), o, d, N)["rgb"]
     _, dL = oracle.l1_loss(ref["rgb"], tgt)
@@ -94,9 +91,7 @@ def test_split_backward_mixed(mlp_dt, gtol):
     fw = gpu_forward(fld, o, d, N)
     do, dd, _, aux = fw["dev"]
     g = gpu_backward(fld, do, dd, aux, dL, N, workspace=1 << 18)
-    for k in ("sdf", "feat", "probes", "mlp"):
-        e = norm_rel(g[k], g_ref[k])
-        assert e <= gtol, f"{k}: {e:.3g} > {gtol}"
+    grad_check(g, g_ref, ("f16", "bf16")[mlp_dt - 1])
 
 
 def test_split_backward_empty_loss():
@@ -165,8 +160,7 @@ def test_tape_backward_matches_oracle(cap):
     _check(g, g_ref)
     do, dd, _, aux = fw["dev"]
     g_fused = gpu_backward(fld, do, dd, aux, dL, N, skip=skip)
-    for k, t in TOL:
-        assert norm_rel(g[k], g_fused[k]) <= t, k
+    grad_check(g, g_fused, "fp32")
 
 
 @pytest.mark.parametrize("flags", [1, 2, 4])
@@ -194,16 +188,14 @@ def test_tape_backward_mixed(mlp_dt, gtol):
     ft = scene(1, 64, 16, shape="torus")
     o, d = rays(8, 32, 16)
     N = 64
-    of_h = oracle.field_from(f, half=True)
+    of_h = oracle.field_from(f, half=True, mlp_round=("f16", "bf16")[mlp_dt - 1])
     ref = oracle.render_forward(of_h, o, d, N)
     tgt = oracle.render_forward(oracle.field_from(ft), o, d, N)["rgb"]
     _, dL = oracle.l1_loss(ref["rgb"], tgt)
     g_ref = oracle.render_backward(of_h, o, d, dL, N)
     _, _, g = _tape_run(f, o, d, dL, N, 0.0, 1 << 18, feat_half=True, mlp_dtype=mlp_dt,
                         bounds=False)
-    for k in ("sdf", "feat", "probes", "mlp"):
-        e = norm_rel(g[k], g_ref[k])
-        assert e <= gtol, f"{k}: {e:.3g} > {gtol}"
+    grad_check(g, g_ref, ("f16", "bf16")[mlp_dt - 1])
 
 
 def test_tape_backward_train256_full_size_sampled():

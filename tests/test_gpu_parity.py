@@ -12,7 +12,7 @@ import oracle
 import workloads as wl
 from gpu_common import (FP32_COLOR_ABS, FP32_COLOR_REL, FP32_GRAD_REL, FP32_MLP_GRAD_REL,
                         SKIP_MARGIN, color_check, dev, device_field, gpu_backward, gpu_forward,
-                        norm_rel, rays, scene, torch)
+                        grad_check, norm_rel, rays, scene, torch)
 
 pytestmark = pytest.mark.gpu
 
@@ -114,10 +114,8 @@ def test_backward_small(skip, N):
     fw = gpu_forward(fld, o, d, N, skip=skip)
     do, dd, _, aux = fw["dev"]
     g = gpu_backward(fld, do, dd, aux, dL, N, skip=skip)
-    for k, tol in (("sdf", FP32_GRAD_REL), ("feat", FP32_GRAD_REL), ("probes", FP32_GRAD_REL),
-                   ("mlp", FP32_MLP_GRAD_REL)):
-        e = norm_rel(g[k], g_ref[k])
-        assert e <= tol, f"{k}: norm-relative error {e:.3g} > {tol}"
+    grad_check(g, g_ref, "fp32")
+    for k in g_ref:
         assert np.linalg.norm(g_ref[k]) > 0
 
 

@@ -1,5 +1,7 @@
 """GPU parity, continued: full-size workloads on sampled outputs, the FP16 /
 BF16 mixed-precision paths, the optimiser step and the sphere tracer."""
+import json
+
 import numpy as np
 import pytest
 
@@ -8,7 +10,7 @@ import workloads as wl
 from gpu_common import (BF16_COLOR_ABS, BF16_GRAD_REL, F16_COLOR_ABS, F16_GRAD_REL,
                         FP32_COLOR_ABS, FP32_COLOR_REL, FP32_GRAD_REL, FP32_MLP_GRAD_REL,
                         SKIP_MARGIN, color_check, dev, device_field, gpu_backward, gpu_forward,
-                        norm_rel, rays, scene, torch)
+                        grad_check, grad_errors, norm_rel, rays, scene, torch)
 
 pytestmark = pytest.mark.gpu
 
@@ -45,10 +47,7 @@ def test_train256_full_size_sampled(bounds):
     g = gpu_backward(fld, do, dd, aux, dL, w.n_samples, skip=w.skip_voxels)
     g_ref = oracle.render_backward(of, o[sel], d[sel], dL[sel], w.n_samples,
                                    skip_voxels=w.skip_voxels)
-    for k, tol in (("sdf", FP32_GRAD_REL), ("feat", FP32_GRAD_REL), ("probes", FP32_GRAD_REL),
-                   ("mlp", FP32_MLP_GRAD_REL)):
-        e = norm_rel(g[k], g_ref[k])
-        assert e <= tol, f"{k}: {e:.3g} > {tol}"
+    grad_check(g, g_ref, "fp32")
 
 
 # ---------------------------------------------------------------------------
@@ -61,7 +60,7 @@ def test_mixed_forward_backward_small(mlp_dt, ctol, gtol):
     ft = scene(1, 64, 16, shape="torus")
     o, d = rays(8, 32, 16)
     N = 64
-    of_h = oracle.field_from(f, half=True)  # same FP16-rounded values the GPU reads
+    of_h = oracle.field_from(f, half=True, mlp_round=("f16", "bf16")[mlp_dt - 1])  # the values the GPU reads
     ref = oracle.render_forward(of_h, o, d, N)
     fld = device_field(f, feat_half=True, mlp_dtype=mlp_dt)
     got = gpu_forward(fld, o, d, N)
@@ -75,22 +74,55 @@ def test_mixed_forward_backward_small(mlp_dt, ctol, gtol):
     g_ref = oracle.render_backward(of_h, o, d, dL, N)
     do, dd, _, aux = got["dev"]
     g = gpu_backward(fld, do, dd, aux, dL, N)
-    for k in ("sdf", "feat", "probes", "mlp"):
-        e = norm_rel(g[k], g_ref[k])
-        assert e <= gtol, f"{k}: {e:.3g} > {gtol}"
+    grad_check(g, g_ref, ("f16", "bf16")[mlp_dt - 1])
 
 
-def test_mixed512_full_size_sampled():
+@pytest.mark.parametrize("prec", ["fp32", "f16", "bf16"])
+def test_mixed512_full_size_sampled(prec):
+    """The benchmark's mixed512 launch (512^3 / 128^3, 2^20 rays, N = 64, no skip),
+    forward with a tape and backward from it, in FP32 and with FP16 storage and the
+    MLP on FP16 / BF16 MFMA.  The oracle evaluates 600 sampled rays, fed the same
+    FP16-rounded values the GPU reads; the loss gradient sits on those rays only."""
+    import paper_2412_10084_amd as ps
     w = wl.WORKLOADS["mixed512"]
     f = scene(0, w.R, w.P)
     o, d = rays(w.views, w.W, w.H)
-    assert o.shape[0] == 1 << 20
-    fld = device_field(f, feat_half=True, mlp_dtype=1)
-    got = gpu_forward(fld, o, d, w.n_samples)
-    idx = np.sort(np.random.default_rng(8).choice(o.shape[0], 800, replace=False))
-    ref = oracle.render_forward(oracle.field_from(f, half=True), o[idx], d[idx], w.n_samples)
-    err = np.abs(got["rgb"][idx] - ref["rgb"]).max()
-    assert err <= F16_COLOR_ABS, f"colour error {err:.3g}"
+    B = o.shape[0]
+    assert B == 1 << 20
+    half = prec != "fp32"
+    mdt = {"fp32": 0, "f16": 1, "bf16": 2}[prec]
+    print(f"mixed512 case: {prec}", flush=True)
+    fld = device_field(f, feat_half=half, mlp_dtype=mdt)
+    tape = ps.backward_workspace(B, w.P, B * (w.n_samples - 1))
+    got = gpu_forward(fld, o, d, w.n_samples, tape=tape)
+    rng = np.random.default_rng(8)
+    idx = np.sort(rng.choice(B, 600, replace=False))
+    of = oracle.field_from(f, half=half, mlp_round=prec if half else "")
+    ref = oracle.render_forward(of, o[idx], d[idx], w.n_samples)
+    if half:
+        ctol = F16_COLOR_ABS if prec == "f16" else BF16_COLOR_ABS
+        nbad, emax = color_check(got["rgb"][idx], ref["rgb"], 0.0, ctol)
+    else:
+        nbad, emax = color_check(got["rgb"][idx], ref["rgb"], FP32_COLOR_REL, FP32_COLOR_ABS)
+    assert nbad == 0, f"{nbad} colours off, max err {emax:.3g}"
+    dL = np.zeros((B, 3))
+    dL[idx] = rng.choice([-1.0, 1.0], size=(idx.size, 3)) / (3.0 * B)
+    do, dd, _, aux = got["dev"]
+    g = gpu_backward(fld, do, dd, aux, dL, w.n_samples, workspace=tape, from_tape=True)
+    g_ref = oracle.render_backward(of, o[idx], d[idx], dL[idx], w.n_samples)
+    # the per-result error table against FP64: arithmetic error (oracle fed the values
+    # the GPU reads) and, for the mixed paths, total error (oracle fed the FP32 values)
+    table = {"prec": prec, "rays": int(idx.size),
+             "colour_max_abs": float(np.abs(got["rgb"][idx] - ref["rgb"]).max()),
+             "grads": grad_errors(g, g_ref)}
+    if half:
+        of32 = oracle.field_from(f)
+        ref32 = oracle.render_forward(of32, o[idx], d[idx], w.n_samples)
+        g32 = oracle.render_backward(of32, o[idx], d[idx], dL[idx], w.n_samples)
+        table["total_colour_max_abs"] = float(np.abs(got["rgb"][idx] - ref32["rgb"]).max())
+        table["total_grads"] = grad_errors(g, g32)
+    print("ERRTABLE " + json.dumps(table), flush=True)
+    grad_check(g, g_ref, prec)
 
 
 # ---------------------------------------------------------------------------
@@ -108,12 +140,15 @@ def _step_inputs(R=24, P=8, seed=21):
     return p, g, m, v
 
 
-# R = 70: several x tiles and z chunks of the tiled SDF pass, ragged at the ends
-@pytest.mark.parametrize("step,R", [(1, 24), (7, 24), (3, 70)])
-def test_grid_step_matches_oracle(step, R):
+# R = 70: several x tiles and z chunks of the tiled SDF pass, ragged at the ends.
+# R = 344, P = 128: the launch geometry of the 512^3 / 128^3 step (feature rows of
+# 3R/4 > 256 float4 span two blocks, probe rows of 128 x 36 floats five).
+@pytest.mark.parametrize("step,R,P", [(1, 24, 8), (7, 24, 8), (3, 70, 8), (2, 344, 128)])
+def test_grid_step_matches_oracle(step, R, P):
     import paper_2412_10084_amd as ps
     t = torch()
-    p, g, m, v = _step_inputs(R=R)
+    print(f"grid step case: R={R} P={P} step={step}", flush=True)
+    p, g, m, v = _step_inputs(R=R, P=P)
     opts = ps.StepOpts()
     keys = ("sdf", "feat", "probes", "mlp")
     dp = {k: dev(p[k]) for k in keys}
@@ -171,7 +206,10 @@ def test_grid_step_matches_oracle(step, R):
             # 2^-25 absolute in the subnormal range) plus the FP32 error above
             eh = np.abs(h - ref) / (np.abs(ref) * 2.0 ** -11 + 2.0 ** -25 + bound)
             assert eh.max() <= 1.0, f"{k}: fp16 copy {eh.max():.3g}"
-    np.testing.assert_allclose(losses.cpu().numpy(), L, rtol=1e-4)
+    # the losses are FP32 sums of up to 1.2e8 non-negative terms: per-thread sums, block
+    # trees and one atomic add per block, so the error grows with the count of block
+    # partials added in sequence (about 1e-4 of the sum at R = 344)
+    np.testing.assert_allclose(losses.cpu().numpy(), L, rtol=1e-4 if R < 100 else 1e-3)
 
 
 # ---------------------------------------------------------------------------
@@ -191,12 +229,46 @@ def test_sphere_trace(half, mlp_dt):
     of = oracle.field_from(f, half=half, half_sdf=half)
     ref = oracle.sphere_trace(of, cams, W, H, eps=1e-3, max_steps=256)
     got = out.cpu().numpy().reshape(-1, 3)
-    # a step whose s lands within 2e-5 of eps (or t of t_f) may decide differently
-    keep = (ref["margin"] > 2e-5) & (ref["steps"] < 250)
-    assert keep.mean() > 0.9, f"only {keep.mean():.3f} of rays away from thresholds"
+    _trace_check(got, ref, mlp_dt)
+
+
+def _trace_check(got, ref, mlp_dt):
+    # the trace runs in FP64 on both sides, so only a step whose s lands within
+    # 1e-6 of eps (or t of t_f) may decide differently
+    keep = (ref["margin"] > 1e-6) & (ref["steps"] < 250)
+    assert keep.mean() > 0.99, f"only {keep.mean():.4f} of rays away from thresholds"
     hit = ref["t_hit"] >= 0
     assert hit.sum() > 300
-    tol = 2e-3 if mlp_dt else 1e-4
-    err = np.abs(got - ref["rgb"]).max(axis=1)
-    assert err[keep].max() <= tol, f"max err {err[keep].max():.3g} (all rays {err.max():.3g})"
+    if mlp_dt:
+        nbad, emax = color_check(got, ref["rgb"], 0.0, F16_COLOR_ABS, keep)
+    else:
+        nbad, emax = color_check(got, ref["rgb"], FP32_COLOR_REL, FP32_COLOR_ABS, keep)
+    assert nbad == 0, f"{nbad} colours off, max err {emax:.3g}"
     assert np.all(got[keep & ~hit] == 0)
+
+
+def test_trace512_full_size_sampled():
+    """The benchmark's inference launch: FP16 grids 512^3 / 128^3, 16 views at
+    1920x1080 in one launch; the oracle traces 2000 sampled pixels."""
+    import paper_2412_10084_amd as ps
+    t = torch()
+    w = wl.WORKLOADS["trace512"]
+    f = scene(0, w.R, w.P)
+    cams = np.stack([c.as_array() for c in wl.fibonacci_cameras(w.views, w.W, w.H)])
+    cams = cams.astype(np.float32)
+    fld = device_field(f, feat_half=True, sdf_half=True)
+    out = t.empty((w.views, w.H, w.W, 3), device="cuda")
+    print("trace512 launch: 16 x 1920 x 1080", flush=True)
+    ps.sphere_trace(fld, dev(cams), w.W, w.H, out, eps=1e-3, max_steps=256)
+    t.cuda.synchronize()
+    rng = np.random.default_rng(31)
+    n_pix = w.views * w.W * w.H
+    ids = np.sort(rng.choice(n_pix, 2000, replace=False))
+    of = oracle.field_from(f, half=True, half_sdf=True)
+    ref = oracle.sphere_trace(of, cams, w.W, w.H, pixel_ids=ids, eps=1e-3, max_steps=256)
+    got = out.reshape(-1, 3)[t.from_numpy(ids).cuda()].cpu().numpy()
+    keep = (ref["margin"] > 1e-6) & (ref["steps"] < 250)
+    assert keep.mean() > 0.99
+    nbad, emax = color_check(got, ref["rgb"], FP32_COLOR_REL, FP32_COLOR_ABS, keep)
+    assert nbad == 0, f"{nbad} colours off, max err {emax:.3g}"
+    assert (ref["t_hit"] >= 0).sum() > 100

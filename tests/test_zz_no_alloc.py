@@ -9,8 +9,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_common import (FP32_GRAD_REL, FP32_MLP_GRAD_REL, dev, device_field, gpu_forward,
-                        norm_rel, rays, scene, torch)
+from gpu_common import dev, device_field, gpu_forward, grad_check, rays, scene, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -42,18 +41,13 @@ def _case(f, o, d, N, skip, seed, with_oracle=True):
     t.cuda.synchronize()
     a = {k: v.cpu().numpy().astype(np.float64) for k, v in g_na.items()}
     b = {k: v.cpu().numpy().astype(np.float64) for k, v in g_ws.items()}
+    grad_check(a, b, "fp32")  # no-alloc vs workspace
     for k in a:
-        tol = FP32_MLP_GRAD_REL if k == "mlp" else FP32_GRAD_REL
-        e = norm_rel(a[k], b[k])
-        assert e <= tol, f"{k}: no-alloc vs workspace {e:.3g} > {tol}"
         assert np.count_nonzero(a[k]) > 0, f"{k}: no gradient"
     if with_oracle:
         ref = oracle.render_backward(oracle.field_from(f), o, d, dL.astype(np.float64), N,
                                      skip_voxels=skip)
-        for k in a:
-            tol = FP32_MLP_GRAD_REL if k == "mlp" else FP32_GRAD_REL
-            e = norm_rel(a[k], ref[k])
-            assert e <= tol, f"{k}: no-alloc vs oracle {e:.3g} > {tol}"
+        grad_check(a, ref, "fp32")  # no-alloc vs oracle
 
 
 def test_noalloc_backward_two_calls_then_overflow():

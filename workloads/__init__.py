@@ -214,6 +214,35 @@ def round_half(a: np.ndarray) -> np.ndarray:
     return a.astype(np.float16)
 
 
+def round_bf16(a: np.ndarray) -> np.ndarray:
+    """float32 -> the nearest bfloat16 value (ties to even), returned as float32:
+    the upper 16 bits of the float32 pattern after adding half of the dropped part."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).reshape(np.shape(a))
+
+
+def mlp_weight_mask(n_in: int, hidden: int = HIDDEN, layers: int = 1,
+                    n_out: int = N_OUT) -> np.ndarray:
+    """True at the weights (not the biases) of a packed MLP [W_1, b_1, ..., Wo, bo]."""
+    parts, fan = [], n_in
+    for _ in range(layers):
+        parts += [np.ones(hidden * fan, bool), np.zeros(hidden, bool)]
+        fan = hidden
+    parts += [np.ones(n_out * hidden, bool), np.zeros(n_out, bool)]
+    return np.concatenate(parts)
+
+
+def round_mlp_weights(mlp: np.ndarray, n_in: int, hidden: int, layers: int,
+                      kind: str) -> np.ndarray:
+    """The packed MLP with its weights (not its biases) rounded to float16 ("f16") or
+    bfloat16 ("bf16"), as float32: the values a reduced-precision MLP multiplies."""
+    m = np.array(mlp, dtype=np.float32)
+    w = mlp_weight_mask(n_in, hidden, layers)
+    m[w] = (round_half(m[w]).astype(np.float32) if kind == "f16" else round_bf16(m[w]))
+    return m
+
+
 # ----------------------------------------------------------------------------
 # the five workloads
 # ----------------------------------------------------------------------------
