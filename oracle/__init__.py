@@ -43,6 +43,11 @@ class _StepOpts(C.Structure):
                 ("lambda_tv_probe", C.c_double)]
 
 
+class _StepExt(C.Structure):
+    _fields_ = [("base", _StepOpts), ("lambda_sdf", C.c_double), ("lambda_normal", C.c_double),
+                ("sigma", C.c_double), ("smooth", C.c_int32), ("weighted", C.c_int32)]
+
+
 NO_FS, NO_FA, NV_ONE = 1, 2, 4
 SH_REFLECT, FRESNEL_PAPER = 8, 16
 MAX_N = 1 << 20  # largest sample count the render calls accept
@@ -70,6 +75,8 @@ def lib():
         _lib.orc_composite.restype = C.c_double
         _lib.orc_l1_loss.restype = C.c_double
         _lib.orc_mlp_size.restype = C.c_int64
+        _lib.orc_l2rel_loss.restype = C.c_double
+        _lib.orc_max_threads.restype = C.c_int
     return _lib
 
 
@@ -328,6 +335,98 @@ def grid_step(params: dict, grads: dict, m: np.ndarray, v: np.ndarray, step: int
                         _p(p["mlp"]), _p(g["sdf"]), _p(g["feat"]), _p(g["probes"]),
                         _p(g["mlp"]), _p(m), _p(v), C.c_int64(step), C.byref(so), _p(losses))
     return p, m, v, losses
+
+
+# ---------------------------------------------------------------------------
+# smoothed SDF and the remaining regularisers (Sec. 3.3)
+# ---------------------------------------------------------------------------
+def gauss5(sigma=1.0):
+    w = np.zeros(5)
+    lib().orc_gauss5(C.c_double(sigma), _p(w))
+    return w
+
+
+def smooth(shat, sigma=1.0):
+    """s = G(shat), the 5^3 Gaussian with replicated edges."""
+    shat = _d(shat)
+    s = np.zeros_like(shat)
+    lib().orc_smooth(C.c_int(shat.shape[0]), C.c_double(sigma), _p(shat), _p(s))
+    return s
+
+
+def smooth_T(y, sigma=1.0):
+    """G^T y."""
+    y = _d(y)
+    out = np.zeros_like(y)
+    lib().orc_smooth_T(C.c_int(y.shape[0]), C.c_double(sigma), _p(y), _p(out))
+    return out
+
+
+def sdf_regs(shat, g_s=None, smooth=True, sigma=1.0, weighted=False, lambda_sdf=0.2,
+             lambda_eik=0.1, lambda_normal=0.05):
+    """(losses [L_sdf, L_Eik, L_normal], dL/dshat, s) with g_s the render gradient
+    with respect to s (zero when None)."""
+    shat = _d(shat)
+    g_s = np.zeros_like(shat) if g_s is None else _d(g_s)
+    g, s = np.zeros_like(shat), np.zeros_like(shat)
+    losses = np.zeros(3)
+    lib().orc_sdf_regs(C.c_int(shat.shape[0]), _p(shat), C.c_int(int(smooth)), C.c_double(sigma),
+                       C.c_int(int(weighted)), C.c_double(lambda_sdf), C.c_double(lambda_eik),
+                       C.c_double(lambda_normal), _p(g_s), _p(g), _p(s), _p(losses))
+    return losses, g, s
+
+
+@dataclass
+class StepExt:
+    base: StepOpts
+    lambda_sdf: float = 0.2
+    lambda_normal: float = 0.05
+    sigma: float = 1.0
+    smooth: bool = True
+    weighted: bool = False
+
+    def cstruct(self) -> _StepExt:
+        return _StepExt(self.base.cstruct(), self.lambda_sdf, self.lambda_normal, self.sigma,
+                        int(self.smooth), int(self.weighted))
+
+
+def grid_step_ext(params: dict, grads: dict, m: np.ndarray, v: np.ndarray, step: int,
+                  opts: StepExt):
+    """params['sdf'] is shat; grads['sdf'] is the render gradient with respect to
+    s = G(shat).  Returns (new params, m, v, losses[5], s of the new shat)."""
+    p = {k: _d(params[k]).copy() for k in ("sdf", "feat", "probes", "mlp")}
+    g = {k: _d(grads[k]) for k in ("sdf", "feat", "probes", "mlp")}
+    m, v = _d(m).copy(), _d(v).copy()
+    R, P = p["sdf"].shape[0], p["probes"].shape[0]
+    n_feat = int(np.prod(p["feat"].shape[3:]))
+    n_pc = int(np.prod(p["probes"].shape[3:]))
+    losses = np.zeros(5)
+    s_new = np.zeros_like(p["sdf"])
+    so = opts.cstruct()
+    lib().orc_grid_step_ext(C.c_int(R), C.c_int(P), C.c_int(n_feat), C.c_int(n_pc),
+                            C.c_int(p["mlp"].size), _p(p["sdf"]), _p(p["feat"]), _p(p["probes"]),
+                            _p(p["mlp"]), _p(g["sdf"]), _p(g["feat"]), _p(g["probes"]),
+                            _p(g["mlp"]), _p(m), _p(v), C.c_int64(step), C.byref(so),
+                            _p(losses), _p(s_new))
+    return p, m, v, losses, s_new
+
+
+def l2rel_loss(rgb, target, lam=40.0, eps=1e-3, n_images=1.0):
+    """(L, dL/drgb) of the relatively weighted L2 photometric loss."""
+    rgb, target = _d(rgb), _d(target)
+    dL = np.zeros_like(rgb)
+    L = lib().orc_l2rel_loss(C.c_int64(rgb.shape[0]), _p(rgb), _p(target), C.c_double(lam),
+                             C.c_double(eps), C.c_double(n_images), _p(dL))
+    return L, dL
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops."""
+    lib().orc_set_threads(C.c_int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def sphere_trace(of: OField, cams: np.ndarray, W: int, H: int, pixel_ids=None, eps=1e-3,

@@ -17,6 +17,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -814,6 +815,7 @@ void orc_adam(int64_t n, double* p, const double* g, double* m, double* v, int64
               double lr, double beta1, double beta2, double eps) {
   double bc1 = 1.0 - pow(beta1, (double)step);
   double bc2 = 1.0 - pow(beta2, (double)step);
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     m[i] = beta1 * m[i] + (1.0 - beta1) * g[i];
     v[i] = beta2 * v[i] + (1.0 - beta2) * g[i] * g[i];
@@ -914,3 +916,234 @@ int orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max_
   }
   return 0;
 }
+
+/* ===========================================================================
+ * The smoothed SDF and the remaining regularisers (Sec. 3.3, Eqs. smooth_sdf,
+ * eikonal_reg, smmoth_normals, photo_loss).
+ * ======================================================================== */
+
+/* 5-tap Gaussian of the 5^3 kernel G (Sec. 3.3 convolves the raw SDF with a 5^3
+ * Gaussian; the paper gives no width).  Reading: separable, w[k+2] proportional to
+ * exp(-k^2 / (2 sigma^2)) for k = -2..2, normalised to sum 1. */
+void orc_gauss5(double sigma, double w[5]) {
+  double sum = 0.0;
+  for (int k = -2; k <= 2; ++k) {
+    w[k + 2] = exp(-(double)(k * k) / (2.0 * sigma * sigma));
+    sum += w[k + 2];
+  }
+  for (int k = 0; k < 5; ++k) w[k] /= sum;
+}
+
+static int64_t clampi(int64_t i, int64_t R) { return i < 0 ? 0 : (i >= R ? R - 1 : i); }
+
+/* s = G(shat): every node sums the 125 nodes around it, weight w_a w_b w_c; a node
+ * index beyond the grid reads the edge node (reading: replicate, so constants are
+ * reproduced). */
+void orc_smooth(int R, double sigma, const double* shat, double* s) {
+  double w[5];
+  orc_gauss5(sigma, w);
+  for (int64_t k = 0; k < R; ++k)
+    for (int64_t j = 0; j < R; ++j)
+      for (int64_t i = 0; i < R; ++i) {
+        double acc = 0.0;
+        for (int c = -2; c <= 2; ++c)
+          for (int b = -2; b <= 2; ++b)
+            for (int a = -2; a <= 2; ++a) {
+              int64_t n = (clampi(k + c, R) * R + clampi(j + b, R)) * R + clampi(i + a, R);
+              acc += w[a + 2] * w[b + 2] * w[c + 2] * shat[n];
+            }
+        s[(k * R + j) * R + i] = acc;
+      }
+}
+
+/* out = G^T y: each term of orc_smooth, taken in reverse (y at the output node,
+ * added to the node it read). */
+void orc_smooth_T(int R, double sigma, const double* y, double* out) {
+  double w[5];
+  orc_gauss5(sigma, w);
+  int64_t n3 = (int64_t)R * R * R;
+  for (int64_t q = 0; q < n3; ++q) out[q] = 0.0;
+  for (int64_t k = 0; k < R; ++k)
+    for (int64_t j = 0; j < R; ++j)
+      for (int64_t i = 0; i < R; ++i) {
+        double yv = y[(k * R + j) * R + i];
+        for (int c = -2; c <= 2; ++c)
+          for (int b = -2; b <= 2; ++b)
+            for (int a = -2; a <= 2; ++a) {
+              int64_t n = (clampi(k + c, R) * R + clampi(j + b, R)) * R + clampi(i + a, R);
+              out[n] += w[a + 2] * w[b + 2] * w[c + 2] * yv;
+            }
+      }
+}
+
+/* Regularisers of the raw SDF shat through s = G(shat) (smooth != 0) or s = shat:
+ *   L_sdf    = lambda_sdf / R^3 * sum over nodes (s - shat)^2               (Eq. smooth_sdf)
+ *   L_Eik    = lambda_eik / (R-2)^3 * sum over interior nodes (|g| - 1)^2    (Eq. eikonal_reg)
+ *   L_normal = lambda_normal / Np * sum over axis-adjacent pairs of interior
+ *              nodes |n_a - n_b|^2, n = g / |g|, Np = 3 (R-2)^2 (R-3)        (Eq. smmoth_normals)
+ * with g the central differences (s[n+e] - s[n-e]) / 2h of s (mean-normalised
+ * sums; the normal term reads grad n as forward differences of the unit normal
+ * field between neighbouring nodes).  With `weighted`, the gradient of these
+ * terms with respect to s at node m (and the direct term of L_sdf with respect
+ * to shat_m) is multiplied by 1 / (1 + 5 |s_m|) (Sec. 3.3's factor on the
+ * gradients of the per-voxel regularisations).
+ *   g_s     [R^3] in:  the render gradient with respect to s
+ *   g_shat  [R^3] out: total gradient with respect to shat,
+ *           G^T (g_s + weighted dL/ds) + weighted dL/dshat (direct)
+ *   s_out   [R^3] out (nullable): s
+ *   losses  [3] out: L_sdf, L_Eik, L_normal
+ * The derivative of |g| at g = 0 is taken as 0. */
+void orc_sdf_regs(int R, const double* shat, int smooth, double sigma, int weighted,
+                  double lambda_sdf, double lambda_eik, double lambda_normal, const double* g_s,
+                  double* g_shat, double* s_out, double losses[3]) {
+  int64_t n3 = (int64_t)R * R * R;
+  double h = 2.0 / (double)(R - 1);
+  int64_t st[3] = {1, R, (int64_t)R * R};
+  double* s = (double*)malloc((size_t)n3 * sizeof(double));
+  double* gr = (double*)calloc((size_t)n3, sizeof(double));  /* dL_reg/ds */
+  double* gd = (double*)calloc((size_t)n3, sizeof(double));  /* dL_sdf/dshat, direct */
+  double* nrm = (double*)calloc((size_t)n3 * 3, sizeof(double));
+  double* gnm = (double*)calloc((size_t)n3, sizeof(double));
+  double* dn = (double*)calloc((size_t)n3 * 3, sizeof(double));
+  if (smooth) orc_smooth(R, sigma, shat, s);
+  else memcpy(s, shat, (size_t)n3 * sizeof(double));
+  /* L_sdf */
+  double acc_sdf = 0.0;
+  for (int64_t q = 0; q < n3; ++q) {
+    double d = s[q] - shat[q];
+    acc_sdf += d * d;
+    gr[q] += 2.0 * lambda_sdf / (double)n3 * d;
+    gd[q] -= 2.0 * lambda_sdf / (double)n3 * d;
+  }
+  /* gradients and unit normals at interior nodes */
+  double M = (double)(R - 2) * (R - 2) * (R - 2);
+  double acc_eik = 0.0;
+  for (int64_t k = 1; k < R - 1; ++k)
+    for (int64_t j = 1; j < R - 1; ++j)
+      for (int64_t i = 1; i < R - 1; ++i) {
+        int64_t n = (k * R + j) * R + i;
+        double g[3];
+        for (int a = 0; a < 3; ++a) g[a] = (s[n + st[a]] - s[n - st[a]]) / (2.0 * h);
+        double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        gnm[n] = gn;
+        for (int a = 0; a < 3; ++a) nrm[3 * n + a] = g[a] / fmax(gn, 1e-30);
+        acc_eik += (gn - 1.0) * (gn - 1.0);
+        if (gn > 0.0) {
+          double coef = lambda_eik / M * 2.0 * (gn - 1.0) / gn;
+          for (int a = 0; a < 3; ++a) {
+            gr[n + st[a]] += coef * g[a] / (2.0 * h);
+            gr[n - st[a]] -= coef * g[a] / (2.0 * h);
+          }
+        }
+      }
+  /* L_normal: pairs (n, n + e_a) with both nodes interior */
+  double Np = 3.0 * (double)(R - 2) * (R - 2) * (R - 3);
+  double acc_n = 0.0;
+  if (R > 3) {
+    for (int64_t k = 1; k < R - 1; ++k)
+      for (int64_t j = 1; j < R - 1; ++j)
+        for (int64_t i = 1; i < R - 1; ++i) {
+          int64_t n = (k * R + j) * R + i;
+          int64_t idx[3] = {i, j, k};
+          for (int a = 0; a < 3; ++a) {
+            if (idx[a] + 1 > R - 2) continue;
+            int64_t m2 = n + st[a];
+            for (int c = 0; c < 3; ++c) {
+              double d = nrm[3 * n + c] - nrm[3 * m2 + c];
+              acc_n += d * d;
+              dn[3 * n + c] += 2.0 * lambda_normal / Np * d;
+              dn[3 * m2 + c] -= 2.0 * lambda_normal / Np * d;
+            }
+          }
+        }
+    /* through n = g / |g| and the central differences */
+    for (int64_t k = 1; k < R - 1; ++k)
+      for (int64_t j = 1; j < R - 1; ++j)
+        for (int64_t i = 1; i < R - 1; ++i) {
+          int64_t n = (k * R + j) * R + i;
+          if (gnm[n] <= 0.0) continue;
+          double nd = 0.0;
+          for (int c = 0; c < 3; ++c) nd += dn[3 * n + c] * nrm[3 * n + c];
+          for (int a = 0; a < 3; ++a) {
+            double dg = (dn[3 * n + a] - nd * nrm[3 * n + a]) / gnm[n];
+            gr[n + st[a]] += dg / (2.0 * h);
+            gr[n - st[a]] -= dg / (2.0 * h);
+          }
+        }
+  }
+  if (weighted)
+    for (int64_t q = 0; q < n3; ++q) {
+      double wq = 1.0 / (1.0 + 5.0 * fabs(s[q]));
+      gr[q] *= wq;
+      gd[q] *= wq;
+    }
+  /* back to shat */
+  for (int64_t q = 0; q < n3; ++q) gr[q] += g_s[q];
+  if (smooth) orc_smooth_T(R, sigma, gr, g_shat);
+  else memcpy(g_shat, gr, (size_t)n3 * sizeof(double));
+  for (int64_t q = 0; q < n3; ++q) g_shat[q] += gd[q];
+  if (s_out) memcpy(s_out, s, (size_t)n3 * sizeof(double));
+  losses[0] = lambda_sdf / (double)n3 * acc_sdf;
+  losses[1] = lambda_eik / M * acc_eik;
+  losses[2] = R > 3 ? lambda_normal / Np * acc_n : 0.0;
+  free(s);
+  free(gr);
+  free(gd);
+  free(nrm);
+  free(gnm);
+  free(dn);
+}
+
+/* One optimiser step with the smoothed SDF: sdf holds shat; g_s is the render
+ * gradient with respect to s = G(shat).  The SDF gradient is orc_sdf_regs's;
+ * features and probes take the smoothness terms of orc_regularizers; then Adam
+ * per group (as orc_grid_step).  losses[5] = L_sdf, L_Eik, L_normal, L_feat,
+ * L_probe; s_new (nullable) receives G of the updated shat (or a copy of it
+ * without smoothing). */
+void orc_grid_step_ext(int R, int P, int n_feat, int n_pc, int n_mlp, double* sdf, double* feat,
+                       double* probes, double* mlp, const double* g_s, const double* g_feat,
+                       const double* g_probes, const double* g_mlp, double* m, double* v,
+                       int64_t step, const orc_step_ext* opt, double losses[5], double* s_new) {
+  const orc_step_opts* b = &opt->base;
+  int64_t ns = (int64_t)R * R * R, nf = ns * n_feat, np = (int64_t)P * P * P * n_pc;
+  double* G = (double*)calloc((size_t)(ns + nf + np), sizeof(double));
+  memcpy(G + ns, g_feat, (size_t)nf * sizeof(double));
+  memcpy(G + ns + nf, g_probes, (size_t)np * sizeof(double));
+  orc_sdf_regs(R, sdf, opt->smooth, opt->sigma, opt->weighted, opt->lambda_sdf, b->lambda_eik,
+               opt->lambda_normal, g_s, G, NULL, losses);
+  losses[3] = tv_grid(R, n_feat, feat, b->lambda_tv_feat, G + ns);
+  losses[4] = tv_grid(P, n_pc, probes, b->lambda_tv_probe, G + ns + nf);
+  orc_adam(ns, sdf, G, m, v, step, b->lr_sdf, b->beta1, b->beta2, b->eps);
+  orc_adam(nf, feat, G + ns, m + ns, v + ns, step, b->lr_feat, b->beta1, b->beta2, b->eps);
+  orc_adam(np, probes, G + ns + nf, m + ns + nf, v + ns + nf, step, b->lr_probe, b->beta1,
+           b->beta2, b->eps);
+  orc_adam(n_mlp, mlp, g_mlp, m + ns + nf + np, v + ns + nf + np, step, b->lr_mlp, b->beta1,
+           b->beta2, b->eps);
+  if (s_new) {
+    if (opt->smooth) orc_smooth(R, opt->sigma, sdf, s_new);
+    else memcpy(s_new, sdf, (size_t)ns * sizeof(double));
+  }
+  free(G);
+}
+
+/* Relatively weighted L2 photometric loss (Eq. photo_loss with the per-pixel weight
+ * (max(c, c_gt) + eps)^-1 on its gradient, the loss scaled by lambda and divided by
+ * the number of images in the batch, Supplementary "Scheduling").  Reading: the
+ * weight is held constant (its own derivative is not taken) and applies per
+ * channel:  L = lambda / n_images * sum (c - c_gt)^2 / (max(c, c_gt) + eps),
+ * dL/dc = 2 lambda / n_images * (c - c_gt) / (max(c, c_gt) + eps). */
+double orc_l2rel_loss(int64_t B, const double* rgb, const double* target, double lambda,
+                      double eps, double n_images, double* dL_drgb) {
+  double acc = 0.0, sc = lambda / n_images;
+  for (int64_t i = 0; i < 3 * B; ++i) {
+    double d = rgb[i] - target[i];
+    double wgt = 1.0 / (fmax(rgb[i], target[i]) + eps);
+    acc += d * d * wgt;
+    dL_drgb[i] = 2.0 * sc * d * wgt;
+  }
+  return sc * acc;
+}
+
+/* threads of the OpenMP loops (the benchmark's CPU baseline times 1 and all) */
+void orc_set_threads(int n) { omp_set_num_threads(n); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -56,6 +56,14 @@ typedef struct {
   double lambda_eik, lambda_tv_feat, lambda_tv_probe;
 } orc_step_opts;
 
+typedef struct {
+  orc_step_opts base;
+  double lambda_sdf, lambda_normal;
+  double sigma;        /* width of the 5-tap Gaussian, in voxels */
+  int32_t smooth;      /* 1: the SDF parameters are shat, rendering reads s = G(shat) */
+  int32_t weighted;    /* 1: (1 + 5 |s|)^-1 on the SDF regulariser gradients */
+} orc_step_ext;
+
 /* ---- building blocks, each pinned separately by the tests ---- */
 int orc_ray_box(const double o[3], const double d[3], double* tn, double* tf);
 void orc_trilinear(const double* grid, int R, int C, const double x[3], double* out);
@@ -96,6 +104,20 @@ void orc_grid_step(int R, int P, int n_feat, int n_pc, int n_mlp, double* sdf, d
                    double* probes, double* mlp, const double* g_sdf, const double* g_feat,
                    const double* g_probes, const double* g_mlp, double* m, double* v,
                    int64_t step, const orc_step_opts* opt, double losses[3]);
+void orc_gauss5(double sigma, double w[5]);
+void orc_smooth(int R, double sigma, const double* shat, double* s);
+void orc_smooth_T(int R, double sigma, const double* y, double* out);
+void orc_sdf_regs(int R, const double* shat, int smooth, double sigma, int weighted,
+                  double lambda_sdf, double lambda_eik, double lambda_normal, const double* g_s,
+                  double* g_shat, double* s_out, double losses[3]);
+void orc_grid_step_ext(int R, int P, int n_feat, int n_pc, int n_mlp, double* sdf, double* feat,
+                       double* probes, double* mlp, const double* g_s, const double* g_feat,
+                       const double* g_probes, const double* g_mlp, double* m, double* v,
+                       int64_t step, const orc_step_ext* opt, double losses[5], double* s_new);
+double orc_l2rel_loss(int64_t B, const double* rgb, const double* target, double lambda,
+                      double eps, double n_images, double* dL_drgb);
+void orc_set_threads(int n);
+int orc_max_threads(void);
 int orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max_steps,
                      int32_t V, const double* cams, int32_t W, int32_t H,
                      const int64_t* pixel_ids, int64_t n_pix, double* out, double* t_hit,
