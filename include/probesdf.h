@@ -288,6 +288,20 @@ int psdf_l1_loss(int64_t B, const float* rgb, const float* target, float* dL_drg
  * parameters.  `sdf_bounds_out` (nullable, [PSDF_BRICKS(R)^3][2], 8-byte
  * aligned) receives the brick bounds of the new sdf as the renderer will read
  * it: of the FP16 copy when sdf_half_out is set, else of sdf_out.
+ * Sec. 3.3's remaining regularisers: with any of sdf_reg_flags, lambda_sdf or
+ * lambda_normal set, the SDF part of the step instead
+ *   - with PSDF_STEP_SMOOTH, takes sdf_in / sdf_out as the raw values shat, g_sdf
+ *     as the render gradient with respect to s = G(shat) (s_in), and writes
+ *     s_out = G(sdf_out) (its FP16 copy in sdf_half_out, its bounds in
+ *     sdf_bounds_out);
+ *   - evaluates on s: L_sdf = lambda_sdf / R^3 * sum (s - shat)^2, the eikonal
+ *     term above, and L_normal = lambda_normal / (3 (R-2)^2 (R-3)) * sum over
+ *     axis-adjacent pairs of interior nodes |n_a - n_b|^2 (n = g / |g|, g the
+ *     central differences), with PSDF_STEP_REG_WEIGHT weighting their gradient at
+ *     node m by 1 / (1 + 5 |s_m|);
+ *   - takes the gradient back to shat through G^T, then Adam as above.
+ * It needs `work` (psdf_step_work_bytes(R) bytes); losses[0] is L_Eik of s and
+ * losses_ext receives (L_sdf, L_normal).
  */
 typedef struct psdf_step_args {
   uint32_t struct_size; /* sizeof(psdf_step_args) */
@@ -321,7 +335,51 @@ typedef struct psdf_step_args {
   void* probes_half_out;
   float* losses;         /* nullable [3] */
   float* sdf_bounds_out; /* nullable */
+  /* Sec. 3.3's smoothed SDF and remaining regularisers (all zero / NULL: unused; see
+   * psdf_grid_step) */
+  int32_t sdf_reg_flags; /* PSDF_STEP_SMOOTH | PSDF_STEP_REG_WEIGHT */
+  float lambda_sdf;      /* L_sdf (Eq. smooth_sdf) */
+  float lambda_normal;   /* L_normal (Eq. smmoth_normals) */
+  float smooth_sigma;    /* width of the Gaussian, voxels (> 0 with PSDF_STEP_SMOOTH) */
+  const float* s_in;     /* PSDF_STEP_SMOOTH: G(sdf_in), the field the renderer read */
+  float* s_out;          /* PSDF_STEP_SMOOTH: receives G(sdf_out) */
+  void* work;            /* psdf_step_work_bytes(R) bytes, 16-byte aligned */
+  int64_t work_bytes;
+  float* losses_ext;     /* nullable [2]: (L_sdf, L_normal) of the input parameters */
 } psdf_step_args;
+
+/* sdf_reg_flags */
+#define PSDF_STEP_SMOOTH 1     /* the sdf parameters are raw values shat; rendering reads
+                                  s = G(shat), G the 5^3 Gaussian of Sec. 3.3 */
+#define PSDF_STEP_REG_WEIGHT 2 /* the SDF regularisers' gradient at node m is weighted
+                                  by 1 / (1 + 5 |s_m|) (Sec. 3.3) */
+
+/* Bytes of the workspace of a grid step that uses the Sec. 3.3 regularisers:
+ * 8 R^3 floats; -1 if R is out of range. */
+int64_t psdf_step_work_bytes(int32_t R);
+
+/*
+ * psdf_smooth_sdf -- s = G(shat), the 5^3 Gaussian of Sec. 3.3 (Eq. smooth_sdf):
+ * 5 taps per axis proportional to exp(-k^2 / (2 sigma^2)), k = -2..2, normalised,
+ * nodes beyond the grid reading the edge node.  The field the renderer reads
+ * when the SDF is trained as raw values (the grid step writes the next one).
+ *   shat, s [R][R][R] FP32 (4-byte aligned, not overlapping); s_half nullable
+ *   FP16 copy of s (2-byte aligned); 2 <= R <= 1024, sigma > 0.
+ */
+int psdf_smooth_sdf(int32_t R, float sigma, const float* shat, float* s, void* s_half,
+                    void* stream);
+
+/*
+ * psdf_l2rel_loss -- the paper's photometric loss (Eq. photo_loss): L2 with the
+ * per-pixel weight (max(c, c_gt) + eps)^-1 on its gradient, scaled by lambda and
+ * divided by the number of images of the batch (supplementary "Scheduling"); the
+ * weight is held constant and applies per channel:
+ *   loss = lambda / n_images * sum (c - c_gt)^2 / (max(c, c_gt) + eps)   (nullable, overwritten)
+ *   dL_drgb = 2 lambda / n_images * (c - c_gt) / (max(c, c_gt) + eps)
+ * rgb, target, dL_drgb [B][3] FP32.  eps > 0, n_images > 0.
+ */
+int psdf_l2rel_loss(int64_t B, const float* rgb, const float* target, float* dL_drgb, float* loss,
+                    float lambda, float eps, float n_images, void* stream);
 
 int psdf_grid_step(const psdf_step_args* args, void* stream);
 

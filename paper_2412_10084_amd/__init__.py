@@ -33,8 +33,10 @@ def mlp_size(flags: int = 0, hidden: int = HIDDEN, layers: int = 1) -> int:
     return hidden * n_in + hidden + (layers - 1) * (hidden * hidden + hidden) + 3 * hidden + 3
 
 EXPORTS = ("psdf_render_forward", "psdf_render_backward", "psdf_render_backward_noalloc",
-           "psdf_l1_loss", "psdf_grid_step", "psdf_render_sphere_trace", "psdf_sdf_bounds",
+           "psdf_l1_loss", "psdf_l2rel_loss", "psdf_grid_step", "psdf_step_work_bytes",
+           "psdf_smooth_sdf", "psdf_render_sphere_trace", "psdf_sdf_bounds",
            "psdf_backward_workspace_bytes", "psdf_last_error", "psdf_abi_version")
+STEP_SMOOTH, STEP_REG_WEIGHT = 1, 2
 NOALLOC_SCRATCH_BYTES = 134217728
 
 
@@ -75,7 +77,10 @@ class _StepArgs(C.Structure):
             "sdf_in", "sdf_out", "feat_in", "feat_out", "probes_in", "probes_out", "mlp",
             "g_sdf", "g_feat", "g_probes", "g_mlp", "m_sdf", "v_sdf", "m_feat", "v_feat",
             "m_probes", "v_probes", "m_mlp", "v_mlp", "sdf_half_out", "feat_half_out",
-            "probes_half_out", "losses", "sdf_bounds_out")]
+            "probes_half_out", "losses", "sdf_bounds_out")] + [
+        ("sdf_reg_flags", C.c_int32), ("lambda_sdf", C.c_float), ("lambda_normal", C.c_float),
+        ("smooth_sigma", C.c_float), ("s_in", C.c_void_p), ("s_out", C.c_void_p),
+        ("work", C.c_void_p), ("work_bytes", C.c_int64), ("losses_ext", C.c_void_p)]
 
 
 class _TraceOpts(C.Structure):
@@ -100,6 +105,10 @@ def lib():
         L.psdf_render_backward_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.psdf_backward_workspace_bytes.argtypes = [i64, i32, i64]
         L.psdf_l1_loss.argtypes = [i64, vp, vp, vp, vp, vp]
+        f32 = C.c_float
+        L.psdf_l2rel_loss.argtypes = [i64, vp, vp, vp, vp, f32, f32, f32, vp]
+        L.psdf_step_work_bytes.argtypes = [i32]
+        L.psdf_smooth_sdf.argtypes = [i32, f32, vp, vp, vp, vp]
         L.psdf_grid_step.argtypes = [vp, vp]
         L.psdf_render_sphere_trace.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp]
         L.psdf_sdf_bounds.argtypes = [i32, i32, vp, vp, vp]
@@ -107,9 +116,11 @@ def lib():
         L.psdf_last_error.argtypes = []
         L.psdf_abi_version.restype = C.c_int
         for n in EXPORTS:
-            if n not in ("psdf_last_error", "psdf_abi_version", "psdf_backward_workspace_bytes"):
+            if n not in ("psdf_last_error", "psdf_abi_version", "psdf_backward_workspace_bytes",
+                         "psdf_step_work_bytes"):
                 getattr(L, n).restype = C.c_int
         L.psdf_backward_workspace_bytes.restype = C.c_int64
+        L.psdf_step_work_bytes.restype = C.c_int64
         if L.psdf_abi_version() != ABI_VERSION:
             raise RuntimeError("libprobesdf ABI version mismatch")
         _lib = L
@@ -216,6 +227,15 @@ class StepOpts:
     lambda_eik: float = 0.1
     lambda_tv_feat: float = 0.05
     lambda_tv_probe: float = 0.2
+    # Sec. 3.3's smoothed SDF and remaining regularisers (off by default)
+    smooth: bool = False        # the sdf parameters are raw values; rendering reads G(shat)
+    reg_weight: bool = False    # (1 + 5 |s|)^-1 on the SDF regularisers' gradients
+    lambda_sdf: float = 0.0
+    lambda_normal: float = 0.0
+    sigma: float = 1.0
+
+    def extended(self) -> bool:
+        return self.smooth or self.reg_weight or self.lambda_sdf != 0 or self.lambda_normal != 0
 
 
 # ---------------------------------------------------------------------------
@@ -309,13 +329,39 @@ def sdf_bounds(sdf, out=None, stream=None):
     return out
 
 
+def step_work_bytes(R: int) -> int:
+    return int(lib().psdf_step_work_bytes(R))
+
+
+def smooth_sdf(shat, s, sigma: float = 1.0, s_half=None, stream=None) -> None:
+    """s = G(shat), the 5^3 Gaussian of the raw SDF (the field the renderer reads)."""
+    _check(lib().psdf_smooth_sdf(shat.shape[0], sigma, _ptr(_f32(shat, "shat")),
+                                 _ptr(_f32(s, "s")), _ptr(s_half), _stream(stream)))
+
+
+def l2rel_loss(rgb, target, dL_drgb, loss=None, lam: float = 40.0, eps: float = 1e-3,
+               n_images: float = 1.0, stream=None) -> None:
+    """The paper's relatively weighted L2 photometric loss and its gradient."""
+    for t, n in ((rgb, "rgb"), (target, "target"), (dL_drgb, "dL_drgb"), (loss, "loss")):
+        _f32(t, n)
+    _check(lib().psdf_l2rel_loss(rgb.shape[0], _ptr(rgb), _ptr(target), _ptr(dL_drgb), _ptr(loss),
+                                 lam, eps, n_images, _stream(stream)))
+
+
 def grid_step(params_in: dict, params_out: dict, grads: dict, m: dict, v: dict, step: int,
               opts: StepOpts, half_out: Optional[dict] = None, losses=None, stream=None,
-              bounds_out=None) -> None:
+              bounds_out=None, s_in=None, s_out=None, work=None, losses_ext=None) -> None:
     """params_*: dict sdf, feat, probes (grids, out of place) and mlp (in place, taken from
     params_in); grads/m/v: dicts with the same keys; half_out: optional FP16 copies;
-    bounds_out: optional brick bounds of the new sdf (of its FP16 copy when given)."""
+    bounds_out: optional brick bounds of the new sdf (of its FP16 copy when given).
+    With opts.extended(): `work` (step_work_bytes(R) bytes; allocated when None), and
+    with opts.smooth the smoothed fields s_in = G(params_in["sdf"]) (what the renderer
+    read) and s_out (receives G(params_out["sdf"]))."""
     half_out = half_out or {}
+    if opts.extended() and work is None:
+        import torch
+        work = torch.empty(step_work_bytes(params_in["sdf"].shape[0]), dtype=torch.uint8,
+                           device=params_in["sdf"].device)
     R = params_in["sdf"].shape[0]
     P = params_in["probes"].shape[0]
     n_feat = params_in["feat"].shape[-1]
@@ -330,7 +376,10 @@ def grid_step(params_in: dict, params_out: dict, grads: dict, m: dict, v: dict, 
                   _ptr(m["feat"]), _ptr(v["feat"]), _ptr(m["probes"]), _ptr(v["probes"]),
                   _ptr(m["mlp"]), _ptr(v["mlp"]), _ptr(half_out.get("sdf")),
                   _ptr(half_out.get("feat")), _ptr(half_out.get("probes")), _ptr(losses),
-                  _ptr(bounds_out))
+                  _ptr(bounds_out),
+                  (STEP_SMOOTH if opts.smooth else 0) | (STEP_REG_WEIGHT if opts.reg_weight else 0),
+                  opts.lambda_sdf, opts.lambda_normal, opts.sigma, _ptr(s_in), _ptr(s_out),
+                  _ptr(work), _nbytes(work), _ptr(losses_ext))
     _check(lib().psdf_grid_step(C.byref(a), _stream(stream)))
 
 

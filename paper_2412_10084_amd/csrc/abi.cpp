@@ -351,6 +351,55 @@ static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// taps of the 5^3 Gaussian: exp(-k^2 / (2 sigma^2)), k = -2..2, normalised (in FP64)
+static psdf::SmoothTaps smooth_taps(float sigma) {
+  psdf::SmoothTaps t;
+  double w[5], sum = 0.0;
+  for (int k = -2; k <= 2; ++k) {
+    w[k + 2] = std::exp(-(double)(k * k) / (2.0 * (double)sigma * (double)sigma));
+    sum += w[k + 2];
+  }
+  for (int k = 0; k < 5; ++k) t.w[k] = (float)(w[k] / sum);
+  return t;
+}
+
+int64_t psdf_step_work_bytes(int32_t R) {
+  if (R < 2 || R > 1024) return -1;
+  return (int64_t)8 * R * R * R * (int64_t)sizeof(float);
+}
+
+int psdf_smooth_sdf(int32_t R, float sigma, const float* shat, float* s, void* s_half,
+                    void* stream) {
+  if (R < 2 || R > 1024) return fail(PSDF_EINVAL, "R=%d outside [2, 1024]", R);
+  if (!(sigma > 0.f) || !std::isfinite(sigma)) return fail(PSDF_EINVAL, "sigma must be finite > 0");
+  int rc;
+  if ((rc = check_f32(shat, "shat")) || (rc = check_f32(s, "s"))) return rc;
+  if (s_half && !aligned(s_half, 2)) return fail(PSDF_EALIGN, "s_half misaligned");
+  const size_t bs = (size_t)R * R * R * 4;
+  if (overlap(shat, bs, s, bs)) return fail(PSDF_EINVAL, "shat and s must not overlap");
+  return hip_status(psdf::launch_smooth(R, smooth_taps(sigma), shat, s,
+                                        static_cast<_Float16*>(s_half), false,
+                                        static_cast<hipStream_t>(stream)),
+                    "smooth_sdf launch");
+}
+
+int psdf_l2rel_loss(int64_t B, const float* rgb, const float* target, float* dL_drgb, float* loss,
+                    float lambda, float eps, float n_images, void* stream) {
+  int rc;
+  if (B < 0 || B > kMaxRays) return fail(PSDF_EINVAL, "B=%lld out of range", (long long)B);
+  if (!std::isfinite(lambda) || !(eps > 0.f) || !std::isfinite(eps) || !(n_images > 0.f) ||
+      !std::isfinite(n_images))
+    return fail(PSDF_EINVAL, "lambda finite, eps > 0 and n_images > 0 required");
+  if (B == 0) return ok();
+  if ((rc = check_f32(rgb, "rgb")) || (rc = check_f32(target, "target")) ||
+      (rc = check_f32(dL_drgb, "dL_drgb")))
+    return rc;
+  if (loss && !aligned(loss, 4)) return fail(PSDF_EALIGN, "loss misaligned");
+  return hip_status(psdf::launch_l2rel_loss(B, rgb, target, dL_drgb, loss, lambda, eps, n_images,
+                                            static_cast<hipStream_t>(stream)),
+                    "l2rel_loss launch");
+}
+
 int psdf_grid_step(const psdf_step_args* s, void* stream) {
   if (!s) return fail(PSDF_EINVAL, "args is NULL");
   if (s->struct_size != sizeof(psdf_step_args))
@@ -387,6 +436,32 @@ int psdf_grid_step(const psdf_step_args* s, void* stream) {
   if (s->losses && !aligned(s->losses, 4)) return fail(PSDF_EALIGN, "losses misaligned");
   if (s->sdf_bounds_out && !aligned(s->sdf_bounds_out, 8))
     return fail(PSDF_EALIGN, "sdf_bounds_out must be 8-byte aligned");
+  const bool ext = s->sdf_reg_flags != 0 || s->lambda_sdf != 0.f || s->lambda_normal != 0.f;
+  const bool smooth = (s->sdf_reg_flags & PSDF_STEP_SMOOTH) != 0;
+  if (ext) {
+    if (s->sdf_reg_flags & ~(PSDF_STEP_SMOOTH | PSDF_STEP_REG_WEIGHT))
+      return fail(PSDF_EINVAL, "unknown sdf_reg_flags 0x%x", s->sdf_reg_flags);
+    if (!std::isfinite(s->lambda_sdf) || !std::isfinite(s->lambda_normal))
+      return fail(PSDF_EINVAL, "lambda_sdf / lambda_normal must be finite");
+    if (!s->work || s->work_bytes < psdf_step_work_bytes(s->R))
+      return fail(PSDF_EINVAL, "the Sec. 3.3 regularisers need a work buffer of %lld bytes",
+                  (long long)psdf_step_work_bytes(s->R));
+    if (!aligned(s->work, 16)) return fail(PSDF_EALIGN, "work must be 16-byte aligned");
+    if (smooth) {
+      if (!(s->smooth_sigma > 0.f) || !std::isfinite(s->smooth_sigma))
+        return fail(PSDF_EINVAL, "smooth_sigma must be finite > 0");
+      if (!s->s_in || !s->s_out) return fail(PSDF_EINVAL, "PSDF_STEP_SMOOTH needs s_in and s_out");
+      if (!aligned(s->s_in, 16) || !aligned(s->s_out, 16))
+        return fail(PSDF_EALIGN, "s_in / s_out must be 16-byte aligned");
+      if (overlap(s->s_out, bs, s->sdf_out, bs) || overlap(s->s_out, bs, s->sdf_in, bs) ||
+          overlap(s->s_out, bs, s->s_in, bs))
+        return fail(PSDF_EINVAL, "s_out must not overlap sdf_in, sdf_out or s_in");
+    } else if (s->lambda_sdf != 0.f) {
+      return fail(PSDF_EINVAL, "lambda_sdf needs PSDF_STEP_SMOOTH (without it s = shat)");
+    }
+    if (s->losses_ext && !aligned(s->losses_ext, 4))
+      return fail(PSDF_EALIGN, "losses_ext misaligned");
+  }
 
   psdf::StepArgs a{};
   a.R = s->R;
@@ -431,6 +506,21 @@ int psdf_grid_step(const psdf_step_args* s, void* stream) {
   a.probes_half = s->probes_half_out;
   a.losses = s->losses;
   a.sdf_bounds = s->sdf_bounds_out;
+  if (ext) {
+    a.ext = 1;
+    a.losses_ext = s->losses_ext;
+    psdf::SdfRegArgs& r = a.reg;
+    r.smooth = smooth ? 1 : 0;
+    r.weighted = (s->sdf_reg_flags & PSDF_STEP_REG_WEIGHT) ? 1 : 0;
+    const double R = s->R;
+    r.lam_sdf = (float)(s->lambda_sdf / (R * R * R));
+    r.lam_eik = (float)(s->lambda_eik / ((R - 2) * (R - 2) * (R - 2)));
+    r.lam_nrm = s->R > 3 ? (float)(s->lambda_normal / (3.0 * (R - 2) * (R - 2) * (R - 3))) : 0.f;
+    r.taps = smooth_taps(smooth ? s->smooth_sigma : 1.f);
+    r.s_in = s->s_in;
+    r.s_out = s->s_out;
+    r.work = s->work;
+  }
   return hip_status(psdf::launch_grid_step(a, static_cast<hipStream_t>(stream)),
                     "grid_step launch");
 }

@@ -135,6 +135,35 @@ struct TraceArgs {
   float* out;
 };
 
+// 5 taps of the Gaussian G of the smoothed SDF
+struct SmoothTaps {
+  float w[5];
+};
+
+// SDF regularisers of Sec. 3.3 on the smoothed SDF (step_reg.hip)
+struct SdfRegArgs {
+  int R;
+  float h;
+  int smooth;    // 1: the parameters are shat, rendering reads s = G(shat)
+  int weighted;  // 1: (1 + 5 |s|)^-1 on the regularisers' gradients
+  float lam_sdf, lam_eik, lam_nrm;  // lambda divided by the count of its sum
+  SmoothTaps taps;
+  const float* s_in;   // G(shat) as rendered (smooth)
+  float* s_out;        // G(shat_out) (smooth)
+  void* work;          // 8 R^3 floats
+  // filled by the launcher
+  const float* shat;
+  const float* s;
+  const float* g_s;
+  float* nrm;
+  float* dg;
+  float* y;
+  float* t;
+  float* loss_eik;
+  float* loss_sdf;
+  float* loss_nrm;
+};
+
 struct StepArgs {
   int R, P, n_feat, n_pc, n_mlp;
   float h;
@@ -166,6 +195,9 @@ struct StepArgs {
   void* probes_half;
   float* losses;
   float* sdf_bounds;  // brick bounds of the new sdf (of sdf_half when set), nullable
+  int ext;            // 1: the SDF goes through the Sec. 3.3 regularisers of `reg`
+  SdfRegArgs reg;
+  float* losses_ext;  // nullable [2]: L_sdf, L_normal
 };
 
 // dtype codes as in the public header
@@ -186,6 +218,11 @@ hipError_t launch_l1_loss(int64_t B, const float* rgb, const float* target, floa
                           float* loss, hipStream_t s);
 hipError_t launch_grid_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_step_sdf(const StepArgs& a, hipStream_t s);
+hipError_t launch_l2rel_loss(int64_t B, const float* rgb, const float* target, float* dL,
+                             float* loss, float lambda, float eps, float n_images, hipStream_t s);
+hipError_t launch_step_sdf_reg(const StepArgs& a, hipStream_t s);
+hipError_t launch_smooth(int R, const SmoothTaps& w, const float* in, float* out, _Float16* half,
+                         bool transpose, hipStream_t s);
 hipError_t launch_sdf_bounds(const void* sdf, int R, int sdf_dt, float* bounds, hipStream_t s);
 
 }  // namespace psdf

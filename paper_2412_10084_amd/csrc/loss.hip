@@ -1,6 +1,6 @@
-// Photometric loss.  The paper uses a relatively weighted L2 (Eq. photo_loss);
-// this kernel computes its L1 form: L = mean over B x 3 of |rgb - target| and
-// dL/drgb = sign(rgb - target) / (3B), sign(0) = 0.
+// Photometric losses: the L1 form L = mean over B x 3 of |rgb - target| with
+// dL/drgb = sign(rgb - target) / (3B), sign(0) = 0; and the paper's relatively
+// weighted L2 (Eq. photo_loss).
 #include "device.h"
 #include "kernels.h"
 
@@ -90,6 +90,47 @@ hipError_t launch_l1_loss(int64_t B, const float* rgb, const float* target, floa
       hipLaunchKernelGGL(l1_loss_kernel<false>, dim3((unsigned)blocks), dim3(LBLOCK), 0, s, n,
                          scale, rgb, target, dL, loss);
   }
+  return hipGetLastError();
+}
+
+// Relatively weighted L2 (Eq. photo_loss with the per-pixel weight (max(c, c_gt) +
+// eps)^-1 on its gradient, scaled by lambda / n_images): per channel
+//   L = sc * sum (c - c_gt)^2 / (max(c, c_gt) + eps),  dL/dc = 2 sc (c - c_gt) / (max + eps),
+// the weight held constant.  Grid-stride over the 3B values, one atomic per block.
+__global__ void __launch_bounds__(LBLOCK) l2rel_loss_kernel(int64_t n, float sc, float eps,
+                                                            const float* rgb, const float* target,
+                                                            float* dL, float* loss) {
+  __shared__ float part[LBLOCK / 64];
+  float acc = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * LBLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * LBLOCK) {
+    const float c = rgb[i], t = target[i];
+    const float d = c - t;
+    const float w = 1.0f / (fmaxf(c, t) + eps);
+    acc += d * d * w;
+    dL[i] = 2.0f * sc * d * w;
+  }
+  if (loss) {
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float s = 0.f;
+      for (int w = 0; w < LBLOCK / 64; ++w) s += part[w];
+      atomic_add_f32(loss, s * sc);
+    }
+  }
+}
+
+hipError_t launch_l2rel_loss(int64_t B, const float* rgb, const float* target, float* dL,
+                             float* loss, float lambda, float eps, float n_images, hipStream_t s) {
+  const int64_t n = 3 * B;
+  if (loss) hipLaunchKernelGGL(zero1_kernel, dim3(1), dim3(64), 0, s, loss);
+  int64_t blocks = (n + 8 * LBLOCK - 1) / (8 * LBLOCK);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks > 0)
+    hipLaunchKernelGGL(l2rel_loss_kernel, dim3((unsigned)blocks), dim3(LBLOCK), 0, s, n,
+                       lambda / n_images, eps, rgb, target, dL, loss);
   return hipGetLastError();
 }
 

@@ -301,9 +301,20 @@ static void launch_tv(const TvArgs& t, int C, const StepArgs& a, hipStream_t s) 
   else hipLaunchKernelGGL(step_tv_any_kernel, grid, dim3(SBLOCK), 0, s, t, C, a);
 }
 
+__global__ void zero2_kernel(float* p) {
+  if (threadIdx.x < 2) p[threadIdx.x] = 0.f;
+}
+
 hipError_t launch_grid_step(const StepArgs& a, hipStream_t s) {
   if (a.losses) hipLaunchKernelGGL(zero3_kernel, dim3(1), dim3(64), 0, s, a.losses);
-  launch_step_sdf(a, s);
+  hipError_t e;
+  if (a.ext) {
+    if (a.losses_ext) hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(64), 0, s, a.losses_ext);
+    e = launch_step_sdf_reg(a, s);
+  } else {
+    e = launch_step_sdf(a, s);
+  }
+  if (e != hipSuccess) return e;
   TvArgs tf{a.R, a.lambda_tv_feat, a.lr_feat, a.feat_in, a.feat_out, a.g_feat, a.m_feat, a.v_feat,
             static_cast<_Float16*>(a.feat_half), a.losses ? a.losses + 1 : nullptr};
   launch_tv(tf, a.n_feat, a, s);

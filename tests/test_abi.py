@@ -171,16 +171,17 @@ def test_backward_workspace_validation():
 
 
 def _step_args(**kw):
-    names = [n for n, _ in ps._StepArgs._fields_]
     a = ps._StepArgs()
     a.struct_size = C.sizeof(ps._StepArgs)
     a.R, a.P, a.n_feat, a.n_pc, a.n_mlp, a.step = 8, 4, 3, 36, 227, 1
     a.lr_sdf = a.lr_feat = a.lr_probe = a.lr_mlp = 0.01
     a.beta1, a.beta2, a.eps = 0.9, 0.995, 1e-8
     base = 0x100000
-    for i, n in enumerate(names[17:]):
+    ptrs = [n for n, ty in ps._StepArgs._fields_ if ty is C.c_void_p]
+    for i, n in enumerate(ptrs):
         setattr(a, n, base + i * 0x100000)  # disjoint buffers
     a.sdf_half_out = a.feat_half_out = a.probes_half_out = a.losses = None
+    a.s_in = a.s_out = a.work = a.losses_ext = None  # Sec. 3.3 regularisers unused
     for k, v in kw.items():
         setattr(a, k, v)
     return a
@@ -225,6 +226,40 @@ def test_sdf_bounds_validation():
     assert L.psdf_sdf_bounds(64, 0, FAKE, FAKE + 4, None) == ps.EALIGN
     assert ps.n_bricks(2) == 1 and ps.n_bricks(9) == 1 and ps.n_bricks(10) == 2
     assert ps.n_bricks(256) == 32 and ps.n_bricks(257) == 32 and ps.n_bricks(258) == 33
+
+
+def test_grid_step_regulariser_validation():
+    """Sec. 3.3's regularisers: a work buffer of the stated size, the smoothed
+    fields with PSDF_STEP_SMOOTH, L_sdf only with smoothing, a positive width."""
+    L = ps.lib()
+    need = ps.step_work_bytes(8)
+    assert need == 8 * 8 ** 3 * 4
+    assert ps.lib().psdf_step_work_bytes(1) == -1
+    W = 0x7000000
+    assert L.psdf_grid_step(C.byref(_step_args(lambda_normal=0.1)), None) == ps.EINVAL
+    assert "work buffer" in ps.last_error()
+    assert L.psdf_grid_step(C.byref(_step_args(lambda_normal=0.1, work=W, work_bytes=need - 1)),
+                            None) == ps.EINVAL
+    assert L.psdf_grid_step(C.byref(_step_args(lambda_normal=0.1, work=W + 4, work_bytes=need)),
+                            None) == ps.EALIGN
+    assert L.psdf_grid_step(C.byref(_step_args(lambda_sdf=0.1, work=W, work_bytes=need)),
+                            None) == ps.EINVAL
+    assert "PSDF_STEP_SMOOTH" in ps.last_error()
+    sm = dict(sdf_reg_flags=ps.STEP_SMOOTH, work=W, work_bytes=need, smooth_sigma=1.0)
+    assert L.psdf_grid_step(C.byref(_step_args(**sm)), None) == ps.EINVAL  # no s_in / s_out
+    sm.update(s_in=0x8000000, s_out=0x9000000)
+    assert L.psdf_grid_step(C.byref(_step_args(**dict(sm, smooth_sigma=0.0))), None) == ps.EINVAL
+    assert L.psdf_grid_step(C.byref(_step_args(**dict(sm, sdf_reg_flags=8))), None) == ps.EINVAL
+    a = _step_args(**sm)
+    a.s_out = a.sdf_out
+    assert L.psdf_grid_step(C.byref(a), None) == ps.EINVAL
+    # smoothing and the relative L2 loss validate before launching
+    assert L.psdf_smooth_sdf(8, 0.0, FAKE, FAKE + 4096, None, None) == ps.EINVAL
+    assert L.psdf_smooth_sdf(8, 1.0, FAKE, FAKE + 16, None, None) == ps.EINVAL  # overlap
+    assert L.psdf_smooth_sdf(1, 1.0, FAKE, FAKE + 4096, None, None) == ps.EINVAL
+    assert L.psdf_l2rel_loss(10, FAKE, FAKE, FAKE, None, 40.0, 0.0, 1.0, None) == ps.EINVAL
+    assert L.psdf_l2rel_loss(10, FAKE, FAKE, FAKE, None, 40.0, 1e-3, 0.0, None) == ps.EINVAL
+    assert L.psdf_l2rel_loss(0, None, None, None, None, 40.0, 1e-3, 1.0, None) == ps.OK
 
 
 def test_grid_step_bounds_alignment():

@@ -160,7 +160,7 @@ def test_grid_step_matches_oracle(step, R, P):
     losses = t.empty(3, device="cuda")
     ps.grid_step(dp, dout, dg, dm_, dv_, step, opts, half_out=half, losses=losses)
     t.cuda.synchronize()
-    o_opts = oracle.StepOpts(**{k: getattr(opts, k) for k in vars(opts)})
+    o_opts = oracle.StepOpts(**{k: getattr(opts, k) for k in vars(oracle.StepOpts())})
     mcat = np.concatenate([m[k].reshape(-1) for k in keys])
     vcat = np.concatenate([v[k].reshape(-1) for k in keys])
     newp, m2, v2, L = oracle.grid_step(p, g, mcat, vcat, step, o_opts)
