@@ -420,6 +420,38 @@ def l2rel_loss(rgb, target, lam=40.0, eps=1e-3, n_images=1.0):
     return L, dL
 
 
+# ---------------------------------------------------------------------------
+# real-time path: per-voxel shading, then volume rendering of the colour field
+# ---------------------------------------------------------------------------
+def voxel_shade(of: OField, cam, band, flags=0):
+    """Colours [R, R, R, 3] of the nodes with |s| <= band seen from the camera
+    centre cam[3], 7, 11 (0 elsewhere)."""
+    cam = _d(cam)
+    centre = np.ascontiguousarray([cam[3], cam[7], cam[11]])
+    _check_field(of, flags)
+    col = np.zeros(of.sdf.shape + (3,))
+    fs = of.cstruct()
+    lib().orc_voxel_shade(C.byref(fs), C.c_int32(flags), _p(centre), C.c_double(band), _p(col))
+    return col
+
+
+def volume_render(of: OField, col, cam, W, H, n_samples, tau=64.0, skip_voxels=0.0,
+                  pixel_ids=None):
+    """Colours of pinhole pixels (ids py * W + px) volume-rendered through the colour
+    field `col` [R, R, R, 3]; returns (rgb, margin)."""
+    cam, col = _d(cam), _d(col)
+    if pixel_ids is None:
+        pixel_ids = np.arange(W * H, dtype=np.int64)
+    ids = np.ascontiguousarray(pixel_ids, dtype=np.int64)
+    out, mg = np.zeros((ids.size, 3)), np.zeros(ids.size)
+    fs = of.cstruct()
+    op = _Opts(n_samples, tau, skip_voxels, 0)
+    _ok(lib().orc_volume_render(C.byref(fs), _p(col), C.byref(op), _p(cam), C.c_int32(W),
+                                C.c_int32(H), ids.ctypes.data_as(_lp), C.c_int64(ids.size),
+                                _p(out), _p(mg)), "volume_render")
+    return out, mg
+
+
 def set_threads(n: int) -> None:
     """Threads of the oracle's OpenMP loops."""
     lib().orc_set_threads(C.c_int(n))

@@ -1147,3 +1147,86 @@ double orc_l2rel_loss(int64_t B, const double* rgb, const double* target, double
 /* threads of the OpenMP loops (the benchmark's CPU baseline times 1 and all) */
 void orc_set_threads(int n) { omp_set_num_threads(n); }
 int orc_max_threads(void) { return omp_get_max_threads(); }
+
+/* ===========================================================================
+ * Real-time render of the supplementary "Performance Analysis": a shading
+ * pass assigns a colour to every voxel, then a volume-rendering pass samples
+ * the SDF and that colour field along the rays.
+ * ======================================================================== */
+
+/* Colour of the voxels seen from a camera centre.  Readings: a voxel is a grid
+ * node x_m; it is shaded iff |s_m| <= band (the others hold colour 0); its view
+ * direction points from the node to the camera, v = (c - x_m) / |c - x_m|; its
+ * colour is the colour model at x_m (orc_shade).
+ *   col [R^3][3] out */
+void orc_voxel_shade(const orc_field* f, int32_t flags, const double cam_centre[3], double band,
+                     double* col) {
+  int R = f->R;
+  double h = 2.0 / (double)(R - 1);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t k = 0; k < R; ++k)
+    for (int64_t j = 0; j < R; ++j)
+      for (int64_t i = 0; i < R; ++i) {
+        int64_t n = (k * R + j) * R + i;
+        double* c = col + 3 * n;
+        c[0] = c[1] = c[2] = 0.0;
+        if (!(fabs(f->sdf[n]) <= band)) continue;
+        double x[3] = {-1.0 + i * h, -1.0 + j * h, -1.0 + k * h};
+        double v[3], vn = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          v[a] = cam_centre[a] - x[a];
+          vn += v[a] * v[a];
+        }
+        vn = sqrt(vn);
+        for (int a = 0; a < 3; ++a) v[a] /= vn;
+        orc_shade(f, flags, x, v, c, NULL);
+      }
+}
+
+/* Volume render of pinhole pixels (the camera layout of orc_sphere_trace):
+ * samples, skip rule and NeuS weights as orc_render_forward (the field's sdf),
+ * C_i = trilinear interpolation of the voxel colours col [R^3][3] at x_i.
+ *   out [n_pix][3], margin [n_pix] (nullable, as orc_render_forward) */
+int orc_volume_render(const orc_field* f, const double* col, const orc_render_opts* opt,
+                      const double* cam, int32_t W, int32_t H, const int64_t* pixel_ids,
+                      int64_t n_pix, double* out, double* margin) {
+  if (opt->n_samples < 2 || opt->n_samples > ORC_MAX_N) return -1;
+  int failed = 0;
+#pragma omp parallel
+  {
+  ray_state* r = ray_state_alloc(opt->n_samples);
+  if (!r) {
+#pragma omp atomic write
+    failed = 1;
+  }
+#pragma omp barrier
+  if (!failed) {
+#pragma omp for schedule(dynamic, 16)
+  for (int64_t q = 0; q < n_pix; ++q) {
+    int64_t id = pixel_ids[q];
+    int py = (int)(id / W), px = (int)(id % W);
+    (void)H;
+    double dc[3] = {(px + 0.5 - cam[14]) / cam[12], (py + 0.5 - cam[15]) / cam[13], 1.0};
+    double o[3], d[3];
+    for (int a = 0; a < 3; ++a) {
+      d[a] = cam[4 * a + 0] * dc[0] + cam[4 * a + 1] * dc[1] + cam[4 * a + 2] * dc[2];
+      o[a] = cam[4 * a + 3];
+    }
+    march(f, opt, o, d, r);
+    double c3[3] = {0, 0, 0};
+    if (r->hit) {
+      for (int i = 0; i < r->N; ++i) {
+        if (!(r->alpha[i] > 0.0)) continue;
+        double C[3];
+        orc_trilinear(col, f->R, 3, r->x[i], C);
+        for (int c = 0; c < 3; ++c) c3[c] += r->w[i] * C[c];
+      }
+    }
+    for (int c = 0; c < 3; ++c) out[3 * q + c] = c3[c];
+    if (margin) margin[q] = r->hit ? r->margin : INFINITY;
+  }
+  }
+  free(r);
+  }
+  return failed ? -1 : 0;
+}

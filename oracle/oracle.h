@@ -116,6 +116,11 @@ void orc_grid_step_ext(int R, int P, int n_feat, int n_pc, int n_mlp, double* sd
                        int64_t step, const orc_step_ext* opt, double losses[5], double* s_new);
 double orc_l2rel_loss(int64_t B, const double* rgb, const double* target, double lambda,
                       double eps, double n_images, double* dL_drgb);
+void orc_voxel_shade(const orc_field* f, int32_t flags, const double cam_centre[3], double band,
+                     double* col);
+int orc_volume_render(const orc_field* f, const double* col, const orc_render_opts* opt,
+                      const double* cam, int32_t W, int32_t H, const int64_t* pixel_ids,
+                      int64_t n_pix, double* out, double* margin);
 void orc_set_threads(int n);
 int orc_max_threads(void);
 int orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max_steps,
