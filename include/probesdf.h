@@ -415,6 +415,41 @@ typedef struct psdf_trace_opts {
 int psdf_render_sphere_trace(const psdf_field* field, const psdf_trace_opts* opts, int32_t V,
                              const float* cams, int32_t W, int32_t H, float* out, void* stream);
 
+/*
+ * Real-time render (supplementary "Performance Analysis": a shading pass assigns
+ * a colour to every voxel, a volume-rendering pass samples the SDF and the colour
+ * field along the rays).  Voxels are the grid nodes; only those near the surface
+ * are shaded.
+ *
+ * psdf_voxel_list -- the nodes with |sdf| <= band (FP32 comparison), as flat
+ * indices in list[0 .. *count) (order unspecified; at most `capacity` written,
+ * *count may exceed it).  View-independent: build it once per SDF.
+ *   sdf [R][R][R] FP32 or FP16 (sdf_dtype); list int32 [capacity]; count int32 [1]
+ *
+ * psdf_voxel_shade -- colour of each listed node seen from the camera centre
+ * (c2w[:, 3] of cam): v = (c - x) / |c - x|, the colour model of the field (FD
+ * normal, F_s, F_a(v), n.v, MLP, sigmoid) at the node.  Writes only the listed
+ * nodes of colour [R^3][4] (r, g, b, 0): FP32 (colour_dtype PSDF_F32, 16-byte
+ * aligned) or FP16 (PSDF_F16, 8-byte aligned); the caller zeroes it once, since
+ * nodes outside the band keep their values.  The workload colour model only.
+ *   cam [16] device FP32 (the layout of psdf_render_sphere_trace); list, count as
+ *   written by psdf_voxel_list with the same capacity
+ *
+ * psdf_volume_render -- one view of W x H pinhole pixels (camera layout of
+ * psdf_render_sphere_trace): per pixel ray, the samples, skip rule, brick skipping
+ * (field->sdf_bounds) and NeuS weights of psdf_render_forward, with the colour of
+ * sample i the trilinear interpolation of the colour grid at x_i.
+ *   out [H][W][3] FP32
+ */
+int psdf_voxel_list(int32_t R, int32_t sdf_dtype, const void* sdf, float band, int32_t* list,
+                    int64_t capacity, int32_t* count, void* stream);
+int psdf_voxel_shade(const psdf_field* field, int32_t flags, const float* cam, const int32_t* list,
+                     const int32_t* count, int64_t capacity, void* colour, int32_t colour_dtype,
+                     void* stream);
+int psdf_volume_render(const psdf_field* field, const psdf_render_opts* opts, const void* colour,
+                       int32_t colour_dtype, const float* cam, int32_t W, int32_t H, float* out,
+                       void* stream);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* psdf_last_error(void);
 

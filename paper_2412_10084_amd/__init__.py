@@ -35,6 +35,7 @@ def mlp_size(flags: int = 0, hidden: int = HIDDEN, layers: int = 1) -> int:
 EXPORTS = ("psdf_render_forward", "psdf_render_backward", "psdf_render_backward_noalloc",
            "psdf_l1_loss", "psdf_l2rel_loss", "psdf_grid_step", "psdf_step_work_bytes",
            "psdf_smooth_sdf", "psdf_render_sphere_trace", "psdf_sdf_bounds",
+           "psdf_voxel_list", "psdf_voxel_shade", "psdf_volume_render",
            "psdf_backward_workspace_bytes", "psdf_last_error", "psdf_abi_version")
 STEP_SMOOTH, STEP_REG_WEIGHT = 1, 2
 NOALLOC_SCRATCH_BYTES = 134217728
@@ -109,6 +110,9 @@ def lib():
         L.psdf_l2rel_loss.argtypes = [i64, vp, vp, vp, vp, f32, f32, f32, vp]
         L.psdf_step_work_bytes.argtypes = [i32]
         L.psdf_smooth_sdf.argtypes = [i32, f32, vp, vp, vp, vp]
+        L.psdf_voxel_list.argtypes = [i32, i32, vp, f32, vp, i64, vp, vp]
+        L.psdf_voxel_shade.argtypes = [vp, i32, vp, vp, vp, i64, vp, i32, vp]
+        L.psdf_volume_render.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
         L.psdf_grid_step.argtypes = [vp, vp]
         L.psdf_render_sphere_trace.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp]
         L.psdf_sdf_bounds.argtypes = [i32, i32, vp, vp, vp]
@@ -389,6 +393,37 @@ def sphere_trace(field: Field, cams, W: int, H: int, out, eps: float = 1e-3,
     to = _TraceOpts(C.sizeof(_TraceOpts), eps, max_steps, flags)
     _check(lib().psdf_render_sphere_trace(C.byref(fs), C.byref(to), cams.shape[0], _ptr(cams), W, H,
                                           _ptr(out), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# real-time render: per-voxel shading, then volume rendering of the colour field
+# ---------------------------------------------------------------------------
+def voxel_list(sdf, band: float, list_out, count_out, stream=None) -> None:
+    """Flat indices of the nodes with |sdf| <= band into list_out (int32), their
+    number into count_out (int32 [1])."""
+    import torch
+    if list_out.dtype != torch.int32 or count_out.dtype != torch.int32:
+        raise PsdfError(EINVAL, "list and count must be int32")
+    _check(lib().psdf_voxel_list(sdf.shape[0], Field._dt(sdf), _ptr(sdf), band, _ptr(list_out),
+                                 list_out.numel(), _ptr(count_out), _stream(stream)))
+
+
+def voxel_shade(field: Field, cam, list_in, count, colour, flags: int = 0, stream=None) -> None:
+    """Colours (R, R, R, 4) float32 or float16 of the listed nodes seen from the
+    camera centre of cam (16,)."""
+    fs = field.cstruct()
+    _check(lib().psdf_voxel_shade(C.byref(fs), flags, _ptr(_f32(cam, "cam")), _ptr(list_in),
+                                  _ptr(count), list_in.numel(), _ptr(colour),
+                                  Field._dt(colour), _stream(stream)))
+
+
+def volume_render(field: Field, opts: RenderOpts, colour, cam, W: int, H: int, out,
+                  stream=None) -> None:
+    """One W x H view volume-rendered through the colour grid; out (H, W, 3)."""
+    fs, op = field.cstruct(), opts.cstruct()
+    _check(lib().psdf_volume_render(C.byref(fs), C.byref(op), _ptr(colour), Field._dt(colour),
+                                    _ptr(_f32(cam, "cam")), W, H, _ptr(_f32(out, "out")),
+                                    _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

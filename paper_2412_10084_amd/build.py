@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libprobesdf.so")
 
 SOURCES = ["abi.cpp", "render_fwd.hip", "render_bwd.hip", "trace.hip", "loss.hip", "step.hip",
-           "bounds.hip", "bwd_split.hip", "step_sdf.hip", "step_reg.hip", "render_model.hip",
+           "bounds.hip", "bwd_split.hip", "step_sdf.hip", "step_reg.hip", "realtime.hip", "render_model.hip",
            # the paper-model kernel instances, several units so that they compile in parallel
            "render_model_bwd32_f32.hip", "render_model_bwd32_f16.hip", "render_model_bwd32_bf16.hip",
            "render_model_bwd16.hip", "render_model_fwd.hip"]

@@ -537,6 +537,95 @@ int psdf_sdf_bounds(int32_t R, int32_t sdf_dtype, const void* sdf, float* bounds
                     "sdf_bounds launch");
 }
 
+int psdf_voxel_list(int32_t R, int32_t sdf_dtype, const void* sdf, float band, int32_t* list,
+                    int64_t capacity, int32_t* count, void* stream) {
+  if (R < 2 || R > 1024) return fail(PSDF_EINVAL, "R=%d outside [2, 1024]", R);
+  if (sdf_dtype != PSDF_F32 && sdf_dtype != PSDF_F16)
+    return fail(PSDF_EUNSUPPORTED, "sdf_dtype %d", sdf_dtype);
+  if (!std::isfinite(band)) return fail(PSDF_EINVAL, "band must be finite");
+  if (!sdf || !count || (capacity > 0 && !list)) return fail(PSDF_EINVAL, "NULL argument");
+  if (capacity < 0 || capacity > (int64_t)R * R * R)
+    return fail(PSDF_EINVAL, "capacity outside [0, R^3]");
+  if (!aligned(sdf, sdf_dtype == PSDF_F32 ? 4 : 2) || !aligned(count, 4) ||
+      (list && !aligned(list, 4)))
+    return fail(PSDF_EALIGN, "sdf / list / count misaligned");
+  return hip_status(psdf::launch_voxel_list(R, sdf_dtype, sdf, band, list, capacity, count,
+                                            static_cast<hipStream_t>(stream)),
+                    "voxel_list launch");
+}
+
+static int check_colour(const void* colour, int32_t colour_dtype) {
+  if (colour_dtype != PSDF_F32 && colour_dtype != PSDF_F16)
+    return fail(PSDF_EUNSUPPORTED, "colour_dtype %d", colour_dtype);
+  if (!colour) return fail(PSDF_EINVAL, "colour is NULL");
+  if (!aligned(colour, colour_dtype == PSDF_F32 ? 16 : 8))
+    return fail(PSDF_EALIGN, "colour must be %d-byte aligned", colour_dtype == PSDF_F32 ? 16 : 8);
+  return PSDF_OK;
+}
+
+static psdf::RealtimeArgs realtime_args(const psdf_field* f, const float* cam) {
+  psdf::RealtimeArgs a{};
+  a.R = f->R;
+  a.P = f->P;
+  a.sdf = f->sdf;
+  a.feat = f->feat;
+  a.probes = f->probes;
+  a.mlp = f->mlp;
+  a.bounds = f->sdf_bounds;
+  a.cam = cam;
+  return a;
+}
+
+int psdf_voxel_shade(const psdf_field* field, int32_t flags, const float* cam, const int32_t* list,
+                     const int32_t* count, int64_t capacity, void* colour, int32_t colour_dtype,
+                     void* stream) {
+  int rc;
+  if ((rc = check_field(field))) return rc;
+  if (flags & ~7) return fail(PSDF_EINVAL, "unknown flags 0x%x (ablation flags only)", flags);
+  if (field->mlp_hidden != 16 || field->mlp_layers != 1)
+    return fail(PSDF_EUNSUPPORTED, "voxel shading takes the one-layer MLP of 16");
+  if ((rc = check_colour(colour, colour_dtype))) return rc;
+  if ((rc = check_f32(cam, "cam"))) return rc;
+  if (!count || capacity < 0 || capacity > (int64_t)field->R * field->R * field->R ||
+      (capacity > 0 && !list))
+    return fail(PSDF_EINVAL, "list / count / capacity out of range");
+  if (capacity == 0) return ok();
+  psdf::RealtimeArgs a = realtime_args(field, cam);
+  a.flags = flags;
+  a.list = list;
+  a.count = count;
+  a.cap = capacity;
+  a.colour = colour;
+  return hip_status(psdf::launch_voxel_shade(a, field->sdf_dtype, field->feat_dtype,
+                                             field->mlp_dtype, field->sh_coeffs, colour_dtype,
+                                             static_cast<hipStream_t>(stream)),
+                    "voxel_shade launch");
+}
+
+int psdf_volume_render(const psdf_field* field, const psdf_render_opts* opts, const void* colour,
+                       int32_t colour_dtype, const float* cam, int32_t W, int32_t H, float* out,
+                       void* stream) {
+  int rc;
+  if ((rc = check_field(field)) || (rc = check_opts(opts))) return rc;
+  if (opts->flags) return fail(PSDF_EINVAL, "volume rendering takes no render flags");
+  if ((rc = check_colour(colour, colour_dtype))) return rc;
+  if (W < 0 || H < 0 || W > 65535 * 16 || H > 65535 * 16)
+    return fail(PSDF_EINVAL, "bad image size W=%d H=%d", W, H);
+  if ((int64_t)W * H == 0) return ok();
+  if ((rc = check_f32(cam, "cam")) || (rc = check_f32(out, "out"))) return rc;
+  psdf::RealtimeArgs a = realtime_args(field, cam);
+  a.colour = const_cast<void*>(colour);
+  a.N = opts->n_samples;
+  a.tau = opts->tau;
+  a.skip_thr = opts->skip_voxels > 0.f ? (float)(opts->skip_voxels * (2.0 / (field->R - 1))) : 0.f;
+  a.W = W;
+  a.H = H;
+  a.out = out;
+  return hip_status(psdf::launch_volume_render(a, field->sdf_dtype, colour_dtype,
+                                               static_cast<hipStream_t>(stream)),
+                    "volume_render launch");
+}
+
 int psdf_render_sphere_trace(const psdf_field* field, const psdf_trace_opts* opts, int32_t V,
                              const float* cams, int32_t W, int32_t H, float* out, void* stream) {
   int rc;

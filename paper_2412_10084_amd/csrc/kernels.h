@@ -200,6 +200,25 @@ struct StepArgs {
   float* losses_ext;  // nullable [2]: L_sdf, L_normal
 };
 
+// real-time render: per-voxel shading and volume rendering (realtime.hip)
+struct RealtimeArgs {
+  int R, P, flags;
+  const void* sdf;
+  const void* feat;
+  const void* probes;
+  const float* mlp;
+  const float* bounds;  // brick bounds of sdf, nullable
+  const float* cam;     // [16] device: c2w (3x4), fx, fy, cx, cy
+  const int* list;      // nodes to shade, *count of them (at most cap)
+  const int* count;
+  int64_t cap;
+  void* colour;         // [R^3][4] FP32 or FP16 (r, g, b, 0)
+  int N;
+  float tau, skip_thr;
+  int W, H;
+  float* out;           // [H][W][3]
+};
+
 // dtype codes as in the public header
 hipError_t launch_render_forward(const RenderArgs& a, const BwdWs* tape, int sdf_dt, int feat_dt,
                                  int mlp_dt, int n_sh, hipStream_t s);
@@ -223,6 +242,11 @@ hipError_t launch_l2rel_loss(int64_t B, const float* rgb, const float* target, f
 hipError_t launch_step_sdf_reg(const StepArgs& a, hipStream_t s);
 hipError_t launch_smooth(int R, const SmoothTaps& w, const float* in, float* out, _Float16* half,
                          bool transpose, hipStream_t s);
+hipError_t launch_voxel_list(int R, int sdf_dt, const void* sdf, float band, int* list,
+                             int64_t cap, int* count, hipStream_t s);
+hipError_t launch_voxel_shade(const RealtimeArgs& a, int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
+                              int colour_dt, hipStream_t s);
+hipError_t launch_volume_render(const RealtimeArgs& a, int sdf_dt, int colour_dt, hipStream_t s);
 hipError_t launch_sdf_bounds(const void* sdf, int R, int sdf_dt, float* bounds, hipStream_t s);
 
 }  // namespace psdf

@@ -309,3 +309,25 @@ def test_binding_rejects_wrong_dtype_and_host_tensors():
         ps.render_forward(fld, ps.RenderOpts(), o, o, rgb)
     with pytest.raises(ps.PsdfError, match="float32"):
         ps.l1_loss(rgb, rgb.half(), rgb)
+
+
+def test_realtime_validation():
+    """Band list, voxel shading and volume rendering validate before launching."""
+    L = ps.lib()
+    assert L.psdf_voxel_list(1, 0, FAKE, 0.1, FAKE, 8, FAKE, None) == ps.EINVAL
+    assert L.psdf_voxel_list(8, 2, FAKE, 0.1, FAKE, 8, FAKE, None) == ps.EUNSUPPORTED
+    assert L.psdf_voxel_list(8, 0, FAKE, 0.1, FAKE, 513, FAKE, None) == ps.EINVAL  # > R^3
+    assert L.psdf_voxel_list(8, 0, FAKE, float("nan"), FAKE, 8, FAKE, None) == ps.EINVAL
+    assert L.psdf_voxel_list(8, 0, FAKE + 2, 0.1, FAKE, 8, FAKE, None) == ps.EALIGN
+    vs = L.psdf_voxel_shade
+    assert vs(C.byref(_field()), 8, FAKE, FAKE, FAKE, 16, FAKE, 0, None) == ps.EINVAL  # flags
+    assert vs(C.byref(_field()), 0, FAKE, FAKE, FAKE, 16, FAKE, 2, None) == ps.EUNSUPPORTED
+    assert vs(C.byref(_field()), 0, FAKE, FAKE, FAKE, 16, FAKE + 8, 0, None) == ps.EALIGN
+    assert vs(C.byref(_field(mlp_hidden=32, mlp_layers=2)), 0, FAKE, FAKE, FAKE, 16, FAKE, 0,
+              None) == ps.EUNSUPPORTED
+    assert vs(C.byref(_field()), 0, FAKE, FAKE, FAKE, 0, FAKE, 0, None) == ps.OK  # nothing listed
+    vr = L.psdf_volume_render
+    assert vr(C.byref(_field()), C.byref(_opts(flags=1)), FAKE, 0, FAKE, 8, 8, FAKE,
+              None) == ps.EINVAL
+    assert vr(C.byref(_field()), C.byref(_opts()), FAKE, 0, FAKE, -1, 8, FAKE, None) == ps.EINVAL
+    assert vr(C.byref(_field()), C.byref(_opts()), FAKE, 0, FAKE, 0, 8, FAKE, None) == ps.OK

@@ -278,7 +278,15 @@ WORKLOADS = {
     "iter512": Workload("iter512", 512, 128, 9, 128, 4.0, 64.0, 8, 512, 256, "f32", "f32", "f32"),
     # inference: FP16 grids 512^3 / 128^3, 16 views at 1920x1080, sphere tracing
     "trace512": Workload("trace512", 512, 128, 9, 0, 0.0, 64.0, 16, 1920, 1080, "f16", "f16", "f32"),
+    # real-time render: FP16 grids 512^3 / 128^3, one view at the paper's 1920x1163 window,
+    # voxels shaded within RT_BAND_VOXELS of the surface, then volume rendered (128
+    # samples, skip |s| > 4 voxels)
+    "rt512": Workload("rt512", 512, 128, 9, 128, 4.0, 64.0, 1, 1920, 1163, "f16", "f16", "f32"),
 }
+
+# shading band of the real-time render, in voxels: the skip threshold plus the two
+# voxels a trilinear corner can lie beyond an active sample (|grad s| ~ 1)
+RT_BAND_VOXELS = 6.0
 
 
 def workload_rays(wl: Workload, order: str = "image"):
