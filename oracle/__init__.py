@@ -28,7 +28,8 @@ class _Field(C.Structure):
     _fields_ = [("R", C.c_int32), ("P", C.c_int32), ("n_feat", C.c_int32), ("n_sh", C.c_int32),
                 ("n_ang", C.c_int32), ("hidden", C.c_int32), ("mlp_layers", C.c_int32),
                 ("sdf", _dp), ("feat", _dp),
-                ("probes", _dp), ("mlp", _dp)]
+                ("probes", _dp), ("mlp", _dp), ("tile_T", C.c_int32),
+                ("tile_index", C.POINTER(C.c_int32)), ("tile_feat", _dp)]
 
 
 class _Opts(C.Structure):
@@ -77,6 +78,7 @@ def lib():
         _lib.orc_mlp_size.restype = C.c_int64
         _lib.orc_l2rel_loss.restype = C.c_double
         _lib.orc_max_threads.restype = C.c_int
+        _lib.orc_plane_smooth.restype = C.c_double
     return _lib
 
 
@@ -102,10 +104,17 @@ class OField:
     n_ang: int = 4
     hidden: int = 16
     layers: int = 1
+    tile_T: int = 0                      # > 0: tri-plane features on 16^3-cell tiles
+    tile_index: np.ndarray = None        # int32 [T, T, T], -1 = empty tile
+    tile_feat: np.ndarray = None         # [slots, 3, 16, 16, n_feat]
 
     def cstruct(self) -> _Field:
+        ti = (self.tile_index.ctypes.data_as(C.POINTER(C.c_int32)) if self.tile_T
+              else C.POINTER(C.c_int32)())
+        tf = _p(self.tile_feat) if self.tile_T else _dp()
         return _Field(self.R, self.P, self.n_feat, self.n_sh, self.n_ang, self.hidden,
-                      self.layers, _p(self.sdf), _p(self.feat), _p(self.probes), _p(self.mlp))
+                      self.layers, _p(self.sdf), _p(self.feat), _p(self.probes), _p(self.mlp),
+                      self.tile_T, ti, tf)
 
     def n_inputs(self, flags: int = 0) -> int:
         return self.n_feat + self.n_ang + (6 if flags & FRESNEL_PAPER else 3)
@@ -138,8 +147,15 @@ def field_from(fld, half: bool = False, half_sdf: bool = False, mlp_round: str =
         import workloads as wl
         n_in = fld.feat.shape[-1] + fld.probes.shape[-1] + (6 if flags & FRESNEL_PAPER else 3)
         mlp = wl.round_mlp_weights(mlp, n_in, fld.hidden, fld.layers, mlp_round)
-    return make_field(sdf, feat, probes, mlp, n_sh=fld.n_sh, hidden=fld.hidden,
-                      layers=fld.layers)
+    of = make_field(sdf, feat, probes, mlp, n_sh=fld.n_sh, hidden=fld.hidden,
+                    layers=fld.layers)
+    tiles = getattr(fld, "tiles", None)
+    if tiles is not None:  # sparse tiles with tri-plane features
+        planes = tiles.planes.astype(np.float16) if half else tiles.planes
+        of.tile_T = tiles.T
+        of.tile_index = np.ascontiguousarray(tiles.index, dtype=np.int32)
+        of.tile_feat = _d(planes)
+    return of
 
 
 # ---------------------------------------------------------------------------
@@ -259,7 +275,8 @@ def render_backward(of: OField, rays_o, rays_d, dL_drgb, n_samples, tau=64.0, sk
                     flags=0):
     o, d, dL = _d(rays_o), _d(rays_d), _d(dL_drgb)
     B = o.shape[0]
-    g = dict(sdf=np.zeros_like(of.sdf), feat=np.zeros_like(of.feat),
+    g = dict(sdf=np.zeros_like(of.sdf),
+             feat=np.zeros_like(of.tile_feat if of.tile_T else of.feat),  # tiles: plane layout
              probes=np.zeros_like(of.probes), mlp=np.zeros_like(of.mlp))
     _check_field(of, flags)
     fs = of.cstruct()
@@ -450,6 +467,23 @@ def volume_render(of: OField, col, cam, W, H, n_samples, tau=64.0, skip_voxels=0
                                 C.c_int32(H), ids.ctypes.data_as(_lp), C.c_int64(ids.size),
                                 _p(out), _p(mg)), "volume_render")
     return out, mg
+
+
+def triplane(of: OField, x):
+    """(F_s at x, tile slot) of a tiled field."""
+    x = _d(x)
+    out = np.zeros(of.n_feat)
+    slot = lib().orc_triplane(C.byref(of.cstruct()), _p(x), _p(out))
+    return out, slot
+
+
+def plane_smooth(planes, lam):
+    """(loss, gradient) of the smoothness of the tri-plane features."""
+    planes = _d(planes)
+    g = np.zeros_like(planes)
+    L = lib().orc_plane_smooth(C.c_int64(planes.shape[0]), C.c_int(planes.shape[-1]), _p(planes),
+                               C.c_double(lam), _p(g))
+    return L, g
 
 
 def set_threads(n: int) -> None:

@@ -289,6 +289,9 @@ int orc_field_check(const orc_field* f, int32_t flags) {
   if (f->n_ang < 1 || f->n_ang > 16 || f->n_feat < 0) return -1;
   if (orc_n_inputs(f, flags) > MAXIN) return -1;
   if (f->hidden < 1 || f->hidden > MAXH || f->mlp_layers < 1 || f->mlp_layers > 2) return -1;
+  if (f->tile_T > 0 && (f->R != 16 * f->tile_T + 1 || f->n_feat > 64 || !f->tile_index ||
+                        !f->tile_feat))
+    return -1;
   return 0;
 }
 
@@ -309,6 +312,140 @@ int orc_field_check(const orc_field* f, int32_t flags) {
  * The reflection always uses the true n.v; ORC_NV_ONE only replaces the
  * incidence inputs.
  * ------------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------------
+ * Sparse tiles with tri-plane spatial features (Sec. 3.1: F_s = F_x (x) F_y (x)
+ * F_z from planes of the coarse tile; Sec. 4: tiles of 16^3 voxels holding
+ * 3 x 16 x 16 x n_s coefficients).  Readings: R = 16 T + 1 nodes, tile of a point
+ * = the tile of its trilinear cell; each plane is a 16 x 16 texture of the tile
+ * with texels at the cell centres, bilinear with clamping inside the tile (no
+ * reads across tiles); the three interpolated planes are multiplied channel by
+ * channel; a point in an empty tile is inactive (the skip rule of the sparse
+ * grid).  F_x is a function of (y, z), F_y of (x, z), F_z of (x, y).
+ * ------------------------------------------------------------------------- */
+/* slot of the tile holding x (-1: empty), and x in the tile's cell units [0, 16] */
+int orc_tile_of(const orc_field* f, const double x[3], double loc[3]) {
+  double h = 2.0 / (double)(f->R - 1);
+  int t[3];
+  for (int a = 0; a < 3; ++a) {
+    double u = (x[a] + 1.0) / h;
+    double k0 = floor(u);
+    if (k0 < 0.0) k0 = 0.0;
+    if (k0 > f->R - 2) k0 = f->R - 2;
+    t[a] = (int)k0 / 16;
+    loc[a] = u - 16.0 * t[a];
+  }
+  int T = f->tile_T;
+  return f->tile_index[((int64_t)t[2] * T + t[1]) * T + t[0]];
+}
+
+/* texel cell and weight along one plane axis */
+static void texel(double l, int* c0, double* w) {
+  double tau = clampd(l - 0.5, 0.0, 15.0);
+  double c = floor(tau);
+  if (c > 14.0) c = 14.0;
+  *c0 = (int)c;
+  *w = tau - c;
+}
+
+/* axes (u, v) of plane a */
+static const int plane_axes[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+
+/* bilinear corners of plane a at loc: texel indices and weights */
+static void plane_corners(const double loc[3], int a, int idx[4], double w[4]) {
+  int cu, cv;
+  double fu, fv;
+  texel(loc[plane_axes[a][0]], &cu, &fu);
+  texel(loc[plane_axes[a][1]], &cv, &fv);
+  idx[0] = cv * 16 + cu;
+  idx[1] = cv * 16 + cu + 1;
+  idx[2] = (cv + 1) * 16 + cu;
+  idx[3] = (cv + 1) * 16 + cu + 1;
+  w[0] = (1 - fu) * (1 - fv);
+  w[1] = fu * (1 - fv);
+  w[2] = (1 - fu) * fv;
+  w[3] = fu * fv;
+}
+
+/* F_s at x into out[n_feat] (0 in an empty tile); returns the tile slot */
+int orc_triplane(const orc_field* f, const double x[3], double* out) {
+  double loc[3];
+  int slot = orc_tile_of(f, x, loc);
+  int nf = f->n_feat;
+  for (int c = 0; c < nf; ++c) out[c] = slot >= 0 ? 1.0 : 0.0;
+  if (slot < 0) return slot;
+  for (int a = 0; a < 3; ++a) {
+    int idx[4];
+    double w[4];
+    plane_corners(loc, a, idx, w);
+    const double* pl = f->tile_feat + ((int64_t)slot * 3 + a) * 256 * nf;
+    for (int c = 0; c < nf; ++c) {
+      double v = 0.0;
+      for (int q = 0; q < 4; ++q) v += w[q] * pl[idx[q] * nf + c];
+      out[c] *= v;
+    }
+  }
+  return slot;
+}
+
+static void add_atomic(double* p, double v);
+
+/* reverse mode of orc_triplane: adds dF_s into the plane gradients g (tile layout) */
+static void triplane_backward(const orc_field* f, const double x[3], const double* dfs,
+                              double* g) {
+  double loc[3];
+  int slot = orc_tile_of(f, x, loc);
+  if (slot < 0) return;
+  int nf = f->n_feat;
+  double val[3][64];
+  int idx[3][4];
+  double w[3][4];
+  for (int a = 0; a < 3; ++a) {
+    plane_corners(loc, a, idx[a], w[a]);
+    const double* pl = f->tile_feat + ((int64_t)slot * 3 + a) * 256 * nf;
+    for (int c = 0; c < nf; ++c) {
+      double v = 0.0;
+      for (int q = 0; q < 4; ++q) v += w[a][q] * pl[idx[a][q] * nf + c];
+      val[a][c] = v;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    double* gp = g + ((int64_t)slot * 3 + a) * 256 * nf;
+    for (int c = 0; c < nf; ++c) {
+      double other = 1.0;
+      for (int b = 0; b < 3; ++b)
+        if (b != a) other *= val[b][c];
+      for (int q = 0; q < 4; ++q) add_atomic(&gp[idx[a][q] * nf + c], w[a][q] * other * dfs[c]);
+    }
+  }
+}
+
+/* Smoothness of the factorised features (Eq. smooth_features), mean-normalised:
+ * lambda / (n_slots 3 2 16 15 n_feat) * sum over every plane, both of its axes and
+ * channel of squared differences of neighbouring texels.  Adds the gradient into g;
+ * returns the loss. */
+double orc_plane_smooth(int64_t n_slots, int n_feat, const double* planes, double lambda,
+                        double* g) {
+  double sc = lambda / ((double)n_slots * 3 * 2 * 16 * 15 * n_feat);
+  double acc = 0.0;
+  for (int64_t p = 0; p < n_slots * 3; ++p) {
+    const double* pl = planes + p * 256 * n_feat;
+    double* gp = g + p * 256 * n_feat;
+    for (int v = 0; v < 16; ++v)
+      for (int u = 0; u < 16; ++u)
+        for (int dir = 0; dir < 2; ++dir) {
+          int u2 = u + (dir == 0), v2 = v + (dir == 1);
+          if (u2 > 15 || v2 > 15) continue;
+          for (int c = 0; c < n_feat; ++c) {
+            double d = pl[(v2 * 16 + u2) * n_feat + c] - pl[(v * 16 + u) * n_feat + c];
+            acc += d * d;
+            gp[(v2 * 16 + u2) * n_feat + c] += 2.0 * sc * d;
+            gp[(v * 16 + u) * n_feat + c] -= 2.0 * sc * d;
+          }
+        }
+  }
+  return sc * acc;
+}
+
 typedef struct {
   double g[3], gn, n[3], c, cin, arg[3];
   double z[MAXIN], pre[2 * MAXH], hid[2 * MAXH], out[3], C[3];
@@ -334,7 +471,8 @@ static void shade_full(const orc_field* f, int32_t flags, const double x[3], con
   if (flags & ORC_NO_FS) {
     for (int k = 0; k < nf; ++k) st->z[k] = 0.0;
   } else {
-    orc_trilinear(f->feat, f->R, nf, x, st->z);
+    if (f->tile_T > 0) orc_triplane(f, x, st->z);
+    else orc_trilinear(f->feat, f->R, nf, x, st->z);
   }
   /* angular features: interpolate the coefficients (Eq. sh_eval2), then
    * evaluate the basis */
@@ -444,6 +582,10 @@ static void march(const orc_field* f, const orc_render_opts* opt, const double* 
       if (i + 1 < N) r->margin = fmin(r->margin, fabs(fabs(r->s[i]) - thr));
     } else {
       r->active[i] = 1;
+    }
+    if (f->tile_T > 0) {
+      double loc[3];
+      if (orc_tile_of(f, r->x[i], loc) < 0) r->active[i] = 0;
     }
   }
   r->logT_final = orc_composite(N, r->s, r->active, opt->tau, r->alpha, r->T, r->w);
@@ -597,7 +739,10 @@ static void shade_backward(const orc_field* f, int32_t flags, const double x[3],
   mlp_backward(f->mlp, n_in, f->hidden, f->mlp_layers, st->z, st->pre, st->hid, dout, g_mlp,
                dz);
   /* spatial features */
-  if (!(flags & ORC_NO_FS)) scatter_tri(g_feat, f->R, nf, x, dz);
+  if (!(flags & ORC_NO_FS)) {
+    if (f->tile_T > 0) triplane_backward(f, x, dz, g_feat);
+    else scatter_tri(g_feat, f->R, nf, x, dz);
+  }
   /* probes: d/d b_ij = w_i Y_j dF_a */
   if (!(flags & ORC_NO_FA)) {
     double gb[MAXSH * 16];

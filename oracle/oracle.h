@@ -34,6 +34,11 @@ typedef struct {
   const double* feat;   /* [R][R][R][n_feat] */
   const double* probes; /* [P][P][P][n_sh][n_ang] */
   const double* mlp;    /* per hidden layer W_l[hidden][n_prev], b_l[hidden]; Wo[3][hidden], bo[3] */
+  /* sparse tiles (Sec. 3.1, Sec. 4): tile_T > 0 selects tri-plane spatial features on
+   * tiles of 16^3 cells, R = 16 tile_T + 1; feat is then unused */
+  int32_t tile_T;              /* tiles per axis, 0: dense features */
+  const int32_t* tile_index;   /* [T][T][T] slot of each tile, -1: empty (not allocated) */
+  const double* tile_feat;     /* [slots][3][16][16][n_feat]: planes F_x(y,z), F_y(x,z), F_z(x,y) */
 } orc_field;
 
 /* flags */
@@ -121,6 +126,10 @@ void orc_voxel_shade(const orc_field* f, int32_t flags, const double cam_centre[
 int orc_volume_render(const orc_field* f, const double* col, const orc_render_opts* opt,
                       const double* cam, int32_t W, int32_t H, const int64_t* pixel_ids,
                       int64_t n_pix, double* out, double* margin);
+int orc_tile_of(const orc_field* f, const double x[3], double loc[3]);
+int orc_triplane(const orc_field* f, const double x[3], double* out);
+double orc_plane_smooth(int64_t n_slots, int n_feat, const double* planes, double lambda,
+                        double* g);
 void orc_set_threads(int n);
 int orc_max_threads(void);
 int orc_sphere_trace(const orc_field* f, int32_t flags, double eps, int32_t max_steps,

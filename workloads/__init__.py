@@ -209,6 +209,52 @@ def random_field(seed: int, R: int, P: int, n_sh: int = 9, shape: str = "sphere"
                  layers=layers)
 
 
+@dataclass
+class Tiles:
+    """Sparse tiles of 16^3 cells with tri-plane spatial features: index [T, T, T]
+    (slot of each allocated tile, -1 empty) and planes [slots, 3, 16, 16, n_feat]
+    (F_x over (y, z), F_y over (x, z), F_z over (x, y), row-major [v][u])."""
+    T: int
+    index: np.ndarray
+    planes: np.ndarray
+
+
+TILE = 16  # cells per tile edge
+
+
+def tiled_field(seed: int, T: int, n_sh: int = 9, shape: str = "sphere", margin_voxels: float = 8.0,
+                plane_std: float = 0.1 ** (1.0 / 3.0), model: str = "workload") -> Field:
+    """A field on R = 16 T + 1 nodes whose spatial features are tri-planes on the
+    tiles that hold a node within margin_voxels voxels of the surface (others empty),
+    probes at the tile corners (P = T + 1).  Planes ~ N(0, plane_std), so their
+    channel product has std 0.1; draw order: planes, probes, MLP."""
+    R, P = TILE * T + 1, T + 1
+    rng = np.random.default_rng(seed)
+    sdf = sphere_sdf_nodes(R) if shape == "sphere" else torus_sdf_nodes(R)
+    h = 2.0 / (R - 1)
+    near = np.abs(sdf) <= margin_voxels * h
+    occ = np.zeros((T, T, T), bool)
+    for k in range(T):
+        for j in range(T):
+            for i in range(T):
+                occ[k, j, i] = near[TILE * k:TILE * k + TILE + 1, TILE * j:TILE * j + TILE + 1,
+                                    TILE * i:TILE * i + TILE + 1].any()
+    index = np.full((T, T, T), -1, np.int32)
+    index[occ] = np.arange(int(occ.sum()), dtype=np.int32)
+    planes = (rng.standard_normal((int(occ.sum()), 3, TILE, TILE, N_FEAT), dtype=np.float32)
+              * np.float32(plane_std))
+    probes = (rng.standard_normal((P, P, P, n_sh, N_ANG), dtype=np.float32) * np.float32(0.1))
+    if model == "workload":
+        hidden, layers, mlp = HIDDEN, 1, xavier_uniform_mlp(rng)
+    else:
+        hidden, layers = PAPER_HIDDEN, PAPER_LAYERS
+        mlp = xavier_uniform_mlp(rng, PAPER_N_IN, hidden, N_OUT, layers)
+    f = Field(R=R, P=P, n_sh=n_sh, sdf=sdf, feat=np.zeros((1, 1, 1, N_FEAT), np.float32),
+              probes=probes, mlp=mlp, hidden=hidden, layers=layers)
+    f.tiles = Tiles(T=T, index=index, planes=planes)
+    return f
+
+
 def round_half(a: np.ndarray) -> np.ndarray:
     """float32 -> float16, round to nearest even (numpy's cast)."""
     return a.astype(np.float16)
