@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define PSDF_ABI_VERSION 4
+#define PSDF_ABI_VERSION 5
 
 #define PSDF_OK 0
 #define PSDF_EINVAL (-1)       /* null pointer, bad size or shape, aliasing */
@@ -147,6 +147,19 @@ typedef struct psdf_field {
   const float* mlp;
   const float* sdf_bounds; /* nullable, see above */
   int32_t mlp_layers;      /* hidden layers of the MLP: 1 (mlp_hidden 16) or 2 (mlp_hidden 32) */
+  /* Sparse tiles (Sec. 3.1, Sec. 4).  tile_T > 0: the domain is T^3 tiles of 16^3
+   * cells (R = 16 T + 1); tile_index [T][T][T] (int32, device) gives each tile's
+   * slot or -1 for an empty tile; samples in empty tiles are inactive; the spatial
+   * features are tri-planes and `feat` points to [n_tiles][3][16][16][n_feat]:
+   * planes F_x over (y, z), F_y over (x, z), F_z over (x, y), rows [v][u], texels at
+   * the tile's cell centres, bilinear and clamped inside the tile, and
+   * F_s = F_x * F_y * F_z channel by channel.  The SDF stays dense, the probes sit
+   * at the tile corners (P = T + 1 is the paper's layout).  Tiled fields run on the
+   * paper colour model's kernels (its limits apply); the feature gradient has the
+   * plane layout.  tile_T = 0: dense features. */
+  int32_t tile_T;
+  const int32_t* tile_index;
+  int64_t n_tiles;
 } psdf_field;
 
 typedef struct psdf_render_opts {
@@ -353,6 +366,20 @@ typedef struct psdf_step_args {
                                   s = G(shat), G the 5^3 Gaussian of Sec. 3.3 */
 #define PSDF_STEP_REG_WEIGHT 2 /* the SDF regularisers' gradient at node m is weighted
                                   by 1 / (1 + 5 |s_m|) (Sec. 3.3) */
+
+/*
+ * psdf_plane_step -- optimiser step of the tri-plane features of sparse tiles:
+ * the smoothness of the factorised features (Eq. smooth_features), mean-
+ * normalised, L = lambda / (n_tiles 3 2 16 15 n_feat) * sum over every plane, both
+ * of its axes and channels of squared differences of neighbouring texels, plus the
+ * accumulated render gradient g, then bias-corrected Adam (as psdf_grid_step);
+ * out of place (in and out must not overlap); g is cleared.
+ *   in, out, g, m, v [n_tiles][3][16][16][n_feat] FP32 (n_feat = 3), 16-byte aligned
+ *   half_out nullable FP16 copy of out; loss nullable [1] (L of `in`)
+ */
+int psdf_plane_step(int64_t n_tiles, int32_t n_feat, const float* in, float* out, float* g,
+                    float* m, float* v, int64_t step, float lr, float beta1, float beta2,
+                    float eps, float lambda, void* half_out, float* loss, void* stream);
 
 /* Bytes of the workspace of a grid step that uses the Sec. 3.3 regularisers:
  * 8 R^3 floats; -1 if R is out of range. */

@@ -20,7 +20,7 @@ FLAG_NO_FS, FLAG_NO_FA, FLAG_NV_ONE = 1, 2, 4
 FLAG_SH_REFLECT, FLAG_FRESNEL_PAPER = 8, 16
 MODEL_MAX_SAMPLES = 513
 OK, EINVAL, EALIGN, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
-ABI_VERSION = 4
+ABI_VERSION = 5
 BWD_FROM_TAPE = 1
 BRICK = 8
 
@@ -35,7 +35,7 @@ def mlp_size(flags: int = 0, hidden: int = HIDDEN, layers: int = 1) -> int:
 EXPORTS = ("psdf_render_forward", "psdf_render_backward", "psdf_render_backward_noalloc",
            "psdf_l1_loss", "psdf_l2rel_loss", "psdf_grid_step", "psdf_step_work_bytes",
            "psdf_smooth_sdf", "psdf_render_sphere_trace", "psdf_sdf_bounds",
-           "psdf_voxel_list", "psdf_voxel_shade", "psdf_volume_render",
+           "psdf_voxel_list", "psdf_voxel_shade", "psdf_volume_render", "psdf_plane_step",
            "psdf_backward_workspace_bytes", "psdf_last_error", "psdf_abi_version")
 STEP_SMOOTH, STEP_REG_WEIGHT = 1, 2
 NOALLOC_SCRATCH_BYTES = 134217728
@@ -53,7 +53,8 @@ class _Field(C.Structure):
                 ("mlp_hidden", C.c_int32), ("sdf_dtype", C.c_int32), ("feat_dtype", C.c_int32),
                 ("mlp_dtype", C.c_int32), ("sdf", C.c_void_p), ("feat", C.c_void_p),
                 ("probes", C.c_void_p), ("mlp", C.c_void_p), ("sdf_bounds", C.c_void_p),
-                ("mlp_layers", C.c_int32)]
+                ("mlp_layers", C.c_int32), ("tile_T", C.c_int32), ("tile_index", C.c_void_p),
+                ("n_tiles", C.c_int64)]
 
 
 class _RenderOpts(C.Structure):
@@ -113,6 +114,8 @@ def lib():
         L.psdf_voxel_list.argtypes = [i32, i32, vp, f32, vp, i64, vp, vp]
         L.psdf_voxel_shade.argtypes = [vp, i32, vp, vp, vp, i64, vp, i32, vp]
         L.psdf_volume_render.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
+        L.psdf_plane_step.argtypes = [i64, i32, vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, f32,
+                                      vp, vp, vp]
         L.psdf_grid_step.argtypes = [vp, vp]
         L.psdf_render_sphere_trace.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp]
         L.psdf_sdf_bounds.argtypes = [i32, i32, vp, vp, vp]
@@ -188,6 +191,7 @@ class Field:
     bounds: object = None
     hidden: int = HIDDEN
     layers: int = 1
+    tiles: object = None  # int32 (T, T, T) tile index: feat holds tri-planes (n_tiles,3,16,16,3)
 
     @staticmethod
     def _dt(t) -> int:
@@ -204,7 +208,9 @@ class Field:
         return _Field(C.sizeof(_Field), R, P, self.feat.shape[-1], sh, self.probes.shape[-1],
                       self.hidden, self._dt(self.sdf), self._dt(self.feat), self.mlp_dtype,
                       _ptr(self.sdf), _ptr(self.feat), _ptr(self.probes), _ptr(self.mlp),
-                      _ptr(self.bounds), self.layers)
+                      _ptr(self.bounds), self.layers,
+                      0 if self.tiles is None else self.tiles.shape[0], _ptr(self.tiles),
+                      0 if self.tiles is None else self.feat.shape[0])
 
 
 @dataclass
@@ -333,6 +339,18 @@ def sdf_bounds(sdf, out=None, stream=None):
     return out
 
 
+def plane_step(planes_in, planes_out, grad, m, v, step: int, lr: float = 0.01,
+               beta1: float = 0.9, beta2: float = 0.995, eps: float = 1e-8,
+               lam: float = 0.05, half_out=None, loss=None, stream=None) -> None:
+    """Smoothness of the tri-plane features of sparse tiles + Adam (out of place)."""
+    for t, n in ((planes_in, "planes_in"), (planes_out, "planes_out"), (grad, "grad"), (m, "m"),
+                 (v, "v"), (loss, "loss")):
+        _f32(t, n)
+    _check(lib().psdf_plane_step(planes_in.shape[0], planes_in.shape[-1], _ptr(planes_in),
+                                 _ptr(planes_out), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1,
+                                 beta2, eps, lam, _ptr(half_out), _ptr(loss), _stream(stream)))
+
+
 def step_work_bytes(R: int) -> int:
     return int(lib().psdf_step_work_bytes(R))
 
@@ -447,7 +465,7 @@ def render(field: Field, opts: RenderOpts, rays_o, rays_d, tape_samples: Optiona
 
 def is_paper_model(field: Field, flags: int) -> bool:
     """True when the render runs the paper colour model's kernels (no tape)."""
-    return (field.hidden, field.layers) != (HIDDEN, 1) or bool(
+    return (field.hidden, field.layers) != (HIDDEN, 1) or field.tiles is not None or bool(
         flags & (FLAG_SH_REFLECT | FLAG_FRESNEL_PAPER))
 
 

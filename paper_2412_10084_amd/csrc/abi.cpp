@@ -66,6 +66,17 @@ int check_field(const psdf_field* f) {
     return fail(PSDF_EALIGN, "probes must be %d-byte aligned", f->feat_dtype == PSDF_F32 ? 16 : 8);
   if (f->sdf_bounds && !aligned(f->sdf_bounds, 8))
     return fail(PSDF_EALIGN, "sdf_bounds must be 8-byte aligned");
+  if (f->tile_T < 0) return fail(PSDF_EINVAL, "tile_T must be >= 0");
+  if (f->tile_T > 0) {
+    if (f->R != 16 * f->tile_T + 1)
+      return fail(PSDF_EINVAL, "tiled fields have R = 16 tile_T + 1 (R=%d, tile_T=%d)", f->R,
+                  f->tile_T);
+    if (!f->tile_index) return fail(PSDF_EINVAL, "tile_index is NULL");
+    if (!aligned(f->tile_index, 4)) return fail(PSDF_EALIGN, "tile_index misaligned");
+    if (f->n_tiles < 0 || f->n_tiles > (int64_t)f->tile_T * f->tile_T * f->tile_T ||
+        (double)f->n_tiles * 3 * 256 * f->n_feat >= 2147483648.0)
+      return fail(PSDF_EINVAL, "n_tiles out of range");
+  }
   return PSDF_OK;
 }
 
@@ -84,7 +95,7 @@ int check_opts(const psdf_render_opts* o) {
 // The paper's colour model (reflected SH argument, (1 - n.v)^0..5 inputs, or the
 // two-layer MLP of 32) runs on its own kernels, with these limits.
 bool paper_model(const psdf_field* f, int32_t flags) {
-  return f->mlp_hidden != 16 || f->mlp_layers != 1 ||
+  return f->mlp_hidden != 16 || f->mlp_layers != 1 || f->tile_T > 0 ||
          (flags & (PSDF_FLAG_SH_REFLECT | PSDF_FLAG_FRESNEL_PAPER)) != 0;
 }
 
@@ -133,6 +144,8 @@ psdf::RenderArgs render_args(const psdf_field* f, const psdf_render_opts* o, int
   a.probes = f->probes;
   a.mlp = f->mlp;
   a.bounds = f->sdf_bounds;
+  a.tile_index = f->tile_T > 0 ? f->tile_index : nullptr;
+  a.tile_T = f->tile_T;
   a.N = o->n_samples;
   a.tau = o->tau;
   a.skip_thr = o->skip_voxels > 0.f ? (float)(o->skip_voxels * (2.0 / (f->R - 1))) : 0.f;
@@ -400,6 +413,46 @@ int psdf_l2rel_loss(int64_t B, const float* rgb, const float* target, float* dL_
                     "l2rel_loss launch");
 }
 
+int psdf_plane_step(int64_t n_tiles, int32_t n_feat, const float* in, float* out, float* g,
+                    float* m, float* v, int64_t step, float lr, float beta1, float beta2,
+                    float eps, float lambda, void* half_out, float* loss, void* stream) {
+  if (n_feat != 3) return fail(PSDF_EUNSUPPORTED, "n_feat=%d (compiled: 3)", n_feat);
+  if (n_tiles < 0 || (double)n_tiles * 3 * 256 * n_feat >= 2147483648.0)
+    return fail(PSDF_EINVAL, "n_tiles out of range");
+  if (step < 1) return fail(PSDF_EINVAL, "step must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f) ||
+      !std::isfinite(lr) || !std::isfinite(lambda))
+    return fail(PSDF_EINVAL, "Adam hyper-parameters / lambda out of range");
+  if (n_tiles == 0) return ok();
+  const void* req[] = {in, out, g, m, v};
+  for (const void* p : req) {
+    if (!p) return fail(PSDF_EINVAL, "a plane step buffer is NULL");
+    if (!aligned(p, 16)) return fail(PSDF_EALIGN, "plane step buffers must be 16-byte aligned");
+  }
+  const size_t nb = (size_t)n_tiles * 3 * 256 * n_feat * 4;
+  if (overlap(in, nb, out, nb)) return fail(PSDF_EINVAL, "the plane step is out of place");
+  if (half_out && !aligned(half_out, 8)) return fail(PSDF_EALIGN, "half_out misaligned");
+  if (loss && !aligned(loss, 4)) return fail(PSDF_EALIGN, "loss misaligned");
+  psdf::PlaneStepArgs a{};
+  a.n_planes = 3 * n_tiles;
+  a.scale = (float)((double)lambda / ((double)n_tiles * 3 * 2 * 16 * 15 * n_feat));
+  a.lr = lr;
+  a.beta1 = beta1;
+  a.beta2 = beta2;
+  a.eps = eps;
+  a.bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  a.bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  a.in = in;
+  a.out = out;
+  a.g = g;
+  a.m = m;
+  a.v = v;
+  a.half = static_cast<_Float16*>(half_out);
+  a.loss = loss;
+  return hip_status(psdf::launch_plane_step(a, static_cast<hipStream_t>(stream)),
+                    "plane_step launch");
+}
+
 int psdf_grid_step(const psdf_step_args* s, void* stream) {
   if (!s) return fail(PSDF_EINVAL, "args is NULL");
   if (s->struct_size != sizeof(psdf_step_args))
@@ -582,8 +635,8 @@ int psdf_voxel_shade(const psdf_field* field, int32_t flags, const float* cam, c
   int rc;
   if ((rc = check_field(field))) return rc;
   if (flags & ~7) return fail(PSDF_EINVAL, "unknown flags 0x%x (ablation flags only)", flags);
-  if (field->mlp_hidden != 16 || field->mlp_layers != 1)
-    return fail(PSDF_EUNSUPPORTED, "voxel shading takes the one-layer MLP of 16");
+  if (field->mlp_hidden != 16 || field->mlp_layers != 1 || field->tile_T > 0)
+    return fail(PSDF_EUNSUPPORTED, "voxel shading takes the one-layer MLP of 16 and dense features");
   if ((rc = check_colour(colour, colour_dtype))) return rc;
   if ((rc = check_f32(cam, "cam"))) return rc;
   if (!count || capacity < 0 || capacity > (int64_t)field->R * field->R * field->R ||
@@ -639,8 +692,9 @@ int psdf_render_sphere_trace(const psdf_field* field, const psdf_trace_opts* opt
     return fail(PSDF_EINVAL, "trace opts out of range");
   if (V < 0 || W < 0 || H < 0 || V > 65535 || W > 65535 * 16 || H > 65535 * 16)
     return fail(PSDF_EINVAL, "bad image size V=%d W=%d H=%d", V, W, H);
-  if (field->mlp_hidden != 16 || field->mlp_layers != 1)
-    return fail(PSDF_EUNSUPPORTED, "sphere tracing shades with the one-layer MLP of 16");
+  if (field->mlp_hidden != 16 || field->mlp_layers != 1 || field->tile_T > 0)
+    return fail(PSDF_EUNSUPPORTED,
+                "sphere tracing shades with the one-layer MLP of 16 and dense features");
   if ((int64_t)V * W * H == 0) return ok();
   if ((rc = check_f32(cams, "cams")) || (rc = check_f32(out, "out"))) return rc;
   psdf::TraceArgs a{};

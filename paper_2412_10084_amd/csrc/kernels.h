@@ -35,6 +35,9 @@ struct RenderArgs {
   float* g_probes;
   float* g_mlp;
   const int* todo;  // backward: nonzero entries select the 64-ray waves to run; nullptr = all
+  // sparse tiles with tri-plane features (paper-model kernels): feat holds the planes
+  const int* tile_index;  // [T^3] slot or -1; nullptr = dense features
+  int tile_T;
 };
 
 // One shaded sample of the entry-parallel backward (160 bytes).
@@ -219,6 +222,20 @@ struct RealtimeArgs {
   float* out;           // [H][W][3]
 };
 
+// optimiser step of the tri-plane features of sparse tiles
+struct PlaneStepArgs {
+  int64_t n_planes;  // 3 per allocated tile
+  float scale;       // lambda / (slots 3 2 16 15 NF)
+  float lr, beta1, beta2, eps, bc1, bc2;
+  const float* in;
+  float* out;
+  float* g;
+  float* m;
+  float* v;
+  _Float16* half;  // nullable
+  float* loss;     // nullable [1]
+};
+
 // dtype codes as in the public header
 hipError_t launch_render_forward(const RenderArgs& a, const BwdWs* tape, int sdf_dt, int feat_dt,
                                  int mlp_dt, int n_sh, hipStream_t s);
@@ -247,6 +264,7 @@ hipError_t launch_voxel_list(int R, int sdf_dt, const void* sdf, float band, int
 hipError_t launch_voxel_shade(const RealtimeArgs& a, int sdf_dt, int feat_dt, int mlp_dt, int n_sh,
                               int colour_dt, hipStream_t s);
 hipError_t launch_volume_render(const RealtimeArgs& a, int sdf_dt, int colour_dt, hipStream_t s);
+hipError_t launch_plane_step(const PlaneStepArgs& a, hipStream_t s);
 hipError_t launch_sdf_bounds(const void* sdf, int R, int sdf_dt, float* bounds, hipStream_t s);
 
 }  // namespace psdf

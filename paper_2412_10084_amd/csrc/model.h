@@ -58,6 +58,107 @@ __device__ __forceinline__ void sh_grad(float x, float y, float z, float (*dY)[3
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sparse tiles of 16^3 cells with tri-plane spatial features (Sec. 3.1, Sec. 4):
+// F_s = F_x(y, z) * F_y(x, z) * F_z(x, y) channel by channel, each plane a 16 x 16
+// texture of its tile (texels at the cell centres, bilinear, clamped inside the
+// tile), planes [slots][3][16][16][NF]; a point lies in the tile of its trilinear
+// cell; tile_index [T][T][T] holds each tile's slot or -1 (empty).
+// ---------------------------------------------------------------------------
+struct Tiles {
+  const int* __restrict__ index;  // nullptr: dense features
+  int T;
+};
+
+// slot of the tile holding x (-1: empty), and x in that tile's cell units
+__device__ __forceinline__ int tile_slot(const Tiles& tl, int R, double inv_h, const double x[3],
+                                         float loc[3]) {
+  int t[3];
+  const double kmax = (double)(R - 2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = (x[a] + 1.0) * inv_h;
+    const double k0 = fmin(fmax(floor(u), 0.0), kmax);
+    t[a] = (int)k0 >> 4;
+    loc[a] = (float)(u - 16.0 * t[a]);
+  }
+  return tl.index[(t[2] * tl.T + t[1]) * tl.T + t[0]];
+}
+
+// texel cell and weight of a tile coordinate along one plane axis
+__device__ __forceinline__ void plane_texel(float l, int& c0, float& f) {
+  const float tau = fminf(fmaxf(l - 0.5f, 0.0f), 15.0f);
+  const float c = fminf(floorf(tau), 14.0f);
+  c0 = (int)c;
+  f = tau - c;
+}
+
+// bilinear value of plane a of a tile (all NF channels), its 4 texels and weights
+template <typename FT>
+__device__ __forceinline__ void plane_lookup(const FT* __restrict__ planes, int slot, int a,
+                                             const float loc[3], float val[NF], int idx[4],
+                                             float w[4]) {
+  const int ua = a == 0 ? 1 : 0, va = a == 2 ? 1 : 2;  // plane axes (y,z), (x,z), (x,y)
+  int cu, cv;
+  float fu, fv;
+  plane_texel(loc[ua], cu, fu);
+  plane_texel(loc[va], cv, fv);
+  idx[0] = cv * 16 + cu;
+  idx[1] = idx[0] + 1;
+  idx[2] = idx[0] + 16;
+  idx[3] = idx[0] + 17;
+  w[0] = (1.f - fu) * (1.f - fv);
+  w[1] = fu * (1.f - fv);
+  w[2] = (1.f - fu) * fv;
+  w[3] = fu * fv;
+  const int base = (slot * 3 + a) * 256;
+#pragma unroll
+  for (int ch = 0; ch < NF; ++ch) {
+    float acc = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = fmaf(w[q], ld1(planes, (base + idx[q]) * NF + ch), acc);
+    val[ch] = acc;
+  }
+}
+
+template <typename FT>
+__device__ __forceinline__ void triplane_fs(const FT* __restrict__ planes, int slot,
+                                            const float loc[3], float fs[NF]) {
+#pragma unroll
+  for (int ch = 0; ch < NF; ++ch) fs[ch] = 1.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float val[NF], w[4];
+    int idx[4];
+    plane_lookup(planes, slot, a, loc, val, idx, w);
+#pragma unroll
+    for (int ch = 0; ch < NF; ++ch) fs[ch] *= val[ch];
+  }
+}
+
+// reverse mode: dF_s into the plane gradient g (FP32 atomics, 36 per sample)
+template <typename FT>
+__device__ __forceinline__ void triplane_scatter(const FT* __restrict__ planes, int slot,
+                                                 const float loc[3], const float dfs[NF],
+                                                 float* __restrict__ g) {
+  float val[3][NF], w[3][4];
+  int idx[3][4];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) plane_lookup(planes, slot, a, loc, val[a], idx[a], w[a]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int base = (slot * 3 + a) * 256;
+#pragma unroll
+    for (int ch = 0; ch < NF; ++ch) {
+      const float other = val[(a + 1) % 3][ch] * val[(a + 2) % 3][ch];
+      const float d = dfs[ch] * other;
+      if (d == 0.f) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) atomic_add_f32(g + (base + idx[a][q]) * NF + ch, w[a][q] * d);
+    }
+  }
+}
+
 // shading state of one sample kept for its reverse mode
 template <int NSH>
 struct ModelShade {
@@ -71,7 +172,7 @@ struct ModelShade {
 template <typename ST, typename FT, int NSH>
 __device__ __forceinline__ void model_inputs(const ST* __restrict__ sdf, const FT* __restrict__ feat,
                                              const FT* __restrict__ probes, const Geo& G,
-                                             const double x[3], const float v[3],
+                                             const Tiles& tl, const double x[3], const float v[3],
                                              ModelShade<NSH>& S) {
   const Cell cs = cell_d(x, G.R, G.inv_h);
   if (!sdf_normal_cross(sdf, G, x, cs, S.nm)) sdf_normal(sdf, G, x, S.nm);
@@ -87,7 +188,11 @@ __device__ __forceinline__ void model_inputs(const ST* __restrict__ sdf, const F
   sh_basis<NSH>(S.arg[0], S.arg[1], S.arg[2], S.Y);
 #pragma unroll
   for (int j = 0; j < MNIN; ++j) S.z[j] = 0.0f;
-  if (!(G.flags & FLAG_NO_FS)) {
+  if (!(G.flags & FLAG_NO_FS) && tl.index) {
+    float loc[3];
+    const int slot = tile_slot(tl, G.R, G.inv_h, x, loc);
+    if (slot >= 0) triplane_fs(feat, slot, loc, S.z);
+  } else if (!(G.flags & FLAG_NO_FS)) {
     float w[8];
     corner_w(cs, w);
 #pragma unroll

@@ -53,12 +53,21 @@ __device__ __forceinline__ float sdf_at(const ST* __restrict__ sdf, const Geo& G
   return tri1(sdf, G.R, cell_d(x, G.R, G.inv_h));
 }
 
+// whether sample i lies in an allocated tile (always, with dense features)
+__device__ __forceinline__ bool in_tile(const Tiles& tl, const Geo& G, const RayD& r, int i) {
+  if (!tl.index) return true;
+  double x[3];
+  float loc[3];
+  sample_pos(r, sample_t(r, i), x);
+  return tile_slot(tl, G.R, G.inv_h, x, loc) >= 0;
+}
+
 // The ray's samples: opacity, transmittance and the list of shaded samples.
 // Returns the number of entries; logT = log T after the last sample.
 template <typename ST>
 __device__ __forceinline__ int model_march(const ST* __restrict__ sdf, const RenderArgs& a,
-                                           const Geo& G, const RayD& r, int lane, ModelEntries& E,
-                                           float& logT) {
+                                           const Geo& G, const Tiles& tl, const RayD& r, int lane,
+                                           ModelEntries& E, float& logT) {
   int n = 0;
   float carry = 0.0f;
   const int N = a.N;
@@ -67,7 +76,9 @@ __device__ __forceinline__ int model_march(const ST* __restrict__ sdf, const Ren
     const float s_i = i < N ? sdf_at(sdf, G, r, i) : 0.0f;
     float s_n = __shfl_down(s_i, 1, 64);
     if (lane == 63) s_n = c0 + 64 < N ? sdf_at(sdf, G, r, c0 + 64) : 0.0f;
-    const bool act = i < N - 1 && (a.skip_thr <= 0.f || fabsf(s_i) <= a.skip_thr);
+    // samples in empty tiles are inactive (the skip rule of the sparse grid)
+    const bool act = i < N - 1 && (a.skip_thr <= 0.f || fabsf(s_i) <= a.skip_thr) &&
+                     in_tile(tl, G, r, i);
     float dl = 0.0f;
     bool sh = false;
     if (act) {
@@ -112,6 +123,7 @@ __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per
   const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
   cfloat* __restrict__ W = const_mlp(a.mlp);
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
+  const Tiles tl{a.tile_index, a.tile_T};
   const int nin = model_n_in(a.flags);
   int64_t r0, r1;
   wave_rays(a.B, per_wave, r0, r1);
@@ -122,7 +134,7 @@ __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per
                                  a.N, r);
     float rgb[3] = {0.f, 0.f, 0.f}, depth = 0.f, wsum = 0.f, logT = 0.f;
     if (hit) {
-      const int n = model_march(sdf, a, G, r, lane, E, logT);
+      const int n = model_march(sdf, a, G, tl, r, lane, E, logT);
       wave_sync();
       const float v[3] = {(float)-r.d[0], (float)-r.d[1], (float)-r.d[2]};
       for (int b0 = 0; b0 < n; b0 += 64) {
@@ -133,7 +145,7 @@ __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per
           double x[3];
           sample_pos(r, sample_t(r, i), x);
           ModelShade<NSH> S;
-          model_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, S);
+          model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
           float pre[L * H], out[3];
           model_mlp_fwd<M, H, L>(W, nin, S.z, pre, out);
           w = E.w[e];
@@ -196,6 +208,7 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
   const FT* __restrict__ probes = static_cast<const FT*>(a.probes);
   cfloat* __restrict__ W = const_mlp(a.mlp);
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
+  const Tiles tl{a.tile_index, a.tile_T};
   const int nin = model_n_in(a.flags);
   const bool reflect = (G.flags & FLAG_SH_REFLECT) && !(G.flags & FLAG_NO_FA);
   ModelDw<H, L> D;
@@ -211,7 +224,7 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
                      a.rays_d[3 * ray], a.rays_d[3 * ray + 1], a.rays_d[3 * ray + 2], a.N, r))
       continue;
     float logT;
-    const int n = model_march(sdf, a, G, r, lane, E, logT);
+    const int n = model_march(sdf, a, G, tl, r, lane, E, logT);
     if (n == 0) continue;
     any = true;
     wave_sync();
@@ -223,7 +236,7 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
         double x[3];
         sample_pos(r, sample_t(r, E.i[e]), x);
         ModelShade<NSH> S;
-        model_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, S);
+        model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
         float pre[L * H], out[3];
         model_mlp_fwd<M, H, L>(W, nin, S.z, pre, out);
 #pragma unroll
@@ -266,7 +279,7 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
       if (ve) {
         i = E.i[e];
         sample_pos(r, sample_t(r, i), x);
-        model_inputs<ST, FT, NSH>(sdf, feat, probes, G, x, v, S);
+        model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
         model_mlp_fwd<M, H, L>(W, nin, S.z, pre, out);
         const float w = E.w[e];
 #pragma unroll
@@ -320,9 +333,18 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
         sdf_patch_flush(Ls.u.sc, Ls.k0, nb, lane, G.R, a.g_sdf);
         wave_sync();
       }
-      if (!(G.flags & FLAG_NO_FS) && a.g_feat)
-        feat_scatter_wave(Ls.u.sc, Ls.fb, ve, cell_d(x, G.R, G.inv_h), dz, nb, lane, G.R,
-                          a.g_feat);
+      if (!(G.flags & FLAG_NO_FS) && a.g_feat) {
+        if (tl.index) {
+          if (ve) {
+            float loc[3];
+            const int slot = tile_slot(tl, G.R, G.inv_h, x, loc);
+            if (slot >= 0) triplane_scatter(feat, slot, loc, dz, a.g_feat);
+          }
+        } else {
+          feat_scatter_wave(Ls.u.sc, Ls.fb, ve, cell_d(x, G.R, G.inv_h), dz, nb, lane, G.R,
+                            a.g_feat);
+        }
+      }
       if (!(G.flags & FLAG_NO_FA) && a.g_probes) {
         probe_acc_clear<NSH>(Ls.u.pa, lane);
         probe_scatter_wave<NSH>(Ls.u.pa, lane, ve,

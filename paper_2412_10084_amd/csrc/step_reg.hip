@@ -299,3 +299,60 @@ hipError_t launch_step_sdf_reg(const StepArgs& a, hipStream_t s) {
 }
 
 }  // namespace psdf
+
+// ---------------------------------------------------------------------------
+// Optimiser step of the tri-plane features of sparse tiles: the smoothness of the
+// factorised features (Eq. smooth_features: lambda / (slots 3 2 16 15 NF) times the
+// squared differences of neighbouring texels of every plane) and Adam; one block
+// per 16 x 16 plane, the plane held in LDS.  Out of place (the stencil reads
+// neighbours); the gradient is cleared.
+// ---------------------------------------------------------------------------
+namespace psdf {
+
+__global__ void __launch_bounds__(256) plane_step_kernel(PlaneStepArgs a) {
+  constexpr int NT = 256 * NF;  // values of one plane
+  __shared__ float pl[NT];
+  const int64_t base = (int64_t)blockIdx.x * NT;
+  for (int e = threadIdx.x; e < NT; e += 256) pl[e] = a.in[base + e];
+  __syncthreads();
+  float loss = 0.f;
+  for (int e = threadIdx.x; e < NT; e += 256) {
+    const int t = e / NF, u = t & 15, v = t >> 4;
+    const float val = pl[e];
+    float gr = 0.f;
+    if (u > 0) gr += val - pl[e - NF];
+    if (v > 0) gr += val - pl[e - 16 * NF];
+    if (u < 15) {
+      const float d = pl[e + NF] - val;
+      gr -= d;
+      loss += d * d;
+    }
+    if (v < 15) {
+      const float d = pl[e + 16 * NF] - val;
+      gr -= d;
+      loss += d * d;
+    }
+    const float G = a.g[base + e] + 2.0f * a.scale * gr;
+    float m = a.m[base + e], vv = a.v[base + e];
+    const float p = adam_update_f(val, G, m, vv, a.lr, a.beta1, a.beta2, a.eps, a.bc1, a.bc2);
+    a.m[base + e] = m;
+    a.v[base + e] = vv;
+    a.out[base + e] = p;
+    if (a.half) a.half[base + e] = (_Float16)p;
+    if (a.g[base + e] != 0.f) a.g[base + e] = 0.f;
+  }
+  if (a.loss) block_add(loss, a.loss, a.scale);
+}
+
+__global__ void zero1_plane_kernel(float* p) {
+  if (threadIdx.x == 0) p[0] = 0.f;
+}
+
+hipError_t launch_plane_step(const PlaneStepArgs& a, hipStream_t s) {
+  if (a.loss) hipLaunchKernelGGL(zero1_plane_kernel, dim3(1), dim3(64), 0, s, a.loss);
+  if (a.n_planes > 0)
+    hipLaunchKernelGGL(plane_step_kernel, dim3((unsigned)a.n_planes), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace psdf

@@ -331,3 +331,27 @@ def test_realtime_validation():
               None) == ps.EINVAL
     assert vr(C.byref(_field()), C.byref(_opts()), FAKE, 0, FAKE, -1, 8, FAKE, None) == ps.EINVAL
     assert vr(C.byref(_field()), C.byref(_opts()), FAKE, 0, FAKE, 0, 8, FAKE, None) == ps.OK
+
+
+def test_tile_and_plane_step_validation():
+    L = ps.lib()
+    assert _fwd(_field(tile_T=1), _opts(), 10) == ps.EINVAL  # R must be 16 T + 1
+    assert _fwd(_field(R=65, tile_T=4), _opts(), 10) == ps.EINVAL  # no tile index
+    assert _fwd(_field(R=65, tile_T=4, tile_index=FAKE + 2), _opts(), 10) == ps.EALIGN
+    assert _fwd(_field(R=65, tile_T=4, tile_index=FAKE, n_tiles=65), _opts(), 10) == ps.EINVAL
+    # tiled fields take the paper colour model's kernels and their limits
+    assert _fwd(_field(R=65, tile_T=4, tile_index=FAKE, n_tiles=8, sh_coeffs=4), _opts(),
+                10) == ps.EUNSUPPORTED
+    ps_ = L.psdf_plane_step
+    args = dict(n=2, nf=3, i=FAKE, o=FAKE * 64, g=FAKE * 128, m=FAKE * 192, v=FAKE * 256)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return ps_(a["n"], a["nf"], a["i"], a["o"], a["g"], a["m"], a["v"], kw.get("step", 1),
+                   0.01, 0.9, 0.995, 1e-8, 0.05, None, None, None)
+
+    assert call(nf=4) == ps.EUNSUPPORTED
+    assert call(step=0) == ps.EINVAL
+    assert call(o=FAKE + 16) == ps.EINVAL  # in / out overlap
+    assert call(m=FAKE * 192 + 4) == ps.EALIGN
+    assert call(n=0) == ps.OK

@@ -1,0 +1,147 @@
+"""GPU parity of the sparse tiles with tri-plane spatial features (Sec. 3.1
+F_s = F_x (x) F_y (x) F_z, Sec. 4 tiles of 16^3 voxels) against the FP64 oracle:
+forward colour and every gradient group (the plane gradients element-wise), with
+and without the skip rule, the workload and paper colour models, FP16 planes,
+empty tiles, a 256^3-class launch on sampled rays, and the plane optimiser step."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_common import (F16_COLOR_ABS, FP32_COLOR_ABS, FP32_COLOR_REL, SKIP_MARGIN, color_check,
+                        dev, elem_check, grad_check, rays, torch)
+
+pytestmark = pytest.mark.gpu
+
+PAPER = 8 | 16
+
+
+def gpu_tiled(f, half=False, mlp_dtype=0):
+    import paper_2412_10084_amd as ps
+    t = torch()
+    fdt = t.float16 if half else t.float32
+    return ps.Field(sdf=dev(f.sdf), feat=dev(f.tiles.planes, fdt), probes=dev(f.probes, fdt),
+                    mlp=dev(f.mlp), mlp_dtype=mlp_dtype, hidden=f.hidden, layers=f.layers,
+                    tiles=dev(f.tiles.index))
+
+
+def run(fld, o, d, N, skip, flags, dL):
+    import paper_2412_10084_amd as ps
+    t = torch()
+    B = o.shape[0]
+    do, dd = dev(o), dev(d)
+    rgb = t.empty((B, 3), device="cuda")
+    aux = t.empty((B, 4), device="cuda")
+    opts = ps.RenderOpts(N, 64.0, skip, flags)
+    ps.render_forward(fld, opts, do, dd, rgb, aux)
+    g = {k: t.zeros(getattr(fld, k).shape, device="cuda") for k in ("sdf", "feat", "probes", "mlp")}
+    ps.render_backward(fld, opts, do, dd, aux, dev(dL.astype(np.float32)), g)
+    t.cuda.synchronize()
+    return rgb.cpu().numpy(), {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+
+
+@pytest.mark.parametrize("model,flags", [("workload", 0), ("paper", PAPER)])
+@pytest.mark.parametrize("skip,N", [(0.0, 64), (4.0, 96)])
+def test_tiled_matches_oracle(model, flags, skip, N):
+    f = wl.tiled_field(0, 4, n_sh=16 if flags else 9, model=model)
+    o, d = rays(8, 32, 16)
+    of = oracle.field_from(f)
+    print(f"tiles case: model={model} skip={skip} N={N}", flush=True)
+    ref = oracle.render_forward(of, o, d, N, skip_voxels=skip, flags=flags)
+    keep = ref["margin"] > SKIP_MARGIN
+    rng = np.random.default_rng(1)
+    dL = rng.choice([-1.0, 1.0], size=(o.shape[0], 3)) / (3.0 * o.shape[0])
+    dL[~keep] = 0.0
+    g_ref = oracle.render_backward(of, o, d, dL, N, skip_voxels=skip, flags=flags)
+    rgb, g = run(gpu_tiled(f), o, d, N, skip, flags, dL)
+    nbad, emax = color_check(rgb, ref["rgb"], FP32_COLOR_REL, FP32_COLOR_ABS, keep)
+    assert nbad == 0, f"{nbad} colours off, max err {emax:.3g}"
+    assert np.count_nonzero(ref["rgb"].sum(1)) > 300
+    assert np.abs(g_ref["feat"]).max() > 0
+    grad_check(g, g_ref, "fp32")
+
+
+def test_tiled_fp16_planes():
+    f = wl.tiled_field(0, 4)
+    o, d = rays(8, 32, 16)
+    N = 64
+    of = oracle.field_from(f, half=True, mlp_round="f16")
+    ref = oracle.render_forward(of, o, d, N)
+    rng = np.random.default_rng(2)
+    dL = rng.choice([-1.0, 1.0], size=(o.shape[0], 3)) / (3.0 * o.shape[0])
+    g_ref = oracle.render_backward(of, o, d, dL, N)
+    rgb, g = run(gpu_tiled(f, half=True, mlp_dtype=1), o, d, N, 0.0, 0, dL)
+    assert np.abs(rgb - ref["rgb"]).max() <= F16_COLOR_ABS
+    grad_check(g, g_ref, "f16")
+
+
+def test_empty_tiles_render_nothing():
+    f = wl.tiled_field(0, 4)
+    f.tiles.index[:] = -1
+    o, d = rays(8, 32, 16)
+    rng = np.random.default_rng(3)
+    dL = rng.standard_normal((o.shape[0], 3))
+    rgb, g = run(gpu_tiled(f), o, d, 64, 0.0, 0, dL)
+    assert not rgb.any()
+    assert not any(v.any() for v in g.values())
+
+
+def test_tiled_train256_class_launch_sampled():
+    """T = 16 (R = 257, P = 17), 2^18 rays, N = 128, skip 4 voxels: the forward and
+    backward over the whole batch, the oracle on 1500 sampled rays."""
+    w = wl.WORKLOADS["train256"]
+    f = wl.tiled_field(0, 16)
+    assert f.R == 257
+    o, d = rays(w.views, w.W, w.H)
+    rng = np.random.default_rng(17)
+    idx = np.sort(rng.choice(o.shape[0], 3000, replace=False))
+    of = oracle.field_from(f)
+    ref = oracle.render_forward(of, o[idx], d[idx], w.n_samples, skip_voxels=w.skip_voxels)
+    keep = ref["margin"] > SKIP_MARGIN
+    sel = idx[keep][:1500]
+    dL = np.zeros((o.shape[0], 3))
+    dL[sel] = rng.choice([-1.0, 1.0], size=(sel.size, 3)) / (3.0 * o.shape[0])
+    print("tiled launch: T=16, 2^18 rays", flush=True)
+    rgb, g = run(gpu_tiled(f), o, d, w.n_samples, w.skip_voxels, 0, dL)
+    nbad, emax = color_check(rgb[idx], ref["rgb"], FP32_COLOR_REL, FP32_COLOR_ABS, keep)
+    assert nbad == 0, f"{nbad} colours off, max err {emax:.3g}"
+    g_ref = oracle.render_backward(of, o[sel], d[sel], dL[sel], w.n_samples,
+                                   skip_voxels=w.skip_voxels)
+    grad_check(g, g_ref, "fp32")
+
+
+@pytest.mark.parametrize("slots", [1, 70])
+def test_plane_step_matches_oracle(slots):
+    import paper_2412_10084_amd as ps
+    t = torch()
+    rng = np.random.default_rng(slots)
+    shape = (slots, 3, 16, 16, 3)
+    p = (rng.standard_normal(shape) * 0.4).astype(np.float32)
+    g = (rng.standard_normal(shape) * 1e-3).astype(np.float32)
+    m = (rng.standard_normal(shape) * 1e-3).astype(np.float32)
+    v = ((rng.standard_normal(shape) * 1e-3) ** 2).astype(np.float32)
+    dp, dout, dg, dm, dv = dev(p), t.empty(shape, device="cuda"), dev(g), dev(m), dev(v)
+    half = t.empty(shape, device="cuda", dtype=t.float16)
+    loss = t.empty(1, device="cuda")
+    step, lam = 4, 0.05
+    ps.plane_step(dp, dout, dg, dm, dv, step, lr=0.01, lam=lam, half_out=half, loss=loss)
+    t.cuda.synchronize()
+    L, gr = oracle.plane_smooth(p, lam)
+    G = g.astype(np.float64) + gr
+    np.testing.assert_allclose(loss.cpu().numpy()[0], L, rtol=1e-4)
+    # the gradient the step used, recovered from the first moment it wrote
+    G_gpu = (dm.cpu().numpy().astype(np.float64) - 0.9 * m) / 0.1
+    nbad, worst = elem_check(G_gpu, G, 1e-4, 1e-6)
+    assert nbad == 0, f"worst {worst:.3g} x bound"
+    # Adam's update from the moments the step wrote, in FP64: one ulp of the result and
+    # 2e-6 of the update (the bound of the plain grid step)
+    mm = dm.cpu().numpy().astype(np.float64)
+    vv = dv.cpu().numpy().astype(np.float64)
+    bc1, bc2 = 1 - 0.9 ** step, 1 - 0.995 ** step
+    upd = 0.01 * (mm / bc1) / (np.sqrt(vv / bc2) + 1e-8)
+    ref_p = p - upd
+    upd = np.abs(upd)
+    err = np.abs(dout.cpu().numpy() - ref_p) / (2.0 ** -23 * np.abs(ref_p) + 2e-6 * upd + 1e-12)
+    assert err.max() <= 1.0, f"worst {err.max():.3g} x bound"
+    assert float(dg.abs().max()) == 0.0
+    np.testing.assert_array_equal(half.cpu().numpy(), dout.cpu().numpy().astype(np.float16))
