@@ -272,8 +272,15 @@ def time_fwd_bwd_512(torch, ps, wl, steps, warmup):
             tb_ms += e[2].elapsed_time(e[3])
         tf_ms /= steps
         tb_ms /= steps
+        A = recorded_samples(torch, ws) / B
+        half_b = label != "fp32"
         out[label] = {"fwd_ms": tf_ms, "bwd_ms": tb_ms,
-                      "fwd_bwd_rays_per_s": B / ((tf_ms + tb_ms) * 1e-3)}
+                      "fwd_bwd_rays_per_s": B / ((tf_ms + tb_ms) * 1e-3),
+                      "shaded_samples_per_ray": A,
+                      "roofline_render": {
+                          e: roofline_obj(e, B * alg_bytes_per_ray(e, w.n_samples, A, half_b), t,
+                                          measured_traffic(e, "mixed512", label))
+                          for e, t in (("render_forward", tf_ms), ("render_backward", tb_ms))}}
         log(f"mixed512 {label}: fwd {tf_ms:.3f} ms, bwd {tb_ms:.3f} ms")
         del fld, grads
         torch.cuda.empty_cache()
@@ -314,6 +321,198 @@ def time_iter512(torch, ps, wl, iters, warmup):
             "grid_step_GBps": 32.0 * (w.R ** 3 * 4 + w.P ** 3 * w.n_sh * 4) / (kern["grid_step"] * 1e-3) / 1e9}
 
 
+def ev_time(torch, fn, reps):
+    """Mean ms of `fn` over `reps` launches: HIP events on torch's current stream, the
+    stream the library launches on."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def recorded_samples(torch, ws) -> int:
+    """Shaded samples the last taped forward recorded (the workspace's slot counter)."""
+    return int(ws[:8].view(torch.int64).item())
+
+
+def alg_bytes_per_ray(entry: str, N: int, A: float, half: bool) -> float:
+    """Algorithmic bytes per ray of the render entry points (every sample's SDF
+    scanned, 8 corners x 4 B; per shaded sample the FD stencil, features and probes:
+    1344 B FP32, 720 B with FP16 features and probes, plus the 32 B of its own cell in
+    the backward, which also writes the same footprint of FP32 gradients, 1376 B;
+    ray / colour I/O)."""
+    per = 720.0 if half else 1344.0
+    if entry == "render_forward":
+        return 32.0 * N + A * per + 64.0
+    return 32.0 * N + A * (per + 32.0 + 1376.0) + 52.0
+
+
+def roofline_obj(kernel: str, per_launch: float, ms: float, traffic):
+    ach = per_launch / (ms * 1e-3) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": per_launch, "launch_ms": ms}
+
+
+def train256_extras(torch, ps, w, st, kern, reps):
+    """Shaded samples per ray (the tape's counter), the render steps' rooflines and the
+    re-marching backward (entry-parallel schedule, no tape) beside the taped one."""
+    p = st["master"]
+    fld = ps.Field(p["sdf"], p["feat"], p["probes"], p["mlp"], 0, st["bounds"])
+    opts = ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels)
+    ps.render_forward(fld, opts, st["o"], st["d"], st["rgb"], st["aux"], tape=st["ws"])
+    torch.cuda.synchronize()
+    B = st["B"]
+    A = recorded_samples(torch, st["ws"]) / B
+    remarch = ev_time(torch, lambda: ps.render_backward(fld, opts, st["o"], st["d"], st["aux"],
+                                                        st["dL"], st["grads"],
+                                                        workspace=st["ws"]), reps)
+    for g in st["grads"].values():
+        g.zero_()
+    roof = {e: roofline_obj(e, B * alg_bytes_per_ray(e, w.n_samples, A, False), kern[e],
+                            measured_traffic(e))
+            for e in ("render_forward", "render_backward")}
+    return A, remarch, roof
+
+
+def paper_field(torch, ps, wl, w, seed, half=False, mlp_dtype=0):
+    """The paper's colour model at a workload's grid sizes: 16 SH coefficients, MLP
+    13 -> 32 -> 32 -> 3 (inputs F_s, F_a at the reflected vector, (1 - n.v)^0..5)."""
+    import numpy as np
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    base = gpu_field(torch, ps, wl, w, seed)
+    probes = torch.randn((w.P, w.P, w.P, 16, 4), generator=g, device="cuda") * 0.1
+    mlp = torch.from_numpy(wl.xavier_uniform_mlp(np.random.default_rng(seed), wl.PAPER_N_IN,
+                                                 wl.PAPER_HIDDEN, wl.N_OUT,
+                                                 wl.PAPER_LAYERS)).cuda()
+    feat = base.feat.half() if half else base.feat
+    probes = probes.half() if half else probes
+    return ps.Field(base.sdf, feat, probes, mlp, mlp_dtype, ps.sdf_bounds(base.sdf),
+                    wl.PAPER_HIDDEN, wl.PAPER_LAYERS)
+
+
+def time_paper_model(torch, ps, wl, reps):
+    """train256 shapes with the paper's colour model (SH at the reflected vector,
+    16 coefficients, (1 - n.v)^0..5, MLP 2 x 32): forward + L1 + backward (re-marching,
+    one ray per wave), FP32 and FP16 storage with the FP16 MLP."""
+    w = wl.WORKLOADS["train256"]
+    o, d = wl.workload_rays(w)
+    do, dd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    B = o.shape[0]
+    opts = ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels, ps.FLAG_SH_REFLECT | ps.FLAG_FRESNEL_PAPER)
+    rgb, aux = torch.empty((B, 3), device="cuda"), torch.empty((B, 4), device="cuda")
+    tgt, dL = torch.full((B, 3), 0.5, device="cuda"), torch.empty((B, 3), device="cuda")
+    out = {}
+    for label, half, mdt in (("fp32", False, 0), ("fp16", True, 1)):
+        fld = paper_field(torch, ps, wl, w, 0, half, mdt)
+        grads = {k: torch.zeros(getattr(fld, k).shape, device="cuda") for k in
+                 ("sdf", "feat", "probes", "mlp")}
+        tf = ev_time(torch, lambda: ps.render_forward(fld, opts, do, dd, rgb, aux), reps)
+        ps.l1_loss(rgb, tgt, dL)
+        tb = ev_time(torch, lambda: ps.render_backward(fld, opts, do, dd, aux, dL, grads), reps)
+        out[label] = {"fwd_ms": tf, "bwd_ms": tb, "fwd_bwd_rays_per_s": B / ((tf + tb) * 1e-3)}
+        log(f"paper model {label}: fwd {tf:.3f} ms, bwd {tb:.3f} ms")
+        del fld, grads
+    out["ratio_fp16_vs_fp32"] = out["fp16"]["fwd_bwd_rays_per_s"] / out["fp32"]["fwd_bwd_rays_per_s"]
+    out["config"] = {"R": w.R, "P": w.P, "sh_coeffs": 16, "mlp": "13-32-32-3", "rays": B,
+                     "samples": w.n_samples, "skip_voxels": w.skip_voxels,
+                     "flags": "SH_REFLECT | FRESNEL_PAPER"}
+    return out
+
+
+def time_tiled(torch, ps, wl, reps):
+    """Sparse 16^3-cell tiles with tri-plane features at 257^3 (T = 16, probes at the
+    tile corners, P = 17): forward + L1 + backward over train256's rays, and the plane
+    optimiser step."""
+    w = wl.WORKLOADS["train256"]
+    f = wl.tiled_field(0, 16)
+    o, d = wl.workload_rays(w)
+    cu = lambda a: torch.from_numpy(a).cuda()
+    do, dd = cu(o), cu(d)
+    B = o.shape[0]
+    fld = ps.Field(cu(f.sdf), cu(f.tiles.planes), cu(f.probes), cu(f.mlp), tiles=cu(f.tiles.index))
+    fld.bounds = ps.sdf_bounds(fld.sdf)
+    opts = ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels)
+    rgb, aux = torch.empty((B, 3), device="cuda"), torch.empty((B, 4), device="cuda")
+    tgt, dL = torch.full((B, 3), 0.5, device="cuda"), torch.empty((B, 3), device="cuda")
+    grads = {k: torch.zeros(getattr(fld, k).shape, device="cuda") for k in
+             ("sdf", "feat", "probes", "mlp")}
+    tf = ev_time(torch, lambda: ps.render_forward(fld, opts, do, dd, rgb, aux), reps)
+    ps.l1_loss(rgb, tgt, dL)
+    tb = ev_time(torch, lambda: ps.render_backward(fld, opts, do, dd, aux, dL, grads), reps)
+    pl = fld.feat
+    po, m, v = torch.empty_like(pl), torch.zeros_like(pl), torch.zeros_like(pl)
+    ts = ev_time(torch, lambda: ps.plane_step(pl, po, grads["feat"], m, v, 1), reps)
+    n_tiles = int(f.tiles.planes.shape[0])
+    log(f"tiled: fwd {tf:.3f} ms, bwd {tb:.3f} ms, plane step {ts:.3f} ms ({n_tiles} tiles)")
+    return {"fwd_ms": tf, "bwd_ms": tb, "plane_step_ms": ts,
+            "fwd_bwd_rays_per_s": B / ((tf + tb) * 1e-3),
+            "config": {"T": 16, "R": f.R, "P": f.P, "tiles": n_tiles,
+                       "tile_fraction": n_tiles / 16 ** 3, "rays": B, "samples": w.n_samples,
+                       "skip_voxels": w.skip_voxels,
+                       "feature_bytes": int(f.tiles.planes.nbytes),
+                       "dense_feature_bytes": f.R ** 3 * 3 * 4}}
+
+
+def time_regs(torch, ps, wl, reps):
+    """train256's grid step with the paper's remaining SDF regularisers (smoothed SDF
+    G(shat), L_sdf, L_normal, the (1 + 5|s|)^-1 weighting) beside the plain one."""
+    w = wl.WORKLOADS["train256"]
+    f = gpu_field(torch, ps, wl, w, 0)
+    p = dict(sdf=f.sdf, feat=f.feat, probes=f.probes, mlp=f.mlp)
+    out = {k: torch.empty_like(v) for k, v in p.items()}
+    g = {k: torch.zeros_like(v) for k, v in p.items()}
+    m = {k: torch.zeros_like(v) for k, v in p.items()}
+    v = {k: torch.zeros_like(t) for k, t in p.items()}
+    s_in, s_out = torch.empty_like(f.sdf), torch.empty_like(f.sdf)
+    ps.smooth_sdf(p["sdf"], s_in)
+    work = torch.empty(ps.step_work_bytes(w.R), dtype=torch.uint8, device="cuda")
+    plain = ps.StepOpts()
+    ext = ps.StepOpts(smooth=True, reg_weight=True, lambda_sdf=0.2, lambda_normal=0.05)
+    t_plain = ev_time(torch, lambda: ps.grid_step(p, out, g, m, v, 1, plain), reps)
+    t_ext = ev_time(torch, lambda: ps.grid_step(p, out, g, m, v, 1, ext, s_in=s_in, s_out=s_out,
+                                                work=work), reps)
+    t_smooth = ev_time(torch, lambda: ps.smooth_sdf(p["sdf"], s_out), reps)
+    log(f"regularisers: plain step {t_plain:.3f} ms, with Sec. 3.3's SDF terms {t_ext:.3f} ms")
+    return {"plain_step_ms": t_plain, "extended_step_ms": t_ext, "smooth_sdf_ms": t_smooth,
+            "config": {"R": w.R, "P": w.P, "lambda_sdf": 0.2, "lambda_normal": 0.05,
+                       "sigma_voxels": 1.0, "weighted": True}}
+
+
+def time_realtime(torch, ps, wl, reps):
+    """rt512: FP16 grids 512^3 / 128^3, one 1920x1163 view; per-voxel shading of the
+    band nodes into an FP16 colour grid, then volume rendering (128 samples, skip 4)."""
+    import numpy as np
+    w = wl.WORKLOADS["rt512"]
+    fld = gpu_field(torch, ps, wl, w, 0, feat_half=True, sdf_half=True)
+    fld.bounds = ps.sdf_bounds(fld.sdf)
+    band = float(np.float32(wl.RT_BAND_VOXELS * 2.0 / (w.R - 1)))
+    cam = torch.from_numpy(wl.fibonacci_cameras(1, w.W, w.H)[0].as_array().astype(np.float32)).cuda()
+    lst = torch.empty(w.R ** 3 // 8, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    t_list = ev_time(torch, lambda: ps.voxel_list(fld.sdf, band, lst, cnt), reps)
+    n = int(cnt.item())
+    assert n <= lst.numel()
+    col = torch.zeros((w.R, w.R, w.R, 4), dtype=torch.float16, device="cuda")
+    out = torch.empty((w.H, w.W, 3), device="cuda")
+    t_shade = ev_time(torch, lambda: ps.voxel_shade(fld, cam, lst, cnt, col), reps)
+    opts = ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels)
+    t_render = ev_time(torch, lambda: ps.volume_render(fld, opts, col, cam, w.W, w.H, out), reps)
+    log(f"real-time: list {t_list:.3f} ms ({n} voxels), shading {t_shade:.3f} ms, "
+        f"render {t_render:.3f} ms")
+    return {"workload": "rt512", "voxel_list_ms": t_list, "voxel_shade_ms": t_shade,
+            "volume_render_ms": t_render, "ms_per_frame": t_shade + t_render,
+            "shaded_voxels": n, "render_rays_per_s": w.W * w.H / (t_render * 1e-3),
+            "config": {"R": w.R, "P": w.P, "W": w.W, "H": w.H, "band_voxels": wl.RT_BAND_VOXELS,
+                       "samples": w.n_samples, "skip_voxels": w.skip_voxels,
+                       "grids": "fp16", "colour_grid": "fp16"}}
+
+
 def kernel_source_hash() -> str:
     import glob
     import hashlib
@@ -325,25 +524,39 @@ def kernel_source_hash() -> str:
 
 
 TRAFFIC_KERNELS = {
-    # the kernels each entry point launches on the benchmark's path (taped training step)
-    "render_backward": ("psdf::bwd_ws_clear_kernel",
-                        "psdf::scan_sums_kernel", "psdf::scan_partials_kernel",
-                        "psdf::scan_offsets_kernel",
-                        "psdf::tape_walk_kernel", "void psdf::tape_shade_kernel<0>", "void psdf::mlp_round_kernel",
-                        "psdf::mlp_reduce_kernel", "psdf::bwd_box_kernel",
-                        "void psdf::probe_reduce_kernel<9>",
-                        "void psdf::render_bwd_kernel<float, float, 9, 0>"),
-    "render_forward": ("psdf::may_box_kernel", "void psdf::render_fwd_kernel<float, float, 9, 0>"),
-    "grid_step": ("psdf::zero3_kernel", "psdf::bounds_init_kernel", "psdf::step_sdf_tiled_kernel",
-                  "psdf::bounds_decode_kernel", "psdf::step_tv3v_kernel",
-                  "void psdf::step_tv4_kernel<36>", "psdf::step_mlp_kernel"),
+    # the kernels each entry point launches on the benchmark's path (taped training step),
+    # by name without template arguments
+    "render_backward": ("bwd_ws_clear_kernel", "scan_sums_kernel", "scan_partials_kernel",
+                        "scan_offsets_kernel", "tape_walk_kernel", "tape_shade_kernel",
+                        "mlp_round_kernel", "mlp_reduce_kernel", "bwd_box_kernel",
+                        "probe_reduce_kernel", "render_bwd_kernel"),
+    "render_forward": ("may_box_kernel", "render_fwd_kernel"),
+    "grid_step": ("zero3_kernel", "bounds_init_kernel", "step_sdf_tiled_kernel",
+                  "bounds_decode_kernel", "step_tv3v_kernel", "step_tv4_kernel", "step_mlp_kernel"),
 }
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
-    the kernels changed since the counters were taken (source hash mismatch)."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_train256.txt")
+def kernel_base_name(full: str) -> str:
+    """'void psdf::tape_shade_kernel<0>(psdf::RenderArgs, ...)' -> 'tape_shade_kernel'; a
+    name the profiler left mangled ('_ZN4psdf17render_fwd_kernelIf...') gives its last
+    nested identifier the same way"""
+    if full.startswith("_ZN"):
+        rest, last = full[3:], ""
+        while rest[:1].isdigit():
+            n = len(rest) - len(rest.lstrip("0123456789"))
+            k = int(rest[:n])
+            last, rest = rest[n:n + k], rest[n + k:]
+        return last
+    name = full.split("(", 1)[0].split("<", 1)[0]
+    return name.rsplit("::", 1)[-1].split()[-1]
+
+
+def measured_traffic(kernel: str, workload: str = "train256", variant: str = ""):
+    """HBM bytes per launch of an entry point from the committed rocprofv3 counter
+    summary of a workload (profiles/hbm_traffic_<workload>[_<variant>].txt), or None
+    when the kernels changed since the counters were taken (source hash mismatch)."""
+    name = f"hbm_traffic_{workload}" + (f"_{variant}" if variant else "") + ".txt"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path) or kernel not in TRAFFIC_KERNELS:
         return None
     total, found, ok = 0.0, 0, False
@@ -352,7 +565,7 @@ def measured_traffic(kernel: str):
             ok = line.split(":", 1)[1].strip() == kernel_source_hash()
         elif line[:1] != "#" and line.strip():
             parts = line.split(None, 4)
-            if len(parts) == 5 and parts[4].startswith(TRAFFIC_KERNELS[kernel]):
+            if len(parts) == 5 and kernel_base_name(parts[4]) in TRAFFIC_KERNELS[kernel]:
                 total += float(parts[3])
                 found += 1
     return total if ok and found else None
@@ -382,11 +595,39 @@ def cpu_baseline(wl, w, field, rays, n_rays=16384):
     B = o.shape[0]
     t_full = t_rays * B / n_rays + t_step
     shaded = float(ref["n_shaded"].mean())
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.max_threads()
+    # the same work on one thread: a quarter of the ray sample and the grid step
+    oracle.set_threads(1)
+    n1 = n_rays // 4
+    t0 = time.time()
+    r1 = oracle.render_forward(of, o[idx[:n1]], d[idx[:n1]], w.n_samples, tau=w.tau,
+                               skip_voxels=w.skip_voxels)
+    _, dL1 = oracle.l1_loss(r1["rgb"], np.full_like(r1["rgb"], 0.5))
+    oracle.render_backward(of, o[idx[:n1]], d[idx[:n1]], dL1, w.n_samples, tau=w.tau,
+                           skip_voxels=w.skip_voxels)
+    t_rays1 = time.time() - t0
+    t0 = time.time()
+    oracle.grid_step(params, grads, np.zeros(n), np.zeros(n), 1, oracle.StepOpts())
+    t_step1 = time.time() - t0
+    oracle.set_threads(cores)
+    t_full1 = t_rays1 * B / n1 + t_step1
     return dict(value=B / t_full, unit="rays/s", cores=cores, kind="oracle",
+                value_1thread=B / t_full1,
                 sample=(f"fwd+L1+bwd on {n_rays} evenly spaced rays of the {B}-ray batch "
-                        f"({t_rays:.2f} s) scaled to the batch, plus one full grid step over "
-                        f"{n} parameters ({t_step:.2f} s, single thread)")), shaded
+                        f"({t_rays:.2f} s on {cores} threads) scaled to the batch, plus one full "
+                        f"grid step over {n} parameters ({t_step:.2f} s, its Adam loop threaded); "
+                        f"value_1thread: {n1} rays ({t_rays1:.2f} s) and the grid step "
+                        f"({t_step1:.2f} s) on one thread")), shaded
+
+
+def calib_copy(torch) -> int:
+    """Three 1 GiB device copies: what FETCH_SIZE / WRITE_SIZE read for known bytes."""
+    x = torch.empty(1 << 28, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return 2 * x.numel() * 4
 
 
 def main():
@@ -398,6 +639,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--only", choices=("mixed512", "iter512", "trace512", "paper", "tiled",
+                                       "regs", "realtime"),
+                    help="run one secondary workload alone (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the render step is measured on one MI355X (one process, "
@@ -410,12 +654,28 @@ def main():
 
     ps.lib()
     torch.cuda.set_device(0)
+    if args.only:
+        reps = max(2, args.steps // 4)
+        legs = {"mixed512": lambda: time_fwd_bwd_512(torch, ps, wl, reps, 1),
+                "iter512": lambda: time_iter512(torch, ps, wl, args.steps, args.warmup),
+                "trace512": lambda: time_inference(torch, ps, wl, reps, 1),
+                "paper": lambda: time_paper_model(torch, ps, wl, reps),
+                "tiled": lambda: time_tiled(torch, ps, wl, reps),
+                "regs": lambda: time_regs(torch, ps, wl, reps),
+                "realtime": lambda: time_realtime(torch, ps, wl, reps)}
+        res = {"only": args.only, args.only: legs[args.only]()}
+        if args.calib_copy:
+            res["calib_copy_bytes"] = calib_copy(torch)
+        print(json.dumps(res), flush=True)
+        return
     w = wl.WORKLOADS["train256"]
     log(f"setting up {w.name}: R={w.R} P={w.P} B={w.rays} N={w.n_samples}")
     st, field, rays = make_state(torch, ps, wl, w)
     ms, kern = time_training(torch, ps, w, st, args.steps, args.warmup, "fp32")
     B = st["B"]
     value = B / (ms * 1e-3)
+    A, remarch_ms, roof_render = train256_extras(torch, ps, w, st, kern, max(2, args.steps // 4))
+    log(f"shaded samples per ray {A:.3f}; re-marching backward {remarch_ms:.3f} ms")
     del st
     torch.cuda.empty_cache()
 
@@ -429,15 +689,19 @@ def main():
                    "step": "render_forward + l1_loss + render_backward + grid_step"},
         "kernels_ms": kern,
         "fwd_bwd_rays_per_s": B / ((kern["render_forward"] + kern["render_backward"]) * 1e-3),
+        "shaded_samples_per_ray": A,
+        "render_backward_remarch_ms": remarch_ms,
+        "roofline_render": roof_render,
     }
 
-    shaded = None
+    shaded = A
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cb, shaded = cpu_baseline(wl, w, field, rays)
+        cb, shaded_cpu = cpu_baseline(wl, w, field, rays)
         result["cpu_baseline"] = cb
-        result["shaded_samples_per_ray"] = shaded
-        log(f"cpu baseline: {cb['value']:.4g} rays/s on {cb['cores']} threads")
+        result["shaded_samples_per_ray_oracle"] = shaded_cpu
+        log(f"cpu baseline: {cb['value']:.4g} rays/s on {cb['cores']} threads, "
+            f"{cb['value_1thread']:.4g} on one")
 
     # roofline of the dominant kernel: algorithmic bytes per launch / launch time
     n_params = w.R ** 3 * 4 + w.P ** 3 * w.n_sh * 4 + 227
@@ -446,20 +710,10 @@ def main():
     if dom == "grid_step":
         # read p, g, m, v; write p, m, v, g (zero): 8 x 4 B per parameter
         per_launch = 32.0 * n_params
-    elif shaded is not None:
-        # per ray: SDF scan 32 B x N; per shaded sample 1376 B read (forward) and
-        # another 1376 B of gradient payload (backward); ray / aux / dL I/O
-        if dom == "render_backward":
-            per_launch = B * (32.0 * w.n_samples + shaded * 2 * 1376.0 + 52.0)
-        else:
-            per_launch = B * (32.0 * w.n_samples + shaded * 1376.0 + 64.0)
+    elif dom in ("render_forward", "render_backward"):
+        per_launch = B * alg_bytes_per_ray(dom, w.n_samples, shaded, False)
     if per_launch is not None:
-        ach = per_launch / (kern[dom] * 1e-3) / 1e9
-        result["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                              "traffic": measured_traffic(dom),
-                              "algorithmic_bytes_per_launch": per_launch,
-                              "launch_ms": kern[dom]}
+        result["roofline"] = roofline_obj(dom, per_launch, kern[dom], measured_traffic(dom))
 
     if not args.no_extras:
         log("mixed precision (fp16 storage, fp16 MFMA MLP) ...")
@@ -487,14 +741,22 @@ def main():
         log("iter512 (full iteration, 100 iterations) ...")
         result["iter512"] = time_iter512(torch, ps, wl, 100, 2)
         torch.cuda.empty_cache()
+        reps = max(2, args.steps // 4)
+        log("paper colour model at train256 shapes ...")
+        result["paper_model"] = time_paper_model(torch, ps, wl, reps)
+        torch.cuda.empty_cache()
+        log("sparse tiles with tri-plane features (T = 16) ...")
+        result["tiled"] = time_tiled(torch, ps, wl, reps)
+        torch.cuda.empty_cache()
+        log("grid step with the smoothed SDF and the remaining regularisers ...")
+        result["regularisers"] = time_regs(torch, ps, wl, reps)
+        torch.cuda.empty_cache()
+        log("real-time render (voxel shading + volume rendering, rt512) ...")
+        result["realtime"] = time_realtime(torch, ps, wl, reps)
+        torch.cuda.empty_cache()
 
     if args.calib_copy:
-        x = torch.empty(1 << 28, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        result["calib_copy_bytes"] = 2 * x.numel() * 4
+        result["calib_copy_bytes"] = calib_copy(torch)
 
     print(json.dumps(result), flush=True)
 

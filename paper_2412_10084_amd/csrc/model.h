@@ -245,7 +245,9 @@ __device__ __forceinline__ void model_inputs(const ST* __restrict__ sdf, const F
 // MLP, per lane.  Reduced modes round the weights, the inputs and the hidden
 // activations to FP16 / BF16 (nearest even) and accumulate in FP32.
 // ---------------------------------------------------------------------------
-template <int M, int H, int L, typename WT>
+// WR: the weights (not the biases) are already rounded as mrnd<M> rounds them (a
+// reduced-precision copy in LDS, model_round_mlp), else they are rounded on use
+template <int M, int H, int L, bool WR = false, typename WT>
 __device__ __forceinline__ void model_mlp_fwd(WT* __restrict__ W, int nin, const float z[MNIN],
                                               float pre[L * H], float out[3]) {
 #pragma unroll
@@ -253,7 +255,7 @@ __device__ __forceinline__ void model_mlp_fwd(WT* __restrict__ W, int nin, const
     float acc = 0.0f;
 #pragma unroll
     for (int j = 0; j < MNIN; ++j)
-      if (j < nin) acc = fmaf(mrnd<M>(W[k * nin + j]), mrnd<M>(z[j]), acc);
+      if (j < nin) acc = fmaf(wrnd<M, WR>(W[k * nin + j]), mrnd<M>(z[j]), acc);
     pre[k] = acc + W[H * nin + k];
   }
   int off = H * nin + H;
@@ -263,7 +265,7 @@ __device__ __forceinline__ void model_mlp_fwd(WT* __restrict__ W, int nin, const
       float acc = 0.0f;
 #pragma unroll
       for (int j = 0; j < H; ++j)
-        acc = fmaf(mrnd<M>(W[off + k * H + j]), mrnd<M>(fmaxf(pre[j], 0.0f)), acc);
+        acc = fmaf(wrnd<M, WR>(W[off + k * H + j]), mrnd<M>(fmaxf(pre[j], 0.0f)), acc);
       pre[H + k] = acc + W[off + H * H + k];
     }
     off += H * H + H;
@@ -273,13 +275,14 @@ __device__ __forceinline__ void model_mlp_fwd(WT* __restrict__ W, int nin, const
     float acc = 0.0f;
 #pragma unroll
     for (int k = 0; k < H; ++k)
-      acc = fmaf(mrnd<M>(W[off + c * H + k]), mrnd<M>(fmaxf(pre[(L - 1) * H + k], 0.0f)), acc);
+      acc = fmaf(wrnd<M, WR>(W[off + c * H + k]), mrnd<M>(fmaxf(pre[(L - 1) * H + k], 0.0f)),
+                 acc);
     out[c] = acc + W[off + 3 * H + c];
   }
 }
 
 // reverse mode: dpre (pre-activation cotangents of every layer) and dz
-template <int M, int H, int L, typename WT>
+template <int M, int H, int L, bool WR = false, typename WT>
 __device__ __forceinline__ void model_mlp_bwd(WT* __restrict__ W, int nin, const float pre[L * H],
                                               const float dout[3], float dpre[L * H],
                                               float dz[MNIN]) {
@@ -289,7 +292,7 @@ __device__ __forceinline__ void model_mlp_bwd(WT* __restrict__ W, int nin, const
   for (int k = 0; k < H; ++k) {
     float acc = 0.0f;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc = fmaf(mrnd<M>(W[offo + c * H + k]), dout[c], acc);
+    for (int c = 0; c < 3; ++c) acc = fmaf(wrnd<M, WR>(W[offo + c * H + k]), dout[c], acc);
     dpre[(L - 1) * H + k] = pre[(L - 1) * H + k] > 0.0f ? acc : 0.0f;
   }
   if constexpr (L == 2) {
@@ -297,7 +300,7 @@ __device__ __forceinline__ void model_mlp_bwd(WT* __restrict__ W, int nin, const
     for (int j = 0; j < H; ++j) {
       float acc = 0.0f;
 #pragma unroll
-      for (int k = 0; k < H; ++k) acc = fmaf(mrnd<M>(W[off1 + k * H + j]), dpre[H + k], acc);
+      for (int k = 0; k < H; ++k) acc = fmaf(wrnd<M, WR>(W[off1 + k * H + j]), dpre[H + k], acc);
       dpre[j] = pre[j] > 0.0f ? acc : 0.0f;
     }
   }
@@ -306,9 +309,26 @@ __device__ __forceinline__ void model_mlp_bwd(WT* __restrict__ W, int nin, const
     float acc = 0.0f;
     if (j < nin) {
 #pragma unroll
-      for (int k = 0; k < H; ++k) acc = fmaf(mrnd<M>(W[k * nin + j]), dpre[k], acc);
+      for (int k = 0; k < H; ++k) acc = fmaf(wrnd<M, WR>(W[k * nin + j]), dpre[k], acc);
     }
     dz[j] = acc;
+  }
+}
+
+// largest packed MLP of the paper models (13 inputs, two hidden layers of 32)
+constexpr int MODEL_MLP_MAX = model_mlp_size(MNIN, 32, 2);
+
+// copy of the packed MLP with its weights (not its biases) rounded for arithmetic M;
+// called by the whole wave, which then reads it from LDS (broadcast reads)
+template <int M>
+__device__ __forceinline__ void model_round_mlp(const float* __restrict__ W, float* dst, int nin,
+                                                int H, int L, int lane) {
+  const int n = model_mlp_size(nin, H, L);
+  const int b0 = H * nin, w1 = b0 + H, b1 = w1 + (L - 1) * H * H, wo = b1 + (L - 1) * H,
+            bo = wo + 3 * H;
+  for (int i = lane; i < n; i += 64) {
+    const bool bias = (i >= b0 && i < w1) || (L == 2 && i >= b1 && i < wo) || i >= bo;
+    dst[i] = bias ? W[i] : mrnd<M>(W[i]);
   }
 }
 

@@ -125,6 +125,17 @@ __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
   const Tiles tl{a.tile_index, a.tile_T};
   const int nin = model_n_in(a.flags);
+  // reduced-precision MLP: a copy with rounded weights in LDS (rounded once, not on
+  // every use); FP32 reads the weights with scalar loads
+  __shared__ float Wr[M == MLP_F32 ? 1 : MODEL_MLP_MAX];
+  if constexpr (M != MLP_F32) {
+    model_round_mlp<M>(a.mlp, Wr, nin, H, L, threadIdx.x);
+    wave_sync();
+  }
+  auto mlp_fwd = [&](const float* z, float* pre, float* out) {
+    if constexpr (M == MLP_F32) model_mlp_fwd<M, H, L>(W, nin, z, pre, out);
+    else model_mlp_fwd<M, H, L, true>(Wr, nin, z, pre, out);
+  };
   int64_t r0, r1;
   wave_rays(a.B, per_wave, r0, r1);
   for (int64_t ray = r0; ray < r1; ++ray) {
@@ -147,7 +158,7 @@ __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per
           ModelShade<NSH> S;
           model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
           float pre[L * H], out[3];
-          model_mlp_fwd<M, H, L>(W, nin, S.z, pre, out);
+          mlp_fwd(S.z, pre, out);
           w = E.w[e];
 #pragma unroll
           for (int c = 0; c < 3; ++c) wc[c] = w * sigmoidf(out[c]);
@@ -210,6 +221,17 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
   const Tiles tl{a.tile_index, a.tile_T};
   const int nin = model_n_in(a.flags);
+  // reduced-precision MLP: a copy with rounded weights in LDS (rounded once, not on
+  // every use); FP32 reads the weights with scalar loads
+  __shared__ float Wr[M == MLP_F32 ? 1 : MODEL_MLP_MAX];
+  if constexpr (M != MLP_F32) {
+    model_round_mlp<M>(a.mlp, Wr, nin, H, L, threadIdx.x);
+    wave_sync();
+  }
+  auto mlp_fwd = [&](const float* z, float* pre, float* out) {
+    if constexpr (M == MLP_F32) model_mlp_fwd<M, H, L>(W, nin, z, pre, out);
+    else model_mlp_fwd<M, H, L, true>(Wr, nin, z, pre, out);
+  };
   const bool reflect = (G.flags & FLAG_SH_REFLECT) && !(G.flags & FLAG_NO_FA);
   ModelDw<H, L> D;
   model_dw_zero(D);
@@ -238,7 +260,7 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
         ModelShade<NSH> S;
         model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
         float pre[L * H], out[3];
-        model_mlp_fwd<M, H, L>(W, nin, S.z, pre, out);
+        mlp_fwd(S.z, pre, out);
 #pragma unroll
         for (int c = 0; c < 3; ++c) Ls.C[e][c] = sigmoidf(out[c]);
       }
@@ -280,7 +302,7 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
         i = E.i[e];
         sample_pos(r, sample_t(r, i), x);
         model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
-        model_mlp_fwd<M, H, L>(W, nin, S.z, pre, out);
+        mlp_fwd(S.z, pre, out);
         const float w = E.w[e];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -299,7 +321,8 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
         for (int j = 0; j < NSH; ++j) S.Y[j] = 0.f;
       }
       float dpre[L * H], dz[MNIN];
-      model_mlp_bwd<M, H, L>(W, nin, pre, dout, dpre, dz);
+      if constexpr (M == MLP_F32) model_mlp_bwd<M, H, L>(W, nin, pre, dout, dpre, dz);
+      else model_mlp_bwd<M, H, L, true>(Wr, nin, pre, dout, dpre, dz);
       if (a.g_mlp) model_dw_batch<M, H, L>(Ls.u.dw, lane, ve, nin, S.z, pre, dpre, dout, D);
       wave_sync();
       // SDF: the FD-normal path and the opacity at s_i in the sample's 4x4x4 patch,

@@ -1,8 +1,8 @@
 // Real-time render of the supplementary "Performance Analysis": a shading pass
 // assigns a colour to every voxel near the surface, then a volume-rendering pass
 // samples the SDF and that colour field along the pixel rays.
-//   voxel_list_kernel    the nodes with |s| <= band, compacted (wave-aggregated
-//                        atomics); view-independent, built once per SDF;
+//   voxel_list_kernel    the nodes with |s| <= band, compacted (one atomic per
+//                        block of 16384 nodes); view-independent, built once per SDF;
 //   voxel_shade_kernel   one listed node per lane: view direction from the node to
 //                        the camera centre, FD normal, F_s, F_a, MLP (per lane, or
 //                        FP16 / BF16 MFMA over the wave) -> colour grid;
@@ -18,22 +18,81 @@ __global__ void zero_count_kernel(int* c) {
   if (threadIdx.x == 0) c[0] = 0;
 }
 
-template <typename ST>
-__global__ void __launch_bounds__(256) voxel_list_kernel(int R, const ST* __restrict__ sdf,
+// One block lists VL_IT x VL_CHUNK consecutive nodes: each thread tests VL_V
+// consecutive nodes per round (one 16- or 32-byte load when the grid is 16-byte
+// aligned), keeps the in-band bits, and the block reserves its whole range with a
+// single atomic before writing the indices, in node order within the block.
+constexpr int VL_V = 8, VL_IT = 8, VL_CHUNK = 256 * VL_V;
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+template <typename ST, bool VEC>
+__device__ __forceinline__ unsigned band_bits(const ST* __restrict__ sdf, int64_t n0, int64_t n3,
+                                              float band) {
+  float v[VL_V];
+  if (VEC && n0 + VL_V <= n3) {
+    if constexpr (sizeof(ST) == 2) {
+      const h8v h = *reinterpret_cast<const h8v*>(sdf + n0);
+#pragma unroll
+      for (int j = 0; j < VL_V; ++j) v[j] = (float)h[j];
+    } else {
+      const float4 a = reinterpret_cast<const float4*>(sdf + n0)[0];
+      const float4 b = reinterpret_cast<const float4*>(sdf + n0)[1];
+      v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
+      v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < VL_V; ++j) v[j] = n0 + j < n3 ? ld1(sdf, (int)(n0 + j)) : INFINITY;
+  }
+  unsigned m = 0;
+#pragma unroll
+  for (int j = 0; j < VL_V; ++j) m |= (fabsf(v[j]) <= band ? 1u : 0u) << j;
+  return m;
+}
+
+template <typename ST, bool VEC>
+__global__ void __launch_bounds__(256) voxel_list_kernel(int64_t n3, const ST* __restrict__ sdf,
                                                          float band, int* __restrict__ list,
                                                          int64_t cap, int* __restrict__ count) {
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t n3 = (int64_t)R * R * R;
-  const bool in = n < n3 && fabsf(ld1(sdf, (int)(n < n3 ? n : 0))) <= band;
-  const uint64_t mask = __ballot(in);
-  if (!mask) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __builtin_ctzll(mask);
-  int base = 0;
-  if (lane == leader) base = atomicAdd(count, (int)__popcll(mask));
-  base = __shfl(base, leader, 64);
-  const int64_t slot = (int64_t)base + lane_rank(mask);
-  if (in && slot < cap) list[slot] = (int)n;
+  __shared__ int woff[VL_IT][4];
+  __shared__ int bbase;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t b0 = (int64_t)blockIdx.x * (VL_CHUNK * VL_IT) + threadIdx.x * VL_V;
+  unsigned bits[VL_IT];
+  int pre[VL_IT];
+#pragma unroll
+  for (int k = 0; k < VL_IT; ++k) bits[k] = band_bits<ST, VEC>(sdf, b0 + (int64_t)k * VL_CHUNK, n3, band);
+#pragma unroll
+  for (int k = 0; k < VL_IT; ++k) {
+    const int c = __popc(bits[k]);
+    int x = c;  // inclusive prefix over the wave's lanes
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    pre[k] = x - c;
+    if (lane == 63) woff[k][wv] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int k = 0; k < VL_IT; ++k)
+      for (int w = 0; w < 4; ++w) {
+        const int t = woff[k][w];
+        woff[k][w] = tot;
+        tot += t;
+      }
+    bbase = tot ? atomicAdd(count, tot) : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < VL_IT; ++k) {
+    int64_t slot = (int64_t)bbase + woff[k][wv] + pre[k];
+    const int64_t n0 = b0 + (int64_t)k * VL_CHUNK;
+    for (unsigned m = bits[k]; m; m &= m - 1, ++slot)
+      if (slot < cap) list[slot] = (int)(n0 + __ffs(m) - 1);
+  }
 }
 
 // colour grid element: FP32 (r, g, b, 0) or FP16 (r, g, b, 0), 16 or 8 bytes
@@ -189,13 +248,21 @@ hipError_t launch_voxel_list(int R, int sdf_dt, const void* sdf, float band, int
                              int64_t cap, int* count, hipStream_t s) {
   hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(64), 0, s, count);
   const int64_t n3 = (int64_t)R * R * R;
-  const dim3 grid((unsigned)((n3 + 255) / 256));
-  if (sdf_dt == 0)
-    hipLaunchKernelGGL(voxel_list_kernel<float>, grid, dim3(256), 0, s, R,
-                       static_cast<const float*>(sdf), band, list, cap, count);
-  else
-    hipLaunchKernelGGL(voxel_list_kernel<_Float16>, grid, dim3(256), 0, s, R,
-                       static_cast<const _Float16*>(sdf), band, list, cap, count);
+  const dim3 grid((unsigned)((n3 + VL_CHUNK * VL_IT - 1) / (VL_CHUNK * VL_IT)));
+  const bool vec = reinterpret_cast<uintptr_t>(sdf) % 16 == 0;
+  if (sdf_dt == 0) {
+    const float* p = static_cast<const float*>(sdf);
+    if (vec)
+      hipLaunchKernelGGL((voxel_list_kernel<float, true>), grid, dim3(256), 0, s, n3, p, band, list, cap, count);
+    else
+      hipLaunchKernelGGL((voxel_list_kernel<float, false>), grid, dim3(256), 0, s, n3, p, band, list, cap, count);
+  } else {
+    const _Float16* p = static_cast<const _Float16*>(sdf);
+    if (vec)
+      hipLaunchKernelGGL((voxel_list_kernel<_Float16, true>), grid, dim3(256), 0, s, n3, p, band, list, cap, count);
+    else
+      hipLaunchKernelGGL((voxel_list_kernel<_Float16, false>), grid, dim3(256), 0, s, n3, p, band, list, cap, count);
+  }
   return hipGetLastError();
 }
 

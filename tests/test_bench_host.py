@@ -35,3 +35,13 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "--gpus must be 1" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_alg_bytes_and_kernel_names():
+    # train256: N = 128, A shaded samples per ray
+    assert bench.alg_bytes_per_ray("render_forward", 128, 1.0, False) == 32 * 128 + 1344 + 64
+    assert bench.alg_bytes_per_ray("render_backward", 128, 2.0, True) == 32 * 128 + 2 * (720 + 32 + 1376) + 52
+    assert bench.kernel_base_name("void psdf::tape_shade_kernel<1>(psdf::RenderArgs, psdf::BwdWs)") == "tape_shade_kernel"
+    assert bench.kernel_base_name("psdf::bwd_box_kernel(psdf::RenderArgs, psdf::BwdWs)") == "bwd_box_kernel"
+    r = bench.roofline_obj("render_forward", 8e9, 1.0, None)
+    assert abs(r["frac"] - 1.0) < 1e-12 and r["achieved"] == 8000.0

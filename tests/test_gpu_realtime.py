@@ -41,6 +41,36 @@ def test_voxel_list_is_the_band():
     del t
 
 
+@pytest.mark.parametrize("half", [False, True])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_voxel_list_ragged_unaligned_and_capped(half, offset):
+    """R = 37 (a ragged last block), the grid at a 16-byte boundary or one element past
+    it (the scalar path), and a capacity below the band's size."""
+    import paper_2412_10084_amd as ps
+    t = torch()
+    R = 37
+    rng = np.random.default_rng(7 + offset)
+    s = rng.uniform(-1, 1, R ** 3).astype(np.float16 if half else np.float32)
+    buf = t.from_numpy(np.concatenate([np.zeros(offset, s.dtype), s])).cuda()
+    sdf = buf[offset:].view(R, R, R)
+    band = 0.25
+    inband = np.flatnonzero(np.abs(s.astype(np.float32)) <= np.float32(band))
+    for cap in (R ** 3, inband.size // 3):
+        lst = t.full((max(cap, 1),), -1, dtype=t.int32, device="cuda")
+        cnt = t.zeros(1, dtype=t.int32, device="cuda")
+        ps.voxel_list(sdf, band, lst[:cap], cnt)
+        t.cuda.synchronize()
+        got = lst.cpu().numpy()
+        assert int(cnt.item()) == inband.size
+        k = min(cap, inband.size)
+        assert np.all(got[k:] == -1)
+        if cap >= inband.size:
+            np.testing.assert_array_equal(np.sort(got[:k]), inband)
+        else:
+            part = got[:k]
+            assert np.unique(part).size == k and np.isin(part, inband).all()
+
+
 @pytest.mark.parametrize("colour_dt,half,mlp_dt", [(0, False, 0), (1, False, 0), (1, True, 1)])
 def test_voxel_shade_matches_oracle(colour_dt, half, mlp_dt):
     R, P = 64, 16
