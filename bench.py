@@ -548,7 +548,8 @@ def kernel_base_name(full: str) -> str:
             last, rest = rest[n:n + k], rest[n + k:]
         return last
     name = full.split("(", 1)[0].split("<", 1)[0]
-    return name.rsplit("::", 1)[-1].split()[-1]
+    words = name.rsplit("::", 1)[-1].split()
+    return words[-1] if words else ""
 
 
 def measured_traffic(kernel: str, workload: str = "train256", variant: str = ""):

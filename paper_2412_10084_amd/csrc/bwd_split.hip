@@ -511,11 +511,21 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
 // depends on the MLP type only.  The weight gradients are summed first, so that
 // the MLP's activations are dead before the records are built (the record fields
 // are read from the entry there), which keeps the pass free of register spills.
+//
+// A wave's 64 entries are staged in LDS with full-line loads first: their fields are
+// read at scattered points of the pass, and one field loaded across 64 lanes at the
+// entry's 160-byte stride touches 80 lines, which other waves evict before the next
+// field is loaded (the pass then fetched ~6x the tape from HBM).
+constexpr int kEntDw = 42;  // LDS row of an entry: 40 dwords + 2 (8-byte rows, 2-way banks)
+static_assert(sizeof(BwdEntry) == 40 * 4, "an entry is 40 dwords (10 x 16 bytes)");
+
 template <int M>
 __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdWs ws) {
   __shared__ DwLds dlds[WAVES];
+  __shared__ __align__(16) unsigned estage[WAVES][64 * kEntDw];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   DwLds& D = dlds[wv];
+  unsigned* const stage = estage[wv];
   // the MLP read through scalar loads; reduced modes use the copy whose weights
   // are already rounded (no per-use conversions to keep in registers)
   cfloat* __restrict__ W = const_mlp(M == MLP_F32 ? a.mlp : ws.mlp_r);
@@ -529,7 +539,26 @@ __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdW
     // entries in write order (coalesced); records go to the entry's slot in
     // probe-cell-key order
     const int64_t e = b * 64 + lane;
-    const BwdEntry& E = ws.entries[min(e, total - 1)];
+    {
+      const int nchunk = (int)min((int64_t)64, total - b * 64) * 10;
+      const uint4* __restrict__ src = reinterpret_cast<const uint4*>(ws.entries + b * 64);
+      uint4 v[10];
+#pragma unroll
+      for (int q = 0; q < 10; ++q) {
+        const int c = q * 64 + lane;
+        v[q] = c < nchunk ? src[c] : make_uint4(0u, 0u, 0u, 0u);
+      }
+      wave_sync();  // the previous batch has read its entries
+#pragma unroll
+      for (int q = 0; q < 10; ++q) {
+        const int c = q * 64 + lane, en = c / 10, f = c - 10 * en;
+        uint2* dst = reinterpret_cast<uint2*>(stage + en * kEntDw + 4 * f);
+        dst[0] = make_uint2(v[q].x, v[q].y);
+        dst[1] = make_uint2(v[q].z, v[q].w);
+      }
+      wave_sync();
+    }
+    const BwdEntry& E = *reinterpret_cast<const BwdEntry*>(stage + lane * kEntDw);
     bool counted = false, ve = false;
     int pk = 0;
     if (e < total) {

@@ -1,15 +1,15 @@
 // Kernels of the render step of the paper's own colour model (model.h): forward
 // and reverse mode with one ray per wave and one sample per lane.
 //
-// A wave takes its rays one at a time.  The 64 lanes evaluate 64 consecutive
+// A wave marches its rays one at a time.  The 64 lanes evaluate 64 consecutive
 // samples of the ray at once (s_i by trilinear interpolation, s_{i+1} from the
 // next lane), the NeuS opacity (Sec. 3.3, Eq. neus, log domain) and the
 // transmittance as a wavefront prefix sum of log(1 - alpha) carried from chunk to
-// chunk.  The shaded samples of the ray (active, alpha > 0) are compacted into an
-// LDS list and shaded 64 per wave instruction stream, whatever their position on
-// the ray.  The reverse mode keeps the whole list, so the colour remaining
-// behind each sample, R_i = sum_{j>=i} w_j C_j, is an exact suffix sum (wavefront
-// suffix scans, last batch first), never a difference.
+// chunk.  The shaded samples (active, alpha > 0) are compacted into LDS and shaded
+// 64 per wave instruction stream: in the forward, the shaded samples of 64
+// consecutive rays share one queue; in the reverse mode, the list holds the whole
+// ray, so the colour remaining behind each sample, R_i = sum_{j>=i} w_j C_j, is an
+// exact suffix sum (wavefront suffix scans, last batch first), never a difference.
 #pragma once
 
 #include "model.h"
@@ -114,9 +114,101 @@ __device__ __forceinline__ void wave_rays(int64_t B, int64_t per_wave, int64_t& 
   r1 = r0 + per_wave < B ? r0 + per_wave : B;
 }
 
+// One chunk of 64 consecutive samples c0 .. c0+63 of a ray, one per lane: which
+// samples may be active (brick bounds of the SDF when given, the tile when the
+// features are tiled), s_i where it is needed (for the sample's own opacity, or
+// as s_{i+1} of the previous sample), the skip rule, the log-domain opacity and
+// the transmittance as a wavefront prefix sum carried in `carry`.  A chunk where
+// no sample may be active costs the tests only.  Returns the ballot of the shaded
+// samples (active, alpha > 0); a shaded lane gets its position, w = T alpha, T,
+// s_i and s_{i+1}.  prev_may carries whether the chunk's last sample may be active.
+struct ChunkOut {
+  double x[3];
+  float w, T, s0, s1;
+};
+
+template <typename ST>
+__device__ __forceinline__ uint64_t model_chunk(const ST* __restrict__ sdf, const RenderArgs& a,
+                                                const Geo& G, const Tiles& tl, const Bricks& K,
+                                                const RayD& r, int c0, int lane, float& carry,
+                                                ChunkOut& o) {
+  const int N = a.N, i = c0 + lane;
+  const bool valid = i < N;
+  sample_pos(r, sample_t(r, valid ? i : N - 1), o.x);
+  int k[3];
+  float f[3];
+  const double kmax = (double)(G.R - 2);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) axis_cell_d(o.x[q], G.inv_h, kmax, k[q], f[q]);
+  bool may = valid;
+  if (K.b && may) {
+    const int br = ((k[2] >> BRICK_SHIFT) * K.nb + (k[1] >> BRICK_SHIFT)) * K.nb + (k[0] >> BRICK_SHIFT);
+    may = brick_may(K, K.b[br]);
+  }
+  if (tl.index && may) {
+    float loc[3];
+    may = tile_slot(tl, G.R, G.inv_h, o.x, loc) >= 0;
+  }
+  // lane 63 also evaluates sample c0 + 64, its successor, when it may be active
+  const bool has_next = lane == 63 && c0 + 64 < N;
+  double xn[3] = {0.0, 0.0, 0.0};
+  if (has_next) sample_pos(r, sample_t(r, c0 + 64), xn);
+  const uint64_t mm = __ballot(may);
+  if (mm == 0) return 0;  // wave-uniform: nothing in this chunk can be active
+  const bool prev = lane > 0 ? ((mm >> (lane - 1)) & 1ull) != 0 : false;
+  float s_i = 0.0f;
+  if (may || prev) {
+    Cell c;
+    c.base = (k[2] * G.R + k[1]) * G.R + k[0];
+    c.fx = f[0];
+    c.fy = f[1];
+    c.fz = f[2];
+    s_i = tri1(sdf, G.R, c);
+  }
+  float s_n = __shfl_down(s_i, 1, 64);
+  if (lane == 63) s_n = (may && has_next) ? tri1(sdf, G.R, cell_d(xn, G.R, G.inv_h)) : 0.0f;
+  const bool act = may && i < N - 1 && (a.skip_thr <= 0.f || fabsf(s_i) <= a.skip_thr);
+  float dl = 0.0f;
+  bool sh = false;
+  if (act) {
+    dl = log_sigmoid(a.tau * s_n) - log_sigmoid(a.tau * s_i);
+    sh = dl < 0.0f;
+  }
+  const float incl = wave_prefix_incl(sh ? dl : 0.0f, lane);
+  float excl = __shfl_up(incl, 1, 64);
+  if (lane == 0) excl = 0.0f;
+  const uint64_t mask = __ballot(sh);
+  if (sh) {
+    o.T = expf(carry + excl);
+    o.w = o.T * -expm1f(dl);
+    o.s0 = s_i;
+    o.s1 = s_n;
+  }
+  carry += __shfl(incl, 63, 64);
+  return mask;
+}
+
+// Forward (Sec. 3.3: c = sum_i T_i alpha_i C_i).  A wave takes its rays in groups of
+// 64: each ray is marched chunk by chunk and its shaded samples join one queue
+// shared by the group's rays; whenever 64 are queued the wave shades them together
+// (one sample per lane, whatever ray it belongs to).  Each ray's weighted colours
+// are summed in sample order by the first lane of its run in the batch.
+constexpr int MODEL_Q = 128;     // queue: < 64 waiting plus one chunk of 64
+constexpr int MODEL_GROUP = 64;  // rays per group
+
+struct ModelFwdLds {
+  double x[MODEL_Q][3];
+  float w[MODEL_Q], tm[MODEL_Q];
+  int rs[MODEL_Q];                // ray of the entry within the group
+  float v[MODEL_GROUP][3];        // view direction of each ray
+  float acc[MODEL_GROUP][5];      // rgb, depth, weight sum
+  float logT[MODEL_GROUP];
+  float part[64][5];              // the batch's per-sample terms
+};
+
 template <typename ST, typename FT, int NSH, int M, int H, int L>
 __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per_wave) {
-  __shared__ ModelEntries E;
+  __shared__ ModelFwdLds Q;
   const int lane = threadIdx.x;
   const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
   const FT* __restrict__ feat = static_cast<const FT*>(a.feat);
@@ -124,6 +216,7 @@ __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per
   cfloat* __restrict__ W = const_mlp(a.mlp);
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
   const Tiles tl{a.tile_index, a.tile_T};
+  const Bricks K = make_bricks(a.bounds, a.R, a.skip_thr);
   const int nin = model_n_in(a.flags);
   // reduced-precision MLP: a copy with rounded weights in LDS (rounded once, not on
   // every use); FP32 reads the weights with scalar loads
@@ -136,56 +229,122 @@ __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per
     if constexpr (M == MLP_F32) model_mlp_fwd<M, H, L>(W, nin, z, pre, out);
     else model_mlp_fwd<M, H, L, true>(Wr, nin, z, pre, out);
   };
+  // shade queue entries [0, nb) and add them to their rays
+  auto shade = [&](int nb) {
+    wave_sync();
+    float t[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    int j = -1;
+    if (lane < nb) {
+      j = Q.rs[lane];
+      const double x[3] = {Q.x[lane][0], Q.x[lane][1], Q.x[lane][2]};
+      const float v[3] = {Q.v[j][0], Q.v[j][1], Q.v[j][2]};
+      ModelShade<NSH> S;
+      model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
+      float pre[L * H], out[3];
+      mlp_fwd(S.z, pre, out);
+      const float w = Q.w[lane];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t[c] = w * sigmoidf(out[c]);
+      t[3] = w * Q.tm[lane];
+      t[4] = w;
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Q.part[lane][c] = t[c];
+    const int jp = __shfl_up(j, 1, 64);
+    const bool lead = lane < nb && (lane == 0 || jp != j);
+    const uint64_t leads = __ballot(lead);
+    wave_sync();
+    if (lead) {
+      const uint64_t above = lane == 63 ? 0ull : (leads >> (lane + 1)) << (lane + 1);
+      const int end = above ? __ffsll((long long)above) - 1 : nb;
+      float s[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) s[c] = Q.acc[j][c];
+      for (int q = lane; q < end; ++q)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) s[c] += Q.part[q][c];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) Q.acc[j][c] = s[c];
+    }
+    wave_sync();
+  };
   int64_t r0, r1;
   wave_rays(a.B, per_wave, r0, r1);
-  for (int64_t ray = r0; ray < r1; ++ray) {
-    RayD r;
-    const bool hit = ray_setup_d(a.rays_o[3 * ray], a.rays_o[3 * ray + 1], a.rays_o[3 * ray + 2],
-                                 a.rays_d[3 * ray], a.rays_d[3 * ray + 1], a.rays_d[3 * ray + 2],
-                                 a.N, r);
-    float rgb[3] = {0.f, 0.f, 0.f}, depth = 0.f, wsum = 0.f, logT = 0.f;
-    if (hit) {
-      const int n = model_march(sdf, a, G, tl, r, lane, E, logT);
-      wave_sync();
-      const float v[3] = {(float)-r.d[0], (float)-r.d[1], (float)-r.d[2]};
-      for (int b0 = 0; b0 < n; b0 += 64) {
-        const int e = b0 + lane;
-        float wc[3] = {0.f, 0.f, 0.f}, w = 0.f, wt = 0.f;
-        if (e < n) {
-          const int i = E.i[e];
-          double x[3];
-          sample_pos(r, sample_t(r, i), x);
-          ModelShade<NSH> S;
-          model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
-          float pre[L * H], out[3];
-          mlp_fwd(S.z, pre, out);
-          w = E.w[e];
+  for (int64_t g0 = r0; g0 < r1; g0 += MODEL_GROUP) {
+    const int ng = (int)min((int64_t)MODEL_GROUP, r1 - g0);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) wc[c] = w * sigmoidf(out[c]);
-          wt = w * (float)(sample_t(r, i) + 0.5 * r.dt);
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) rgb[c] += wave_sum(wc[c]);
-        depth += wave_sum(wt);
-        wsum += wave_sum(w);
+    for (int c = 0; c < 5; ++c) Q.acc[lane][c] = 0.f;
+    Q.logT[lane] = 0.f;
+    int qn = 0;  // queued entries (wave-uniform)
+    for (int j = 0; j < ng; ++j) {
+      const int64_t ray = g0 + j;
+      RayD r;
+      const bool hit = ray_setup_d(a.rays_o[3 * ray], a.rays_o[3 * ray + 1], a.rays_o[3 * ray + 2],
+                                   a.rays_d[3 * ray], a.rays_d[3 * ray + 1], a.rays_d[3 * ray + 2],
+                                   a.N, r);
+      if (lane == 0) {
+        Q.v[j][0] = (float)-r.d[0];
+        Q.v[j][1] = (float)-r.d[1];
+        Q.v[j][2] = (float)-r.d[2];
       }
-      wave_sync();
+      if (!hit) continue;  // wave-uniform
+      float carry = 0.0f;
+      for (int c0 = 0; c0 < a.N - 1; c0 += 64) {
+        ChunkOut o;
+        const uint64_t mask = model_chunk(sdf, a, G, tl, K, r, c0, lane, carry, o);
+        if (!mask) continue;
+        if ((mask >> lane) & 1ull) {
+          const int e = qn + lane_rank(mask);
+          Q.x[e][0] = o.x[0];
+          Q.x[e][1] = o.x[1];
+          Q.x[e][2] = o.x[2];
+          Q.w[e] = o.w;
+          Q.tm[e] = (float)(sample_t(r, c0 + lane) + 0.5 * r.dt);
+          Q.rs[e] = j;
+        }
+        qn += (int)__popcll(mask);
+        if (qn >= 64) {
+          shade(64);
+          // the rest of the queue moves to its front
+          const int src = 64 + lane;
+          const bool mv = src < qn;
+          double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+          float w = 0.f, tm = 0.f;
+          int rs = 0;
+          if (mv) {
+            x0 = Q.x[src][0], x1 = Q.x[src][1], x2 = Q.x[src][2];
+            w = Q.w[src], tm = Q.tm[src], rs = Q.rs[src];
+          }
+          wave_sync();
+          if (mv) {
+            Q.x[lane][0] = x0, Q.x[lane][1] = x1, Q.x[lane][2] = x2;
+            Q.w[lane] = w, Q.tm[lane] = tm, Q.rs[lane] = rs;
+          }
+          qn -= 64;
+        }
+      }
+      if (lane == 0) Q.logT[j] = carry;
     }
-    if (lane == 0) {
-      a.rgb[3 * ray] = rgb[0];
-      a.rgb[3 * ray + 1] = rgb[1];
-      a.rgb[3 * ray + 2] = rgb[2];
+    if (qn > 0) shade(qn);
+    wave_sync();
+    if (lane < ng) {
+      const int64_t ray = g0 + lane;
+      const float* s = Q.acc[lane];
+      a.rgb[3 * ray] = s[0];
+      a.rgb[3 * ray + 1] = s[1];
+      a.rgb[3 * ray + 2] = s[2];
       if (a.aux) {
-        a.aux[4 * ray] = rgb[0];
-        a.aux[4 * ray + 1] = rgb[1];
-        a.aux[4 * ray + 2] = rgb[2];
-        a.aux[4 * ray + 3] = logT;
+        a.aux[4 * ray] = s[0];
+        a.aux[4 * ray + 1] = s[1];
+        a.aux[4 * ray + 2] = s[2];
+        a.aux[4 * ray + 3] = Q.logT[lane];
       }
       if (a.depth_wsum) {
-        a.depth_wsum[2 * ray] = depth;
-        a.depth_wsum[2 * ray + 1] = wsum;
+        a.depth_wsum[2 * ray] = s[3];
+        a.depth_wsum[2 * ray + 1] = s[4];
       }
     }
+    wave_sync();
   }
 }
 

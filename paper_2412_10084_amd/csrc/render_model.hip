@@ -17,10 +17,11 @@ hipError_t launch_render_model(const RenderArgs& a, bool backward, int sdf_dt, i
                                int mlp_dt, int n_sh, int hidden, int layers, hipStream_t s) {
   if (a.B == 0) return hipSuccess;
   if (sdf_dt != 0 || a.N > MODEL_EMAX + 1) return hipErrorInvalidValue;
-  // each wave takes a contiguous range of rays; the reverse mode flushes one MLP
-  // gradient atomic per parameter per wave, so it runs fewer, longer waves
-  const int64_t most = backward ? 2048 : 32768;
-  const int64_t waves = a.B < most ? a.B : most;
+  // each wave takes a contiguous range of rays: one group of MODEL_GROUP rays in the
+  // forward; the reverse mode flushes one MLP gradient atomic per parameter per
+  // wave, so it runs fewer, longer waves
+  const int64_t most = 2048;
+  const int64_t waves = backward ? (a.B < most ? a.B : most) : (a.B + MODEL_GROUP - 1) / MODEL_GROUP;
   const int64_t per = (a.B + waves - 1) / waves;
   const dim3 grid((unsigned)((a.B + per - 1) / per));
 #define PSDF_MODEL_M(H, L, BWD)                                                       \

@@ -43,5 +43,9 @@ def test_alg_bytes_and_kernel_names():
     assert bench.alg_bytes_per_ray("render_backward", 128, 2.0, True) == 32 * 128 + 2 * (720 + 32 + 1376) + 52
     assert bench.kernel_base_name("void psdf::tape_shade_kernel<1>(psdf::RenderArgs, psdf::BwdWs)") == "tape_shade_kernel"
     assert bench.kernel_base_name("psdf::bwd_box_kernel(psdf::RenderArgs, psdf::BwdWs)") == "bwd_box_kernel"
+    # names the profiler leaves mangled, and library kernels in anonymous namespaces
+    assert bench.kernel_base_name("_ZN4psdf17render_fwd_kernelIfDF16_Li9ELi1EEEvNS_10RenderArgsENS_5BwdWsEi") \
+        == "render_fwd_kernel"
+    assert bench.kernel_base_name("void at::native::(anonymous namespace)::distribution_kernel<float>(int)") == ""
     r = bench.roofline_obj("render_forward", 8e9, 1.0, None)
     assert abs(r["frac"] - 1.0) < 1e-12 and r["achieved"] == 8000.0
