@@ -45,67 +45,6 @@ __device__ __forceinline__ float wave_suffix_incl(float v, int lane) {
   return v;
 }
 
-template <typename ST>
-__device__ __forceinline__ float sdf_at(const ST* __restrict__ sdf, const Geo& G, const RayD& r,
-                                        int i) {
-  double x[3];
-  sample_pos(r, sample_t(r, i), x);
-  return tri1(sdf, G.R, cell_d(x, G.R, G.inv_h));
-}
-
-// whether sample i lies in an allocated tile (always, with dense features)
-__device__ __forceinline__ bool in_tile(const Tiles& tl, const Geo& G, const RayD& r, int i) {
-  if (!tl.index) return true;
-  double x[3];
-  float loc[3];
-  sample_pos(r, sample_t(r, i), x);
-  return tile_slot(tl, G.R, G.inv_h, x, loc) >= 0;
-}
-
-// The ray's samples: opacity, transmittance and the list of shaded samples.
-// Returns the number of entries; logT = log T after the last sample.
-template <typename ST>
-__device__ __forceinline__ int model_march(const ST* __restrict__ sdf, const RenderArgs& a,
-                                           const Geo& G, const Tiles& tl, const RayD& r, int lane,
-                                           ModelEntries& E, float& logT) {
-  int n = 0;
-  float carry = 0.0f;
-  const int N = a.N;
-  for (int c0 = 0; c0 < N - 1; c0 += 64) {  // wave-uniform
-    const int i = c0 + lane;
-    const float s_i = i < N ? sdf_at(sdf, G, r, i) : 0.0f;
-    float s_n = __shfl_down(s_i, 1, 64);
-    if (lane == 63) s_n = c0 + 64 < N ? sdf_at(sdf, G, r, c0 + 64) : 0.0f;
-    // samples in empty tiles are inactive (the skip rule of the sparse grid)
-    const bool act = i < N - 1 && (a.skip_thr <= 0.f || fabsf(s_i) <= a.skip_thr) &&
-                     in_tile(tl, G, r, i);
-    float dl = 0.0f;
-    bool sh = false;
-    if (act) {
-      dl = log_sigmoid(a.tau * s_n) - log_sigmoid(a.tau * s_i);
-      sh = dl < 0.0f;
-    }
-    const float ldl = sh ? dl : 0.0f;
-    const float incl = wave_prefix_incl(ldl, lane);
-    float excl = __shfl_up(incl, 1, 64);
-    if (lane == 0) excl = 0.0f;
-    const uint64_t mask = __ballot(sh);
-    if (sh) {
-      const float T = expf(carry + excl);
-      const int e = n + lane_rank(mask);
-      E.i[e] = i;
-      E.w[e] = T * -expm1f(dl);
-      E.T[e] = T;
-      E.s0[e] = s_i;
-      E.s1[e] = s_n;
-    }
-    n += (int)__popcll(mask);
-    carry += __shfl(incl, 63, 64);
-  }
-  logT = carry;
-  return n;
-}
-
 // rays [r0, r1) of this wave: contiguous ranges, remapped so that each XCD
 // (with its own L2) takes one contiguous part of the batch
 __device__ __forceinline__ void wave_rays(int64_t B, int64_t per_wave, int64_t& r0, int64_t& r1) {
@@ -348,11 +287,23 @@ __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per
   }
 }
 
+// Reverse mode (gradients added into a.g_*).  A wave collects the shaded samples of
+// consecutive rays (at most 64 rays and MODEL_EMAX samples) before it processes
+// them, so every batch of the shading and of the reverse mode is full whatever the
+// number of shaded samples per ray: the colours of the listed samples, the colour
+// behind each sample by a suffix scan segmented by ray (last batch first), then
+// per batch of 64 the MLP and the interpolations in reverse, with
+//   dL/dC_i = w_i dL/drgb,  dL/d dl_i = dL/drgb . (R_i - T_i C_i),
+//   d dl_i/d s_i = -tau sigma(-tau s_i),  d dl_i/d s_{i+1} = tau sigma(-tau s_{i+1}).
 template <int NSH>
 struct ModelBwdLds {
   ModelEntries E;
+  unsigned char rs[MODEL_EMAX];  // ray of the entry within the group
   float C[MODEL_EMAX][3];
   float gdl[MODEL_EMAX];
+  RayD ray[MODEL_GROUP];
+  float v[MODEL_GROUP][3];
+  float dL[MODEL_GROUP][3];
   union {
     DwLds dw;
     ProbeAcc<NSH> pa;
@@ -362,11 +313,6 @@ struct ModelBwdLds {
   int fb[64];
 };
 
-// Reverse mode (gradients added into a.g_*): per ray, the march and the colours of
-// its shaded samples, the suffix walk for dL/d dl_i, then per batch of 64 shaded
-// samples the MLP and the interpolations in reverse, with
-//   dL/dC_i = w_i dL/drgb,  dL/d dl_i = dL/drgb . (R_i - T_i C_i),
-//   d dl_i/d s_i = -tau sigma(-tau s_i),  d dl_i/d s_{i+1} = tau sigma(-tau s_{i+1}).
 template <typename ST, typename FT, int NSH, int M, int H, int L>
 __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per_wave) {
   __shared__ ModelBwdLds<NSH> S_;
@@ -379,6 +325,7 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
   cfloat* __restrict__ W = const_mlp(a.mlp);
   const Geo G{a.R, a.P, 2.0 / (a.R - 1), 0.5 * (a.R - 1), 0.5 * (a.P - 1), a.flags};
   const Tiles tl{a.tile_index, a.tile_T};
+  const Bricks K = make_bricks(a.bounds, a.R, a.skip_thr);
   const int nin = model_n_in(a.flags);
   // reduced-precision MLP: a copy with rounded weights in LDS (rounded once, not on
   // every use); FP32 reads the weights with scalar loads
@@ -395,27 +342,18 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
   ModelDw<H, L> D;
   model_dw_zero(D);
   bool any = false;
-  int64_t r0, r1;
-  wave_rays(a.B, per_wave, r0, r1);
-  for (int64_t ray = r0; ray < r1; ++ray) {
-    const float dL[3] = {a.dL[3 * ray], a.dL[3 * ray + 1], a.dL[3 * ray + 2]};
-    if (dL[0] == 0.f && dL[1] == 0.f && dL[2] == 0.f) continue;  // wave-uniform
-    RayD r;
-    if (!ray_setup_d(a.rays_o[3 * ray], a.rays_o[3 * ray + 1], a.rays_o[3 * ray + 2],
-                     a.rays_d[3 * ray], a.rays_d[3 * ray + 1], a.rays_d[3 * ray + 2], a.N, r))
-      continue;
-    float logT;
-    const int n = model_march(sdf, a, G, tl, r, lane, E, logT);
-    if (n == 0) continue;
-    any = true;
+
+  // the listed samples of the group: entries [0, n) of rays [0, nr)
+  auto process = [&](int n) {
     wave_sync();
-    const float v[3] = {(float)-r.d[0], (float)-r.d[1], (float)-r.d[2]};
-    // colours of the shaded samples
+    // colours of the listed samples
     for (int b0 = 0; b0 < n; b0 += 64) {
       const int e = b0 + lane;
       if (e < n) {
+        const int j = Ls.rs[e];
         double x[3];
-        sample_pos(r, sample_t(r, E.i[e]), x);
+        sample_pos(Ls.ray[j], sample_t(Ls.ray[j], E.i[e]), x);
+        const float v[3] = {Ls.v[j][0], Ls.v[j][1], Ls.v[j][2]};
         ModelShade<NSH> S;
         model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
         float pre[L * H], out[3];
@@ -425,22 +363,38 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
       }
     }
     wave_sync();
-    // suffix walk, last batch first: R_e = sum_{e' >= e} w C
+    // R_e = sum over the ray's entries e' >= e of w C: a suffix scan segmented by ray,
+    // last batch first; `carry` continues the ray that starts the later batch
     {
       float carry[3] = {0.f, 0.f, 0.f};
+      int carry_ray = -1;
       for (int b0 = ((n - 1) >> 6) << 6; b0 >= 0; b0 -= 64) {
         const int e = b0 + lane;
         const bool ve = e < n;
+        const int j = ve ? Ls.rs[e] : -1 - lane;  // lanes past the end: their own segments
         float Rv[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float wc = ve ? E.w[e] * Ls.C[e][c] : 0.f;
-          const float suf = wave_suffix_incl(wc, lane);
-          Rv[c] = suf + carry[c];
-          carry[c] += __shfl(suf, 0, 64);
+        for (int c = 0; c < 3; ++c) Rv[c] = ve ? E.w[e] * Ls.C[e][c] : 0.f;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int jd = __shfl_down(j, d, 64);
+          const bool same = lane + d < 64 && jd == j;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float y = __shfl_down(Rv[c], d, 64);
+            if (same) Rv[c] += y;
+          }
         }
+        if (j == carry_ray) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) Rv[c] += carry[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) carry[c] = __shfl(Rv[c], 0, 64);
+        carry_ray = __shfl(j, 0, 64);
         if (ve) {
           const float T = E.T[e];
+          const float* dL = Ls.dL[j];
           Ls.gdl[e] = dL[0] * (Rv[0] - T * Ls.C[e][0]) + dL[1] * (Rv[1] - T * Ls.C[e][1]) +
                       dL[2] * (Rv[2] - T * Ls.C[e][2]);
         }
@@ -456,17 +410,22 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
       ModelShade<NSH> S;
       float pre[L * H], out[3], dout[3] = {0.f, 0.f, 0.f};
       float gdl = 0.f, s0 = 0.f, s1 = 0.f;
-      int i = 0;
+      float v[3] = {0.f, 0.f, 0.f};
+      int i = 0, j = 0;
       if (ve) {
+        j = Ls.rs[e];
         i = E.i[e];
-        sample_pos(r, sample_t(r, i), x);
+        sample_pos(Ls.ray[j], sample_t(Ls.ray[j], i), x);
+        v[0] = Ls.v[j][0];
+        v[1] = Ls.v[j][1];
+        v[2] = Ls.v[j][2];
         model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
         mlp_fwd(S.z, pre, out);
         const float w = E.w[e];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float C = sigmoidf(out[c]);
-          dout[c] = w * dL[c] * C * (1.f - C);
+          const float Cc = sigmoidf(out[c]);
+          dout[c] = w * Ls.dL[j][c] * Cc * (1.f - Cc);
         }
         gdl = Ls.gdl[e];
         s0 = E.s0[e];
@@ -475,9 +434,9 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
 #pragma unroll
         for (int k = 0; k < L * H; ++k) pre[k] = 0.f;
 #pragma unroll
-        for (int j = 0; j < MNIN; ++j) S.z[j] = 0.f;
+        for (int q = 0; q < MNIN; ++q) S.z[q] = 0.f;
 #pragma unroll
-        for (int j = 0; j < NSH; ++j) S.Y[j] = 0.f;
+        for (int q = 0; q < NSH; ++q) S.Y[q] = 0.f;
       }
       float dpre[L * H], dz[MNIN];
       if constexpr (M == MLP_F32) model_mlp_bwd<M, H, L>(W, nin, pre, dout, dpre, dz);
@@ -507,7 +466,7 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
           const float gs1 = a.tau * sigmoidf(-a.tau * s1) * gdl;
           if (gs1 != 0.f) {
             double x1[3];
-            sample_pos(r, sample_t(r, i + 1), x1);
+            sample_pos(Ls.ray[j], sample_t(Ls.ray[j], i + 1), x1);
             scatter8(a.g_sdf, G.R, cell_d(x1, G.R, G.inv_h), gs1);
           }
         }
@@ -535,7 +494,55 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
       }
       wave_sync();
     }
+  };
+
+  int n = 0, nr = 0;  // listed samples and rays (wave-uniform)
+  int64_t r0, r1;
+  wave_rays(a.B, per_wave, r0, r1);
+  for (int64_t ray = r0; ray < r1; ++ray) {
+    const float dL[3] = {a.dL[3 * ray], a.dL[3 * ray + 1], a.dL[3 * ray + 2]};
+    if (dL[0] == 0.f && dL[1] == 0.f && dL[2] == 0.f) continue;  // wave-uniform
+    RayD r;
+    if (!ray_setup_d(a.rays_o[3 * ray], a.rays_o[3 * ray + 1], a.rays_o[3 * ray + 2],
+                     a.rays_d[3 * ray], a.rays_d[3 * ray + 1], a.rays_d[3 * ray + 2], a.N, r))
+      continue;
+    // room for every sample of this ray
+    if (nr == MODEL_GROUP || n + (a.N - 1) > MODEL_EMAX) {
+      process(n);
+      n = nr = 0;
+    }
+    wave_sync();
+    const int n0 = n;
+    float carry = 0.0f;
+    for (int c0 = 0; c0 < a.N - 1; c0 += 64) {
+      ChunkOut o;
+      const uint64_t mask = model_chunk(sdf, a, G, tl, K, r, c0, lane, carry, o);
+      if (!mask) continue;
+      if ((mask >> lane) & 1ull) {
+        const int e = n + lane_rank(mask);
+        E.i[e] = c0 + lane;
+        E.w[e] = o.w;
+        E.T[e] = o.T;
+        E.s0[e] = o.s0;
+        E.s1[e] = o.s1;
+        Ls.rs[e] = (unsigned char)nr;
+      }
+      n += (int)__popcll(mask);
+    }
+    if (n == n0) continue;  // no shaded sample: nothing to add
+    if (lane == 0) {
+      Ls.ray[nr] = r;
+      Ls.v[nr][0] = (float)-r.d[0];
+      Ls.v[nr][1] = (float)-r.d[1];
+      Ls.v[nr][2] = (float)-r.d[2];
+      Ls.dL[nr][0] = dL[0];
+      Ls.dL[nr][1] = dL[1];
+      Ls.dL[nr][2] = dL[2];
+    }
+    ++nr;
+    any = true;
   }
+  if (n > 0) process(n);
   if (any && a.g_mlp) model_dw_flush<H, L>(D, lane, nin, a.g_mlp);
 }
 
