@@ -27,12 +27,14 @@ def model_field(seed, R, P, n_sh, hidden, layers, flags, shape="sphere"):
     return f
 
 
-def gpu_field(f, half=False, mlp_dtype=0):
+def gpu_field(f, half=False, mlp_dtype=0, bounds=False):
     import paper_2412_10084_amd as ps
     t = torch()
     fdt = t.float16 if half else t.float32
-    return ps.Field(sdf=dev(f.sdf), feat=dev(f.feat, fdt), probes=dev(f.probes, fdt),
-                    mlp=dev(f.mlp), mlp_dtype=mlp_dtype, hidden=f.hidden, layers=f.layers)
+    sdf = dev(f.sdf)
+    return ps.Field(sdf=sdf, feat=dev(f.feat, fdt), probes=dev(f.probes, fdt),
+                    mlp=dev(f.mlp), mlp_dtype=mlp_dtype, hidden=f.hidden, layers=f.layers,
+                    bounds=ps.sdf_bounds(sdf) if bounds else None)
 
 
 def run(fld, o, d, N, skip, flags, dL=None):
@@ -137,9 +139,35 @@ def test_paper_model_mixed(mlp_dt, prec, ctol):
     grad_check(got["grads"], g_ref, prec + "_paper")
 
 
-def test_paper_model_train256_full_size_sampled():
+@pytest.mark.parametrize("n_sh,hidden,layers,flags", [CASES[0], CASES[2]])
+def test_paper_model_brick_skipping_changes_nothing(n_sh, hidden, layers, flags):
+    """With the SDF's brick bounds the march skips chunks that cannot be active: the
+    forward is bit-identical to the march without them, and the gradients match the
+    oracle (and the unbounded run up to the FP32 atomics' order)."""
+    f = model_field(3, 64, 16, n_sh, hidden, layers, flags)
+    o, d = rays(8, 32, 16)
+    N, skip = 96, 4.0
+    of = oracle.field_from(f)
+    ref = oracle.render_forward(of, o, d, N, skip_voxels=skip, flags=flags)
+    keep = ref["margin"] > SKIP_MARGIN
+    rng = np.random.default_rng(4)
+    dL = rng.choice([-1.0, 1.0], size=(o.shape[0], 3)) / (3.0 * o.shape[0])
+    dL[~keep] = 0.0
+    plain = run(gpu_field(f), o, d, N, skip, flags, dL)
+    fast = run(gpu_field(f, bounds=True), o, d, N, skip, flags, dL)
+    for k in ("rgb", "aux", "depth_wsum"):
+        np.testing.assert_array_equal(fast[k], plain[k])
+    assert np.count_nonzero(plain["rgb"].sum(1)) > 300
+    g_ref = oracle.render_backward(of, o, d, dL, N, skip_voxels=skip, flags=flags)
+    grad_check(fast["grads"], g_ref, "fp32")
+    grad_check(fast["grads"], plain["grads"], "fp32")
+
+
+@pytest.mark.parametrize("bounds", [False, True])
+def test_paper_model_train256_full_size_sampled(bounds):
     """train256's launch (256^3 / 64^3, 2^18 rays, N = 128, skip 4 voxels) with the
-    paper's model (16 SH coefficients): the oracle evaluates 1500 sampled rays."""
+    paper's model (16 SH coefficients), with and without the brick bounds the
+    benchmark passes: the oracle evaluates 1500 sampled rays."""
     w = wl.WORKLOADS["train256"]
     f = model_field(0, w.R, w.P, 16, 32, 2, PAPER)
     o, d = rays(w.views, w.W, w.H)
@@ -152,8 +180,8 @@ def test_paper_model_train256_full_size_sampled():
     sel = idx[keep][:1500]
     dL = np.zeros((o.shape[0], 3))
     dL[sel] = rng.choice([-1.0, 1.0], size=(sel.size, 3)) / (3.0 * o.shape[0])
-    print("paper model train256 launch", flush=True)
-    got = run(gpu_field(f), o, d, w.n_samples, w.skip_voxels, PAPER, dL)
+    print(f"paper model train256 launch, bounds={bounds}", flush=True)
+    got = run(gpu_field(f, bounds=bounds), o, d, w.n_samples, w.skip_voxels, PAPER, dL)
     nbad, emax = color_check(got["rgb"][idx], ref["rgb"], FP32_COLOR_REL, FP32_COLOR_ABS, keep)
     assert nbad == 0, f"{nbad} colours off, max err {emax:.3g}"
     assert np.count_nonzero(ref["rgb"].sum(1)) > 200

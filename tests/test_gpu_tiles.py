@@ -16,13 +16,14 @@ pytestmark = pytest.mark.gpu
 PAPER = 8 | 16
 
 
-def gpu_tiled(f, half=False, mlp_dtype=0):
+def gpu_tiled(f, half=False, mlp_dtype=0, bounds=False):
     import paper_2412_10084_amd as ps
     t = torch()
     fdt = t.float16 if half else t.float32
-    return ps.Field(sdf=dev(f.sdf), feat=dev(f.tiles.planes, fdt), probes=dev(f.probes, fdt),
+    sdf = dev(f.sdf)
+    return ps.Field(sdf=sdf, feat=dev(f.tiles.planes, fdt), probes=dev(f.probes, fdt),
                     mlp=dev(f.mlp), mlp_dtype=mlp_dtype, hidden=f.hidden, layers=f.layers,
-                    tiles=dev(f.tiles.index))
+                    tiles=dev(f.tiles.index), bounds=ps.sdf_bounds(sdf) if bounds else None)
 
 
 def run(fld, o, d, N, skip, flags, dL):
@@ -86,9 +87,11 @@ def test_empty_tiles_render_nothing():
     assert not any(v.any() for v in g.values())
 
 
-def test_tiled_train256_class_launch_sampled():
+@pytest.mark.parametrize("bounds", [False, True])
+def test_tiled_train256_class_launch_sampled(bounds):
     """T = 16 (R = 257, P = 17), 2^18 rays, N = 128, skip 4 voxels: the forward and
-    backward over the whole batch, the oracle on 1500 sampled rays."""
+    backward over the whole batch, with and without the SDF's brick bounds, the
+    oracle on 1500 sampled rays."""
     w = wl.WORKLOADS["train256"]
     f = wl.tiled_field(0, 16)
     assert f.R == 257
@@ -101,8 +104,8 @@ def test_tiled_train256_class_launch_sampled():
     sel = idx[keep][:1500]
     dL = np.zeros((o.shape[0], 3))
     dL[sel] = rng.choice([-1.0, 1.0], size=(sel.size, 3)) / (3.0 * o.shape[0])
-    print("tiled launch: T=16, 2^18 rays", flush=True)
-    rgb, g = run(gpu_tiled(f), o, d, w.n_samples, w.skip_voxels, 0, dL)
+    print(f"tiled launch: T=16, 2^18 rays, bounds={bounds}", flush=True)
+    rgb, g = run(gpu_tiled(f, bounds=bounds), o, d, w.n_samples, w.skip_voxels, 0, dL)
     nbad, emax = color_check(rgb[idx], ref["rgb"], FP32_COLOR_REL, FP32_COLOR_ABS, keep)
     assert nbad == 0, f"{nbad} colours off, max err {emax:.3g}"
     g_ref = oracle.render_backward(of, o[sel], d[sel], dL[sel], w.n_samples,
