@@ -113,10 +113,20 @@ __device__ __forceinline__ float q_plane(EikLds& L, int R, int x0, int y0, int z
     const float gxv = (s0[c + 1] - s0[c - 1]) * inv2h;
     const float gyv = (s0[c + SXW] - s0[c - SXW]) * inv2h;
     const float gzv = (sp[c] - sm[c]) * inv2h;
-    const float gn = sqrtf(gxv * gxv + gyv * gyv + gzv * gzv);
-    const float e = gn - 1.0f;
+    const float g2 = gxv * gxv + gyv * gyv + gzv * gzv;
     const bool inner = gx >= 1 && gy >= 1 && z >= 1 && gx <= R - 2 && gy <= R - 2 && z <= R - 2;
-    const float f = inner && gn > 0.f ? 2.0f * e / gn : 0.f;
+    // 2 (|g| - 1) / |g| = 2 - 2 / |g| with the hardware reciprocal square root (1 ulp);
+    // gradients too small for it (never on an SDF) take the correctly rounded forms
+    float gn, f;
+    if (g2 >= 1e-30f) {
+      const float rg = __builtin_amdgcn_rsqf(g2);
+      gn = g2 * rg;
+      f = inner ? 2.0f - 2.0f * rg : 0.f;
+    } else {
+      gn = sqrtf(g2);
+      f = inner && gn > 0.f ? 2.0f * (gn - 1.0f) / gn : 0.f;
+    }
+    const float e = gn - 1.0f;
     qxy[0 * QN + idx] = f * gxv;
     qxy[1 * QN + idx] = f * gyv;
     qz[idx] = f * gzv;
