@@ -332,6 +332,98 @@ __device__ __forceinline__ void model_round_mlp(const float* __restrict__ W, flo
   }
 }
 
+// The MLP of a wave's 64 samples on MFMA (FP16 or BF16 operands, FP32 accumulation),
+// from the rounded copy `Wr` in LDS.  Samples lie on the N dimension, in four blocks
+// of 16: a layer's accumulator fragment (lane i + 16 g holds hidden units 4g .. 4g+3
+// of sample i of the block) is exactly the B operand of the next layer, so only the
+// inputs and the outputs pass through LDS.  Every lane of the wave calls it (lanes
+// without a sample pass zero inputs).
+//   H0^T = W0 (H x 16 padded inputs) . Z^T,  H1^T = W1 (H x H) . relu(H0^T + b0),
+//   O^T = Wo (16 padded outputs x H) . relu(H_{L-1}^T + b_{L-1})
+template <int M>
+struct ModelMfmaLds {
+  typename MType<M>::t zs[64][16];
+  float cs[64][4];
+};
+
+template <int M, int H, int L>
+__device__ __forceinline__ void model_mlp_wave(const float* Wr, int nin, ModelMfmaLds<M>& S,
+                                               int lane, const float z[MNIN], float out[3]) {
+  typedef typename MType<M>::t T;
+  typedef typename MType<M>::v V4;
+  constexpr int NT = H / 16;  // 16-row tiles of a hidden layer
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    V4 zq;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * q + r;
+      zq[r] = (T)(k < MNIN && k < nin ? z[k < MNIN ? k : 0] : 0.0f);
+    }
+    *reinterpret_cast<V4*>(&S.zs[lane][4 * q]) = zq;
+  }
+  const int ob0 = H * nin, ow1 = ob0 + H, ob1 = ow1 + (L - 1) * H * H, owo = ob1 + (L - 1) * H,
+            obo = owo + 3 * H;
+  V4 a0[NT], ao[NT];
+  float bb0[NT][4], bo[4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * g + r;
+      a0[t][r] = (T)(k < nin ? Wr[(16 * t + i) * nin + k] : 0.0f);
+      bb0[t][r] = Wr[ob0 + 16 * t + k];
+      ao[t][r] = (T)(i < 3 ? Wr[owo + i * H + 16 * t + k] : 0.0f);
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bo[r] = 4 * g + r < 3 ? Wr[obo + 4 * g + r] : 0.0f;
+  wave_sync();
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const V4 bz = *reinterpret_cast<const V4*>(&S.zs[16 * b + i][4 * g]);
+    V4 h[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      f4 d = {0.f, 0.f, 0.f, 0.f};
+      d = MType<M>::mma(a0[t], bz, d);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[t][r] = (T)fmaxf(d[r] + bb0[t][r], 0.0f);
+    }
+    if constexpr (L == 2) {
+      V4 h2[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        f4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt) {
+          V4 a1;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a1[r] = (T)Wr[ow1 + (16 * t + i) * H + 16 * kt + 4 * g + r];
+          d = MType<M>::mma(a1, h[kt], d);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h2[t][r] = (T)fmaxf(d[r] + Wr[ob1 + 16 * t + 4 * g + r], 0.0f);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) h[t] = h2[t];
+    }
+    f4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) o = MType<M>::mma(ao[kt], h[kt], o);
+    if (g == 0) {
+      S.cs[16 * b + i][0] = o[0] + bo[0];
+      S.cs[16 * b + i][1] = o[1] + bo[1];
+      S.cs[16 * b + i][2] = o[2] + bo[2];
+    }
+  }
+  wave_sync();
+  out[0] = S.cs[lane][0];
+  out[1] = S.cs[lane][1];
+  out[2] = S.cs[lane][2];
+  wave_sync();
+}
+
 // ---------------------------------------------------------------------------
 // MLP weight gradients of a batch of samples (one per lane) as outer-product sums
 // on FP32 MFMA, in 16 x 16 tiles (rows: a layer's outputs; columns: its inputs

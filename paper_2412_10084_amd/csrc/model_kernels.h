@@ -148,6 +148,7 @@ struct ModelFwdLds {
 template <typename ST, typename FT, int NSH, int M, int H, int L>
 __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per_wave) {
   __shared__ ModelFwdLds Q;
+  __shared__ ModelMfmaLds<M> MM;  // reduced-precision MLP on MFMA
   const int lane = threadIdx.x;
   const ST* __restrict__ sdf = static_cast<const ST*>(a.sdf);
   const FT* __restrict__ feat = static_cast<const FT*>(a.feat);
@@ -173,14 +174,26 @@ __global__ void __launch_bounds__(64) model_fwd_kernel(RenderArgs a, int64_t per
     wave_sync();
     float t[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     int j = -1;
+    ModelShade<NSH> S;
     if (lane < nb) {
       j = Q.rs[lane];
       const double x[3] = {Q.x[lane][0], Q.x[lane][1], Q.x[lane][2]};
       const float v[3] = {Q.v[j][0], Q.v[j][1], Q.v[j][2]};
-      ModelShade<NSH> S;
       model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
-      float pre[L * H], out[3];
-      mlp_fwd(S.z, pre, out);
+    } else {
+#pragma unroll
+      for (int q = 0; q < MNIN; ++q) S.z[q] = 0.f;
+    }
+    float out[3] = {0.f, 0.f, 0.f};
+    if constexpr (M == MLP_F32) {
+      if (lane < nb) {
+        float pre[L * H];
+        mlp_fwd(S.z, pre, out);
+      }
+    } else {
+      model_mlp_wave<M, H, L>(Wr, nin, MM, lane, S.z, out);
+    }
+    if (lane < nb) {
       const float w = Q.w[lane];
 #pragma unroll
       for (int c = 0; c < 3; ++c) t[c] = w * sigmoidf(out[c]);
@@ -316,6 +329,7 @@ struct ModelBwdLds {
 template <typename ST, typename FT, int NSH, int M, int H, int L>
 __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per_wave) {
   __shared__ ModelBwdLds<NSH> S_;
+  __shared__ ModelMfmaLds<M> MM;  // the colour pass's reduced-precision MLP on MFMA
   ModelBwdLds<NSH>& Ls = S_;
   ModelEntries& E = Ls.E;
   const int lane = threadIdx.x;
@@ -349,15 +363,27 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
     // colours of the listed samples
     for (int b0 = 0; b0 < n; b0 += 64) {
       const int e = b0 + lane;
+      ModelShade<NSH> S;
       if (e < n) {
         const int j = Ls.rs[e];
         double x[3];
         sample_pos(Ls.ray[j], sample_t(Ls.ray[j], E.i[e]), x);
         const float v[3] = {Ls.v[j][0], Ls.v[j][1], Ls.v[j][2]};
-        ModelShade<NSH> S;
         model_inputs<ST, FT, NSH>(sdf, feat, probes, G, tl, x, v, S);
-        float pre[L * H], out[3];
-        mlp_fwd(S.z, pre, out);
+      } else {
+#pragma unroll
+        for (int q = 0; q < MNIN; ++q) S.z[q] = 0.f;
+      }
+      float out[3] = {0.f, 0.f, 0.f};
+      if constexpr (M == MLP_F32) {
+        if (e < n) {
+          float pre[L * H];
+          mlp_fwd(S.z, pre, out);
+        }
+      } else {
+        model_mlp_wave<M, H, L>(Wr, nin, MM, lane, S.z, out);
+      }
+      if (e < n) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) Ls.C[e][c] = sigmoidf(out[c]);
       }
