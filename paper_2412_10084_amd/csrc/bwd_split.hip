@@ -812,12 +812,19 @@ __global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs
 // taped schedule: the per-ray walk that runs before the shading pass (the
 // colours come from the forward)
 // ---------------------------------------------------------------------------
+// The walk reads bytes [32, 96) of each entry (weight, T, s_i, s_{i+1}, ray, key, wave,
+// previous chunk, colour): a chunk's spans are staged in LDS with 16-byte loads, 16 lanes
+// per 4 entries, instead of one 4-byte load per field and lane at the entry's stride.
+constexpr int kSpanB = 32, kSpanDw = 16, kSpanRow = kSpanDw + 1;  // odd row: no bank conflicts
+#define PSDF_SPAN_DW(f) ((int)(offsetof(BwdEntry, f) - kSpanB) / 4)
+static_assert(offsetof(BwdEntry, w) >= kSpanB && offsetof(BwdEntry, C) + 12 <= kSpanB + 4 * kSpanDw &&
+                  offsetof(BwdEntry, key) >= kSpanB && offsetof(BwdEntry, prev) >= kSpanB &&
+                  offsetof(BwdEntry, T) >= kSpanB,
+              "the walk's fields lie in the staged span");
+
 struct WalkLds {
   RayD ray[64];
-  int si[64];
-  float w[64];
-  float T[64];
-  float C[64][3];
+  unsigned span[64][kSpanRow];
   float gdl[64];
   int nin[64];
   unsigned long long mine[64];  // entries of the chunk owned by each lane's ray
@@ -850,21 +857,33 @@ __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws
   int base = ws.last[lw];
   int n = cnt - 64 * ((cnt - 1) / 64);
   while (base >= 0) {  // wave-uniform
-    wave_sync();
-    L.mine[lane] = 0ull;
+    {
+      const char* __restrict__ src = reinterpret_cast<const char*>(ws.entries + base) + kSpanB;
+      uint4 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = q * 64 + lane, e = c >> 2, part = c & 3;
+        v[q] = e < n ? *reinterpret_cast<const uint4*>(src + (int64_t)e * sizeof(BwdEntry) + 16 * part)
+                     : make_uint4(0u, 0u, 0u, 0u);
+      }
+      wave_sync();  // the previous chunk's walk is done with the stage
+      L.mine[lane] = 0ull;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = q * 64 + lane, e = c >> 2, part = c & 3;
+        unsigned* d = &L.span[e][4 * part];
+        d[0] = v[q].x;
+        d[1] = v[q].y;
+        d[2] = v[q].z;
+        d[3] = v[q].w;
+      }
+    }
     wave_sync();
     int key = 0, prev = -1;
     if (lane < n) {
-      const BwdEntry& E = ws.entries[base + lane];
-      key = E.key;
-      prev = E.prev;
+      key = (int)L.span[lane][PSDF_SPAN_DW(key)];
+      prev = (int)L.span[lane][PSDF_SPAN_DW(prev)];
       atomicOr(&L.mine[key & 63], 1ull << lane);
-      L.si[lane] = key >> 6;
-      L.w[lane] = E.w;
-      L.T[lane] = E.T;
-      L.C[lane][0] = E.C[0];
-      L.C[lane][1] = E.C[1];
-      L.C[lane][2] = E.C[2];
     }
     wave_sync();
     // each lane walks its own ray's entries of the chunk, last sample first (a
@@ -873,13 +892,16 @@ __global__ void __launch_bounds__(BLOCK) tape_walk_kernel(RenderArgs a, BwdWs ws
       const int k = 63 - __clzll(m);
       m &= ~(1ull << k);
       {
-        const float w = L.w[k], T = L.T[k];
-        const float c0 = L.C[k][0], c1 = L.C[k][1], c2 = L.C[k][2];
+        const unsigned* sp = L.span[k];
+        const float w = __uint_as_float(sp[PSDF_SPAN_DW(w)]), T = __uint_as_float(sp[PSDF_SPAN_DW(T)]);
+        const float c0 = __uint_as_float(sp[PSDF_SPAN_DW(C)]);
+        const float c1 = __uint_as_float(sp[PSDF_SPAN_DW(C) + 1]);
+        const float c2 = __uint_as_float(sp[PSDF_SPAN_DW(C) + 2]);
         Rc[0] = fmaf(w, c0, Rc[0]);
         Rc[1] = fmaf(w, c1, Rc[1]);
         Rc[2] = fmaf(w, c2, Rc[2]);
         const float g = dL[0] * (Rc[0] - T * c0) + dL[1] * (Rc[1] - T * c1) + dL[2] * (Rc[2] - T * c2);
-        const int si = L.si[k];
+        const int si = (int)sp[PSDF_SPAN_DW(key)] >> 6;
         const bool nin = nx_i == si + 1;
         if (nin) ws.entries[nx_slot].gdl_prev = g;
         L.gdl[k] = g;
