@@ -621,6 +621,18 @@ def cpu_baseline(wl, w, field, rays, n_rays=16384):
                         f"({t_step1:.2f} s) on one thread")), shaded
 
 
+def copy_bandwidth(torch) -> dict:
+    """Rate of a plain 1 GiB device-to-device copy (torch's copy kernel), read + write
+    bytes over its event-timed duration: what a streaming kernel reaches on this part,
+    beside the published peak the rooflines use."""
+    x = torch.empty(1 << 28, device="cuda")
+    y = torch.empty_like(x)
+    ms = ev_time(torch, lambda: y.copy_(x), 5)
+    byts = 2 * x.numel() * 4
+    del x, y
+    return {"bytes": byts, "ms": ms, "GBps": byts / (ms * 1e-3) / 1e9}
+
+
 def calib_copy(torch) -> int:
     """Three 1 GiB device copies: what FETCH_SIZE / WRITE_SIZE read for known bytes."""
     x = torch.empty(1 << 28, device="cuda")
@@ -640,6 +652,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--order", choices=("image", "tile8", "shuffled"), default="image",
+                    help="ray order of the timed train256 step (image order by default)")
     ap.add_argument("--only", choices=("mixed512", "iter512", "trace512", "paper", "tiled",
                                        "regs", "realtime"),
                     help="run one secondary workload alone (for profiling) and print its JSON")
@@ -671,7 +685,7 @@ def main():
         return
     w = wl.WORKLOADS["train256"]
     log(f"setting up {w.name}: R={w.R} P={w.P} B={w.rays} N={w.n_samples}")
-    st, field, rays = make_state(torch, ps, wl, w)
+    st, field, rays = make_state(torch, ps, wl, w, order=args.order)
     ms, kern = time_training(torch, ps, w, st, args.steps, args.warmup, "fp32")
     B = st["B"]
     value = B / (ms * 1e-3)
@@ -686,7 +700,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "train256", "R": w.R, "P": w.P, "sh_coeffs": w.n_sh,
-                   "rays": B, "samples": w.n_samples, "skip_voxels": w.skip_voxels,
+                   "rays": B, "samples": w.n_samples, "skip_voxels": w.skip_voxels, "ray_order": args.order,
                    "step": "render_forward + l1_loss + render_backward + grid_step"},
         "kernels_ms": kern,
         "fwd_bwd_rays_per_s": B / ((kern["render_forward"] + kern["render_backward"]) * 1e-3),
@@ -715,6 +729,8 @@ def main():
         per_launch = B * alg_bytes_per_ray(dom, w.n_samples, shaded, False)
     if per_launch is not None:
         result["roofline"] = roofline_obj(dom, per_launch, kern[dom], measured_traffic(dom))
+    result["copy_bandwidth"] = copy_bandwidth(torch)
+    torch.cuda.empty_cache()
 
     if not args.no_extras:
         log("mixed precision (fp16 storage, fp16 MFMA MLP) ...")
