@@ -352,6 +352,39 @@ def alg_bytes_per_ray(entry: str, N: int, A: float, half: bool) -> float:
     return 32.0 * N + A * (per + 32.0 + 1376.0) + 52.0
 
 
+def alg_bytes_model(entry: str, N: int, A: float, half: bool, n_sh: int, tiled: bool) -> float:
+    """Algorithmic bytes per ray of the paper colour model's kernels (and of tiled
+    fields, which run on them): the SDF scan, and per shaded sample the FD stencil (96 B),
+    the spatial features (8 corners x 3, or 12 tri-plane texels x 3, in the storage
+    precision) and 8 probe corners x n_sh x 4 coefficients; the backward also writes
+    the same footprint of FP32 gradients plus the 32 B of the sample's own cell."""
+    fb = 2.0 if half else 4.0
+    feat = (12 if tiled else 8) * 3
+    shade = 96.0 + feat * fb + 8 * n_sh * 4 * fb
+    if entry == "render_forward":
+        return 32.0 * N + A * shade + 64.0
+    return 32.0 * N + A * (shade + 32.0 + 96.0 + feat * 4.0 + 8 * n_sh * 16.0) + 52.0
+
+
+def shaded_per_ray(torch, ps, w, sdf, P, o, d) -> float:
+    """Shaded samples per ray (active, alpha > 0) of an SDF: they depend on the SDF and
+    the rays only, so the workload model's taped forward over zero features counts them."""
+    R = sdf.shape[0]
+    fld = ps.Field(sdf, torch.zeros((R, R, R, 3), device="cuda", dtype=torch.float32),
+                   torch.zeros((P, P, P, w.n_sh, 4), device="cuda"),
+                   torch.zeros(227, device="cuda"), 0, ps.sdf_bounds(sdf))
+    B = o.shape[0]
+    ws = ps.backward_workspace(B, P, ws_samples(w, B))
+    rgb, aux = torch.empty((B, 3), device="cuda"), torch.empty((B, 4), device="cuda")
+    ps.render_forward(fld, ps.RenderOpts(w.n_samples, w.tau, w.skip_voxels), o, d, rgb, aux,
+                      tape=ws)
+    torch.cuda.synchronize()
+    A = recorded_samples(torch, ws) / B
+    del fld, ws
+    torch.cuda.empty_cache()
+    return A
+
+
 def roofline_obj(kernel: str, per_launch: float, ms: float, traffic):
     ach = per_launch / (ms * 1e-3) / 1e9
     return {"kernel": kernel, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
@@ -408,6 +441,9 @@ def time_paper_model(torch, ps, wl, reps):
     rgb, aux = torch.empty((B, 3), device="cuda"), torch.empty((B, 4), device="cuda")
     tgt, dL = torch.full((B, 3), 0.5, device="cuda"), torch.empty((B, 3), device="cuda")
     out = {}
+    base = gpu_field(torch, ps, wl, w, 0)
+    A = shaded_per_ray(torch, ps, w, base.sdf, w.P, do, dd)
+    del base
     for label, half, mdt in (("fp32", False, 0), ("fp16", True, 1)):
         fld = paper_field(torch, ps, wl, w, 0, half, mdt)
         grads = {k: torch.zeros(getattr(fld, k).shape, device="cuda") for k in
@@ -415,10 +451,16 @@ def time_paper_model(torch, ps, wl, reps):
         tf = ev_time(torch, lambda: ps.render_forward(fld, opts, do, dd, rgb, aux), reps)
         ps.l1_loss(rgb, tgt, dL)
         tb = ev_time(torch, lambda: ps.render_backward(fld, opts, do, dd, aux, dL, grads), reps)
-        out[label] = {"fwd_ms": tf, "bwd_ms": tb, "fwd_bwd_rays_per_s": B / ((tf + tb) * 1e-3)}
+        roof = {}
+        for e, ms in (("render_forward", tf), ("render_backward", tb)):
+            per = B * alg_bytes_model(e, w.n_samples, A, half, 16, False)
+            roof[e] = roofline_obj(e, per, ms, measured_traffic(e + "_model", "paper", label))
+        out[label] = {"fwd_ms": tf, "bwd_ms": tb, "fwd_bwd_rays_per_s": B / ((tf + tb) * 1e-3),
+                      "roofline": roof}
         log(f"paper model {label}: fwd {tf:.3f} ms, bwd {tb:.3f} ms")
         del fld, grads
     out["ratio_fp16_vs_fp32"] = out["fp16"]["fwd_bwd_rays_per_s"] / out["fp32"]["fwd_bwd_rays_per_s"]
+    out["shaded_samples_per_ray"] = A
     out["config"] = {"R": w.R, "P": w.P, "sh_coeffs": 16, "mlp": "13-32-32-3", "rays": B,
                      "samples": w.n_samples, "skip_voxels": w.skip_voxels,
                      "flags": "SH_REFLECT | FRESNEL_PAPER"}
@@ -450,8 +492,15 @@ def time_tiled(torch, ps, wl, reps):
     ts = ev_time(torch, lambda: ps.plane_step(pl, po, grads["feat"], m, v, 1), reps)
     n_tiles = int(f.tiles.planes.shape[0])
     log(f"tiled: fwd {tf:.3f} ms, bwd {tb:.3f} ms, plane step {ts:.3f} ms ({n_tiles} tiles)")
+    del grads, po, m, v
+    A = shaded_per_ray(torch, ps, w, fld.sdf, f.P, do, dd)
+    roof = {}
+    for e, ms in (("render_forward", tf), ("render_backward", tb)):
+        per = B * alg_bytes_model(e, w.n_samples, A, False, f.n_sh, True)
+        roof[e] = roofline_obj(e, per, ms, measured_traffic(e + "_model", "tiled"))
     return {"fwd_ms": tf, "bwd_ms": tb, "plane_step_ms": ts,
-            "fwd_bwd_rays_per_s": B / ((tf + tb) * 1e-3),
+            "fwd_bwd_rays_per_s": B / ((tf + tb) * 1e-3), "shaded_samples_per_ray": A,
+            "roofline": roof,
             "config": {"T": 16, "R": f.R, "P": f.P, "tiles": n_tiles,
                        "tile_fraction": n_tiles / 16 ** 3, "rays": B, "samples": w.n_samples,
                        "skip_voxels": w.skip_voxels,
@@ -505,9 +554,27 @@ def time_realtime(torch, ps, wl, reps):
     t_render = ev_time(torch, lambda: ps.volume_render(fld, opts, col, cam, w.W, w.H, out), reps)
     log(f"real-time: list {t_list:.3f} ms ({n} voxels), shading {t_shade:.3f} ms, "
         f"render {t_render:.3f} ms")
+    del lst, col, out
+    torch.cuda.empty_cache()
+    # algorithmic bytes: the band list reads the FP16 SDF and writes the indices; a band
+    # node's shading reads its index, its own and six neighbouring SDF nodes, its features
+    # and 8 probe corners (FP16) and writes one FP16 colour; a pixel reads 8 FP16 SDF
+    # corners per sample and 8 FP16 colour corners per shaded sample
+    o, d = wl.camera_rays(wl.fibonacci_cameras(1, w.W, w.H), w.W, w.H)
+    A = shaded_per_ray(torch, ps, w, fld.sdf, w.P, torch.from_numpy(o).cuda(),
+                       torch.from_numpy(d).cuda())
+    node = 4 + 7 * 2 + 3 * 2 + 8 * w.n_sh * 4 * 2 + 8
+    roof = {"voxel_list": roofline_obj("voxel_list", w.R ** 3 * 2.0 + n * 4.0, t_list,
+                                       measured_traffic("voxel_list", "realtime")),
+            "voxel_shade": roofline_obj("voxel_shade", n * float(node), t_shade,
+                                        measured_traffic("voxel_shade", "realtime")),
+            "volume_render": roofline_obj("volume_render",
+                                          w.W * w.H * (16.0 * w.n_samples + A * 64.0 + 12.0),
+                                          t_render, measured_traffic("volume_render", "realtime"))}
     return {"workload": "rt512", "voxel_list_ms": t_list, "voxel_shade_ms": t_shade,
             "volume_render_ms": t_render, "ms_per_frame": t_shade + t_render,
             "shaded_voxels": n, "render_rays_per_s": w.W * w.H / (t_render * 1e-3),
+            "shaded_samples_per_pixel": A, "roofline": roof,
             "config": {"R": w.R, "P": w.P, "W": w.W, "H": w.H, "band_voxels": wl.RT_BAND_VOXELS,
                        "samples": w.n_samples, "skip_voxels": w.skip_voxels,
                        "grids": "fp16", "colour_grid": "fp16"}}
@@ -533,6 +600,12 @@ TRAFFIC_KERNELS = {
     "render_forward": ("may_box_kernel", "render_fwd_kernel"),
     "grid_step": ("zero3_kernel", "bounds_init_kernel", "step_sdf_tiled_kernel",
                   "bounds_decode_kernel", "step_tv3v_kernel", "step_tv4_kernel", "step_mlp_kernel"),
+    # the paper colour model's and the tiled fields' kernels
+    "render_forward_model": ("model_fwd_kernel",),
+    "render_backward_model": ("model_bwd_kernel",),
+    "voxel_list": ("zero_count_kernel", "voxel_list_kernel"),
+    "voxel_shade": ("voxel_shade_kernel",),
+    "volume_render": ("volume_render_kernel",),
 }
 
 

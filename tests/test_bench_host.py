@@ -47,5 +47,12 @@ def test_alg_bytes_and_kernel_names():
     assert bench.kernel_base_name("_ZN4psdf17render_fwd_kernelIfDF16_Li9ELi1EEEvNS_10RenderArgsENS_5BwdWsEi") \
         == "render_fwd_kernel"
     assert bench.kernel_base_name("void at::native::(anonymous namespace)::distribution_kernel<float>(int)") == ""
+    # paper model: 16 SH, FP32; dense and tiled features; FP16 halves features and probes
+    assert bench.alg_bytes_model("render_forward", 128, 1.0, False, 16, False) == \
+        32 * 128 + (96 + 96 + 2048) + 64
+    assert bench.alg_bytes_model("render_forward", 64, 2.0, True, 9, True) == \
+        32 * 64 + 2 * (96 + 72 + 576) + 64
+    assert bench.alg_bytes_model("render_backward", 128, 1.0, False, 16, False) == \
+        32 * 128 + (96 + 96 + 2048) + 32 + (96 + 96 + 2048) + 52
     r = bench.roofline_obj("render_forward", 8e9, 1.0, None)
     assert abs(r["frac"] - 1.0) < 1e-12 and r["achieved"] == 8000.0
