@@ -332,6 +332,62 @@ __device__ __forceinline__ void model_round_mlp(const float* __restrict__ W, flo
   }
 }
 
+// Probe gradients of a batch of samples (one per lane): dL/db_{node,j,k} = w_c Y_j dL/dF_a,k
+// over the 8 corners c of each sample's probe cell.  The samples' corner weights, SH values
+// and dL/dF_a are staged in LDS; then, for each distinct cell of the batch, lane q
+// (coefficient j = q / 4, k = q % 4) sums its coefficient over the cell's samples in lane
+// order for the 8 corners and adds them with one coalesced run of global atomics per
+// corner.  No LDS atomics: samples of one cell are common in a batch, and LDS atomics on a
+// shared slot serialise.
+template <int NSH>
+struct ProbeStage {
+  int key[64];
+  float w8[64][9];
+  float y[64][NSH + 1];
+  float dfa[64][NA + 1];
+};
+
+template <int NSH>
+__device__ __forceinline__ void probe_scatter_lanes(ProbeStage<NSH>& S, int lane, bool ve,
+                                                    const Cell& cp, int P, const float* Y,
+                                                    const float* dFa, float* g_probes) {
+  constexpr int NC = NSH * NA;  // coefficients of a probe node
+  static_assert(NC <= 64, "one lane per coefficient");
+  const int mykey = ve ? cp.base : -1;
+  float w[8];
+  corner_w(cp, w);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) S.w8[lane][c] = w[c];
+#pragma unroll
+  for (int j = 0; j < NSH; ++j) S.y[lane][j] = Y[j];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) S.dfa[lane][k] = dFa[k];
+  wave_sync();
+  const int jq = lane / NA, kq = lane - NA * jq;
+  uint64_t todo = __ballot(ve);
+  while (todo) {  // wave-uniform: one distinct cell per round
+    const int leader = __builtin_ctzll(todo);
+    const int key = __builtin_amdgcn_readlane(mykey, leader);
+    uint64_t mm = __ballot(ve && mykey == key);
+    todo &= ~mm;
+    if (lane < NC) {
+      float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      while (mm) {
+        const int sm = __builtin_ctzll(mm);
+        mm &= mm - 1;
+        const float yd = S.y[sm][jq] * S.dfa[sm][kq];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = fmaf(S.w8[sm][c], yd, acc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (acc[c] != 0.f)
+          atomic_add_f32(g_probes + (int64_t)(key + corner_off(c, P)) * NC + lane, acc[c]);
+    }
+  }
+  wave_sync();
+}
+
 // The MLP of a wave's 64 samples on MFMA (FP16 or BF16 operands, FP32 accumulation),
 // from the rounded copy `Wr` in LDS.  Samples lie on the N dimension, in four blocks
 // of 16: a layer's accumulator fragment (lane i + 16 g holds hidden units 4g .. 4g+3

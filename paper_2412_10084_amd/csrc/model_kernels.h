@@ -319,7 +319,7 @@ struct ModelBwdLds {
   float dL[MODEL_GROUP][3];
   union {
     DwLds dw;
-    ProbeAcc<NSH> pa;
+    ProbeStage<NSH> ps;
     float sc[64][65];
   } u;
   int k0[64][3];
@@ -512,12 +512,10 @@ __global__ void __launch_bounds__(64) model_bwd_kernel(RenderArgs a, int64_t per
                             a.g_feat);
         }
       }
-      if (!(G.flags & FLAG_NO_FA) && a.g_probes) {
-        probe_acc_clear<NSH>(Ls.u.pa, lane);
-        probe_scatter_wave<NSH>(Ls.u.pa, lane, ve,
-                                ve ? cell_d(x, G.P, G.inv_hp) : Cell{0, 0.f, 0.f, 0.f}, G.P, S.Y,
-                                dz + NF, a.g_probes);
-      }
+      if (!(G.flags & FLAG_NO_FA) && a.g_probes)
+        probe_scatter_lanes<NSH>(Ls.u.ps, lane, ve,
+                                 ve ? cell_d(x, G.P, G.inv_hp) : Cell{0, 0.f, 0.f, 0.f}, G.P,
+                                 S.Y, dz + NF, a.g_probes);
       wave_sync();
     }
   };
