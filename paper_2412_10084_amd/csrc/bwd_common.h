@@ -231,10 +231,12 @@ __device__ __forceinline__ void sdf_cross_add(float* q, int sy, int sz, const fl
 // SDF box pass over the lanes with `part` set: the opacity gradient at s_i
 // (coefficient a0, trilinear at x), the central-difference path (cotangent dg of
 // the FD gradient at x) and, where sample i+1 is not shaded itself, the opacity
-// gradient at s_{i+1} (coefficient a1, trilinear at x + off; with `direct1` it
-// is added to the grid directly instead, which a single lane's box always
-// allows).  Returns false, having done nothing, when the nodes do not fit in
-// `cap` floats (wave-uniform).
+// gradient at s_{i+1} (coefficient a1, trilinear at x + off).  The successor's 8
+// corners go into the box when the box of every lane's nodes fits in `cap`
+// floats; else the box holds the lanes' own 4x4x4 patches and a successor whose
+// corners lie outside it is added to the grid directly (with `direct1` every
+// successor is, which a single lane's box always allows).  Returns false, having
+// done nothing, when the patches alone do not fit (wave-uniform).
 __device__ __forceinline__ bool sdf_box_pass(float* box, int cap, int lane, bool part,
                                              const double x[3], const float dg[3], float a0,
                                              const float off[3], float a1, bool direct1,
@@ -248,18 +250,35 @@ __device__ __forceinline__ bool sdf_box_pass(float* box, int cap, int lane, bool
 #pragma unroll
     for (int a = 0; a < 3; ++a) axis_cell_d(x[a] + (double)off[a], G.inv_h, kmax, k1[a], f1[a]);
   }
-  const bool has1 = any1 && !direct1;
+  // the lanes' own patches: nodes k0-1 .. k0+2
   int lo[3], ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    // nodes k0-1 .. k0+2, and k1 .. k1+1 for the successor sample
-    const int l = !part ? 0x7FFFFFFF : has1 ? min(k0[a] - 1, k1[a]) : k0[a] - 1;
-    const int h = !part ? -0x7FFFFFFF : has1 ? max(k0[a] + 2, k1[a] + 1) : k0[a] + 2;
-    lo[a] = wave_min_i(l);
-    ext[a] = wave_max_i(h) - lo[a] + 1;
+    lo[a] = wave_min_i(part ? k0[a] - 1 : 0x7FFFFFFF);
+    ext[a] = wave_max_i(part ? k0[a] + 2 : -0x7FFFFFFF) - lo[a] + 1;
   }
   if ((int64_t)ext[0] * ext[1] * ext[2] > cap) return false;
-  if (any1 && direct1) {
+  bool has1 = any1 && !direct1;
+  if (wave_any(has1)) {
+    // with the successors' corners k1 .. k1+1, if that box fits
+    int los[3], exs[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      los[a] = min(lo[a], wave_min_i(has1 ? k1[a] : 0x7FFFFFFF));
+      exs[a] = max(lo[a] + ext[a] - 1, wave_max_i(has1 ? k1[a] + 1 : -0x7FFFFFFF)) - los[a] + 1;
+    }
+    if ((int64_t)exs[0] * exs[1] * exs[2] <= cap) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = los[a];
+        ext[a] = exs[a];
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) has1 = has1 && k1[a] >= lo[a] && k1[a] + 1 < lo[a] + ext[a];
+    }
+  }
+  if (any1 && !has1) {
     const Cell c1{(k1[2] * G.R + k1[1]) * G.R + k1[0], f1[0], f1[1], f1[2]};
     scatter8(g_sdf, G.R, c1, a1);
   }

@@ -182,6 +182,22 @@ def test_tape_backward_no_skip_and_partial_groups():
     assert not g["sdf"].any()
 
 
+@pytest.mark.parametrize("skip", [0.0, 4.0])
+def test_tape_backward_far_successors(skip):
+    """Samples about ten cells apart (R = 96, N = 16) with a dense loss gradient: in a
+    batch of one block of probe cells, the next-sample corners of the batch's last
+    shaded samples no longer fit the LDS box with the samples' own patches, so the
+    box holds the patches and those corners go to the grid directly."""
+    N = 16
+    f, o, d, dL, g_ref = _case(N, skip, B=4096, R=96, P=24)
+    assert np.count_nonzero(dL.any(axis=1)) > 1000
+    fld, fw, g = _tape_run(f, o, d, dL, N, skip, 1 << 18)
+    _check(g, g_ref)
+    do, dd, _, aux = fw["dev"]
+    g_fused = gpu_backward(fld, do, dd, aux, dL, N, skip=skip)
+    grad_check(g, g_fused, "fp32")
+
+
 @pytest.mark.parametrize("mlp_dt,gtol", [(1, F16_GRAD_REL), (2, BF16_GRAD_REL)])
 def test_tape_backward_mixed(mlp_dt, gtol):
     f = scene(0, 64, 16)
