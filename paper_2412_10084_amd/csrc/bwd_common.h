@@ -129,35 +129,37 @@ __device__ __forceinline__ void box_flush(const float* box, float inv, int ex, i
   int iz = r / ey, iy = r - iz * ey;
   const int dz = rows_per / ey, dy = rows_per - dz * ey;
   if (row_len <= 64) {
-    // one element per lane and step; four steps at a time, their LDS reads first
+    // one element per lane and step, four steps at a time: the four LDS reads are
+    // issued unconditionally (indices inside the box), then the atomics
     const int nstep = (nrows + rows_per - 1) / rows_per;
     const int gx = ox + x0 / C;
     const bool x_in = x0 < row_len && gx >= 0 && gx < R;
+    const int64_t rstride = (int64_t)R * C;  // elements per grid row
+    const int64_t xoff = (int64_t)ox * C + x0;
     for (int s0 = 0; s0 < nstep; s0 += 4) {
-      float v[4];
-      float* dst[4];
+      int ru[4], gy[4], gz[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int ru = r + u * rows_per;
-        int uy = iy + u * dy, uz = iz + u * dz;
-        while (uy >= ey) {
-          uy -= ey;
-          ++uz;
+        ru[u] = r;
+        gy[u] = oy + iy;
+        gz[u] = oz + iz;
+        r += rows_per;
+        iy += dy;  // dy < ey: one wrap at most
+        iz += dz;
+        if (iy >= ey) {
+          iy -= ey;
+          ++iz;
         }
-        const int gy = oy + uy, gz = oz + uz;
-        const bool in = x_in && ru < nrows && gy >= 0 && gy < R && gz >= 0 && gz < R;
-        v[u] = in ? value(ru * row_len + x0) : 0.f;
-        dst[u] = g + ((int64_t)(gz * R + gy) * R + ox) * C + x0;
       }
+      float v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (v[u] != 0.f) atomic_add_f32(dst[u], v[u]);
-      r += 4 * rows_per;
-      iy += 4 * dy;
-      iz += 4 * dz;
-      while (iy >= ey) {
-        iy -= ey;
-        ++iz;
+      for (int u = 0; u < 4; ++u) v[u] = value(x_in && ru[u] < nrows ? ru[u] * row_len + x0 : 0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool in = x_in && ru[u] < nrows && (unsigned)gy[u] < (unsigned)R &&
+                        (unsigned)gz[u] < (unsigned)R;
+        if (in && v[u] != 0.f)
+          atomic_add_f32(g + ((int64_t)gz[u] * R + gy[u]) * rstride + xoff, v[u]);
       }
     }
     return;

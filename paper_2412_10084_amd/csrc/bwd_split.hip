@@ -774,7 +774,7 @@ __global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs
     for (int r0 = end - cnt; r0 < end; r0 += 64) {
       // one record per lane: its SH x dL/dF_a products go to LDS (row of the
       // record), its 8 corner weights stay in registers
-      const int m = min(64, end - r0);
+      const int m = __builtin_amdgcn_readfirstlane(min(64, end - r0));
       float wl[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) wl[c] = 0.f;
@@ -791,8 +791,18 @@ __global__ void __launch_bounds__(BLOCK) probe_reduce_kernel(RenderArgs a, BwdWs
       }
       wave_sync();
       // coefficient lanes sum the records: one LDS read and the record's weights
-      // (broadcast from its lane) per record
-      for (int t = 0; t < m; ++t) {
+      // (broadcast from its lane) per record, eight records' reads in flight
+      int t = 0;
+      for (; t + 8 <= m; t += 8) {
+        float g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) g[u] = P[(t + u) * PS + q];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int c = 0; c < 8; ++c) acc[c] = fmaf(rdlane(wl[c], t + u), g[u], acc[c]);
+      }
+      for (; t < m; ++t) {
         const float g = P[t * PS + q];
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc[c] = fmaf(rdlane(wl[c], t), g, acc[c]);
