@@ -519,13 +519,19 @@ __global__ void __launch_bounds__(BLOCK, 2) bwd_shade_kernel(RenderArgs a, BwdWs
 constexpr int kEntDw = 42;  // LDS row of an entry: 40 dwords + 2 (8-byte rows, 2-way banks)
 static_assert(sizeof(BwdEntry) == 40 * 4, "an entry is 40 dwords (10 x 16 bytes)");
 
+// A wave's staged entries and its MLP-gradient tiles share LDS: the fields the records
+// need are read into registers before the tiles are written (three blocks per CU).
+union ShadeStage {
+  unsigned e[64 * kEntDw];
+  DwLds dw;
+};
+
 template <int M>
-__global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdWs ws) {
-  __shared__ DwLds dlds[WAVES];
-  __shared__ __align__(16) unsigned estage[WAVES][64 * kEntDw];
+__global__ void __launch_bounds__(BLOCK, 3) tape_shade_kernel(RenderArgs a, BwdWs ws) {
+  __shared__ __align__(16) ShadeStage sst[WAVES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  DwLds& D = dlds[wv];
-  unsigned* const stage = estage[wv];
+  DwLds& D = sst[wv].dw;
+  unsigned* const stage = sst[wv].e;
   // the MLP read through scalar loads; reduced modes use the copy whose weights
   // are already rounded (no per-use conversions to keep in registers)
   cfloat* __restrict__ W = const_mlp(M == MLP_F32 ? a.mlp : ws.mlp_r);
@@ -602,12 +608,18 @@ __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdW
     }
     float dpre[HID], dz[NIN];
     mlp_backward_lane<M, true>(W, dout, pre, ve, dpre, dz);
+    // the entry's remaining fields, before the MLP-gradient tiles overwrite the stage
+    const double x[3] = {E.x[0], E.x[1], E.x[2]};
+    const float ev[3] = {E.v[0], E.v[1], E.v[2]};
+    const float en[3] = {E.nrm[0], E.nrm[1], E.nrm[2]};
+    const float egn = E.gn, es0 = E.s0, es1 = E.s1, egdl = E.gdl, egdl_prev = E.gdl_prev;
+    const float eoff[3] = {E.nx_off[0], E.nx_off[1], E.nx_off[2]};
+    wave_sync();
     if (a.g_mlp) mlp_dw_wave<M>(D, lane, ve, z, hid, dpre, dout, acc_w1, acc_w2, db2);
     wave_sync();
     const int gb = __shfl(gbase, my_leader, 64);
     if (counted) {
       const int slot = gb + lane_rank(my_grp);
-      const double x[3] = {E.x[0], E.x[1], E.x[2]};
       // SDF and feature cotangents for the box pass: the normal path and the
       // opacity path at s_i, where this sample's alpha and the previous sample's
       // meet (the rest of the opacity path is scattered by the per-ray walk)
@@ -617,26 +629,25 @@ __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdW
       r.x[2] = x[2];
       r.dg[0] = r.dg[1] = r.dg[2] = 0.f;
       if (ve && !(G.flags & FLAG_NV_ONE)) {
-        const float v[3] = {E.v[0], E.v[1], E.v[2]};
         Normal nm;
-        nm.n[0] = E.nrm[0];
-        nm.n[1] = E.nrm[1];
-        nm.n[2] = E.nrm[2];
-        nm.gn = E.gn;
+        nm.n[0] = en[0];
+        nm.n[1] = en[1];
+        nm.n[2] = en[2];
+        nm.gn = egn;
         nm.c = z[7];
-        normal_dg(v, nm, dz, r.dg);
+        normal_dg(ev, nm, dz, r.dg);
       }
-      r.a0 = ve ? a.tau * sigmoidf(-a.tau * E.s0) * (E.gdl_prev - E.gdl) : 0.f;
+      r.a0 = ve ? a.tau * sigmoidf(-a.tau * es0) * (egdl_prev - egdl) : 0.f;
       const bool fs = ve && !(G.flags & FLAG_NO_FS);
       r.df[0] = fs ? dz[0] : 0.f;
       r.df[1] = fs ? dz[1] : 0.f;
       r.df[2] = fs ? dz[2] : 0.f;
       r.valid = ve ? 1 : 0;
-      r.off[0] = E.nx_off[0];
-      r.off[1] = E.nx_off[1];
-      r.off[2] = E.nx_off[2];
+      r.off[0] = eoff[0];
+      r.off[1] = eoff[1];
+      r.off[2] = eoff[2];
       const bool nx = r.off[0] != 0.f || r.off[1] != 0.f || r.off[2] != 0.f;
-      r.a1 = ve && nx ? a.tau * sigmoidf(-a.tau * E.s1) * E.gdl : 0.f;
+      r.a1 = ve && nx ? a.tau * sigmoidf(-a.tau * es1) * egdl : 0.f;
       r.pad[0] = r.pad[1] = 0.f;
       ws.srecs[slot] = r;
       if (ws.probe_bins) {
@@ -646,9 +657,9 @@ __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdW
         pr.f[0] = cp.fx;
         pr.f[1] = cp.fy;
         pr.f[2] = cp.fz;
-        pr.v[0] = E.v[0];
-        pr.v[1] = E.v[1];
-        pr.v[2] = E.v[2];
+        pr.v[0] = ev[0];
+        pr.v[1] = ev[1];
+        pr.v[2] = ev[2];
         pr.dfa[0] = ve ? dz[3] : 0.f;
         pr.dfa[1] = ve ? dz[4] : 0.f;
         pr.dfa[2] = ve ? dz[5] : 0.f;
@@ -667,7 +678,7 @@ __global__ void __launch_bounds__(BLOCK, 2) tape_shade_kernel(RenderArgs a, BwdW
     __syncthreads();
     const int t = threadIdx.x;
     if (t < NMLP) {
-      const float s = (dlds[0].st[0][t] + dlds[1].st[0][t]) + (dlds[2].st[0][t] + dlds[3].st[0][t]);
+      const float s = (sst[0].dw.st[0][t] + sst[1].dw.st[0][t]) + (sst[2].dw.st[0][t] + sst[3].dw.st[0][t]);
       ws.mlp_part[(int64_t)blockIdx.x * NMLP + t] = s;
     }
   }
@@ -1060,9 +1071,11 @@ hipError_t launch_render_backward_split(const RenderArgs& a, const BwdWs& ws_in,
     hipLaunchKernelGGL(scan_offsets_kernel, dim3((unsigned)ws.nsum), dim3(256), 0, s, ws);
   }
   if (from_tape && a.g_sdf) hipLaunchKernelGGL(tape_walk_kernel, wgrid, dim3(BLOCK), 0, s, a, ws);
-  // enough waves to fill the chip; each loops over batches of 64 entries
+  // enough waves to fill the chip; each loops over batches of 64 entries.  The taped
+  // shading pass runs three blocks per CU (its LDS allows three): 768 blocks are all
+  // resident at once, with no second round of blocks behind the first
   const int64_t want = (ws.cap + 64 * WAVES - 1) / (64 * WAVES);
-  const dim3 sgrid((unsigned)max((int64_t)1, min(want, (int64_t)1024)));
+  const dim3 sgrid((unsigned)max((int64_t)1, min(want, (int64_t)(from_tape ? 3 * 256 : 1024))));
   if (from_tape) {
     if (mlp_dt != 0)
       PSDF_MLP_SWITCH(mlp_dt, hipLaunchKernelGGL((mlp_round_kernel<M>), dim3(1), dim3(256), 0, s,
